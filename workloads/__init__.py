@@ -1,0 +1,176 @@
+"""Seeded synthetic workloads for the FPD fiber solver (arXiv:2212.14153, Sec. IV).
+
+This module only states *inputs*: lattice sizes, physical groups turned into lattice
+units, straight initial fibers, and seeded random perturbations.  It holds none of the
+method's arithmetic (no equilibria, no collision, no forces), so both the GPU library
+and the CPU oracle can be fed from it.
+
+The paper runs its own simulations and uses no public dataset.  The configurations
+below re-create its workloads synthetically: a straight fiber of N beads centred in a
+confined Couette channel (Sec. IV.A), with the dimensionless groups of Eq. (18)
+mapped to lattice units:
+
+    shear rate        gamma = 2 U / H                      (Fig. 1 caption)
+    Reynolds number   Re_ps = gamma l_c^2 / (4 nu_f)       (Eq. 18, rho = 1)
+    stiffness         K     = 2 k_b / (eta_f gamma l_c^2)  (Eq. 18)
+    confinement       C     = l_c / H                      (Eq. 18)
+
+The stretching constant is not taken from the paper's K_s = 3.33e6, which is unstable
+for explicit coupling in lattice units; k_s / l_0^2 = 0.1 * pi * a^2 is used instead.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, asdict, replace
+
+import numpy as np
+
+S_E_DEFAULT = 1.64
+S_EPS_DEFAULT = 1.54
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One simulation in lattice units plus its initial fiber."""
+    name: str
+    nx: int
+    ny: int
+    u_wall: float
+    nu_f: float
+    eta_ratio: float
+    xi: float
+    n_beads: int
+    radius: float
+    l0: float
+    k_s: float
+    k_b: float
+    theta0: float            # initial fiber angle in radians
+    cx: float                # fiber centroid
+    cy: float
+    steps: int
+    storage: str = "f64"     # "f64" | "f32" | "f16dev" | "bf16dev"
+    init_flow: int = 1       # 0 rest, 1 linear Couette
+    s_e: float = S_E_DEFAULT
+    s_eps: float = S_EPS_DEFAULT
+    s_q_fixed: float = 0.0
+    kappa: float = float("nan")
+    re_ps: float = float("nan")
+    confinement: float = float("nan")
+
+    def params(self) -> dict:
+        """Lattice parameters as a plain mapping (both sides read what they need)."""
+        return {k: v for k, v in asdict(self).items()}
+
+    def beads(self) -> np.ndarray:
+        return straight_fiber(self.n_beads, self.l0, self.theta0, self.cx, self.cy)
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+    @property
+    def sites(self) -> int:
+        return self.nx * self.ny
+
+
+def straight_fiber(n: int, l0: float, theta: float, cx: float, cy: float) -> np.ndarray:
+    """R_i = c + (i - (N+1)/2) l0 (cos theta, sin theta), i = 1..N."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    s = (i - (n + 1) / 2.0) * l0
+    return np.stack([cx + s * math.cos(theta), cy + s * math.sin(theta)], axis=1)
+
+
+def stretch_constant(radius: float, l0: float) -> float:
+    """k_s with k_s / l0^2 = 0.1 * pi * a^2 (stable explicit coupling)."""
+    return 0.1 * math.pi * radius * radius * l0 * l0
+
+
+def physical_to_lattice(*, nx: int, ny: int, n_beads: int, radius: float, l0: float,
+                        u_wall: float, re_ps: float, kappa: float) -> dict:
+    """nu_f and k_b from Re_ps and K of Eq. (18) (rho = 1, l_c = N l0)."""
+    lc = n_beads * l0
+    gamma = 2.0 * u_wall / ny
+    nu_f = gamma * lc * lc / (4.0 * re_ps)
+    k_b = kappa * nu_f * gamma * lc * lc / 2.0
+    return {"nu_f": nu_f, "k_b": k_b, "k_s": stretch_constant(radius, l0),
+            "confinement": lc / ny}
+
+
+def _make(name, *, nx, ny, n_beads, radius, l0, u_wall, re_ps, kappa, theta0, steps,
+          storage, eta_ratio=50.0, xi=1.0, init_flow=1) -> Workload:
+    m = physical_to_lattice(nx=nx, ny=ny, n_beads=n_beads, radius=radius, l0=l0,
+                            u_wall=u_wall, re_ps=re_ps, kappa=kappa)
+    return Workload(name=name, nx=nx, ny=ny, u_wall=u_wall, nu_f=m["nu_f"],
+                    eta_ratio=eta_ratio, xi=xi, n_beads=n_beads, radius=radius, l0=l0,
+                    k_s=m["k_s"], k_b=m["k_b"], theta0=theta0, cx=nx / 2.0, cy=ny / 2.0,
+                    steps=steps, storage=storage, init_flow=init_flow, kappa=kappa,
+                    re_ps=re_ps, confinement=m["confinement"])
+
+
+def c1_small_fp64() -> Workload:
+    """64x32 channel, U = 0.01, 5 beads of radius 2 at spacing 2 tilted 45 deg,
+    r_eta = 50, xi = 1, Re_ps = 1, K = 0.33 (the paper's S-turn stiffness), 1000 steps."""
+    return _make("c1_64x32_fp64", nx=64, ny=32, n_beads=5, radius=2.0, l0=2.0, u_wall=0.01,
+                 re_ps=1.0, kappa=0.33, theta0=math.pi / 4, steps=1000, storage="f64")
+
+
+def c2_medium_fp32(seed: int = 2212) -> Workload:
+    """1024x256, 20 beads of radius 3, l_c / H = 0.5, Re_ps = 10, K log-uniform in
+    [1e-3, 1e1] drawn from the seed, flat start (theta = 0), 50k steps."""
+    rng = np.random.default_rng(seed)
+    kappa = float(10.0 ** rng.uniform(-3.0, 1.0))
+    lc = 0.5 * 256
+    return _make("c2_1024x256_fp32", nx=1024, ny=256, n_beads=20, radius=3.0, l0=lc / 20,
+                 u_wall=0.01, re_ps=10.0, kappa=kappa, theta0=0.0, steps=50000,
+                 storage="f32")
+
+
+def c3_large(storage: str = "f32") -> Workload:
+    """8192x2048 (16.8M sites), 40 beads of radius 4 at spacing 8, Re_ps = 5, K = 3.3,
+    theta = 45 deg, 2000 steps: the bandwidth-roofline run."""
+    return _make(f"c3_8192x2048_{storage}", nx=8192, ny=2048, n_beads=40, radius=4.0,
+                 l0=8.0, u_wall=0.01, re_ps=5.0, kappa=3.3, theta0=math.pi / 4,
+                 steps=2000, storage=storage)
+
+
+def sweep_sims(count: int = 256, seed: int = 14153, steps: int = 20000,
+               storage: str = "f32") -> list:
+    """Parameter-sweep simulations: N_y ~ U{64..512}, N_x = 2 N_y, N ~ U{5..30},
+    C ~ U[0.2, 0.8], l0 = C N_y / N, a = l0 / 2 (tuples with a < 2 are drawn again),
+    Re_ps ~ U[1, 10], U = Re_ps / (15 C^2 H) clamped to [1e-3, 0.05] (targets nu = 1/30),
+    K ~ log-uniform [1e-3, 1e1], xi = 1, r_eta = 50, theta = 45 deg."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        ny = int(rng.integers(64, 513))
+        n = int(rng.integers(5, 31))
+        conf = float(rng.uniform(0.2, 0.8))
+        re = float(rng.uniform(1.0, 10.0))
+        kappa = float(10.0 ** rng.uniform(-3.0, 1.0))
+        lc = conf * ny
+        l0 = lc / n
+        a = l0 / 2.0
+        if a < 2.0:
+            continue
+        u = min(max(re / (15.0 * conf * conf * ny), 1e-3), 0.05)
+        out.append(_make(f"sweep{len(out):03d}", nx=2 * ny, ny=ny, n_beads=n, radius=a,
+                         l0=l0, u_wall=u, re_ps=re, kappa=kappa, theta0=math.pi / 4,
+                         steps=steps, storage=storage))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float = 50.0, seed: int = 50) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def perturbation(shape, amplitude: float, seed: int) -> np.ndarray:
+    """Seeded uniform noise in [-amplitude, amplitude] (float64)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amplitude, amplitude, size=shape)
+
+
+def random_beads(n: int, nx: int, ny: int, margin: float, seed: int) -> np.ndarray:
+    """n bead centres drawn uniformly in [0, nx) x [margin, ny - margin]."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(0.0, nx, n), rng.uniform(margin, ny - margin, n)], axis=1)
