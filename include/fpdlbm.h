@@ -1,0 +1,220 @@
+/*
+ * fpdlbm.h -- C ABI of the MI355X (gfx950) library for one time step of the fluid
+ * particle dynamics (FPD) method for a flexible bead-spring fiber in confined shear flow,
+ * solved by a D2Q9 multiple-relaxation-time lattice Boltzmann (MRT-LBM) scheme
+ * (arXiv:2212.14153, Sec. II).
+ *
+ * What one step computes (Sec. II.C, integration steps (1)-(3)):
+ *   (1) from the bead centres R_i^n: the interface profiles phi_i^n (Eq. 2), the bead
+ *       forces F_i^n (Eqs. 10-12), the force density f^n (Eq. 4) and the viscosity
+ *       eta^n (Eq. 1);
+ *   (2) one MRT-LBM collide-and-stream update of the fluid with the local viscosity
+ *       eta^n and the force density f^n, walls at y = 0 and y = H moving at -U and +U
+ *       (Sec. IV.A, Fig. 1b), x periodic;
+ *   (3) the bead velocities V_i^{n+1} (Eq. 5) and the forward-Euler update
+ *       R_i^{n+1} = R_i^n + dt V_i^{n+1}.
+ *
+ * Units and geometry: lattice units, dx = dt = 1, c_s^2 = 1/3, reference density 1.
+ * The paper's z axis is y.  Node (i, j), 0 <= i < nx, 0 <= j < ny, sits at the square
+ * centre (i + 1/2, j + 1/2) (Sec. II.C); the walls lie at y = 0 and y = ny; bead
+ * coordinates are continuous in [0, nx) x (0, ny) (x may leave [0, nx); it is taken
+ * modulo nx through the minimum image).
+ *
+ * Array layouts on the host side of this ABI (all arrays are caller-owned, float64,
+ * C order):
+ *   populations f[9][ny][nx], direction k = 0..8 with
+ *     e_0 = (0,0), e_1..e_4 = (1,0),(0,1),(-1,0),(0,-1),
+ *     e_5..e_8 = (1,1),(-1,1),(-1,-1),(1,-1);
+ *   per-node fields [ny][nx]; bead arrays [n_beads][2].
+ * Device-side layout (not visible through this ABI): nine SoA planes, rows padded to a
+ * multiple of 64 elements, two buffers (pull streaming), stored as f - w_k.
+ *
+ * Errors: every int-returning call returns FPD_OK (0) or a negative FPD_E* code and
+ * never throws; fpd_last_error() gives a message for the calling thread.  Calls on one
+ * simulation must come from one thread at a time.  Calls that return data to the host
+ * synchronise the simulation's stream; fpd_step only enqueues work.
+ */
+#ifndef FPDLBM_H
+#define FPDLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes ---- */
+#define FPD_OK          0
+#define FPD_EINVAL     -1   /* invalid argument or parameter set                         */
+#define FPD_ENOMEM     -2   /* device allocation failed or the HBM budget is exhausted    */
+#define FPD_EUNSTABLE  -3   /* a health check tripped (see FPD_HEALTH_*)                  */
+#define FPD_EDEVICE    -4   /* HIP runtime error                                          */
+#define FPD_ESTATE     -5   /* call not valid in the current state                        */
+
+/* population storage formats (arithmetic is FP64 for FPD_F64, FP32 otherwise) */
+#define FPD_F64        0    /* float64 f - w_k                                            */
+#define FPD_F32        1    /* float32 f - w_k                                            */
+#define FPD_F16DEV     2    /* binary16 of (f - w_k) * 2^14                               */
+#define FPD_BF16DEV    3    /* bfloat16 of (f - w_k)                                      */
+
+/* initial flow (the paper starts from a flat fiber in the shear flow, Sec. IV.C) */
+#define FPD_INIT_REST            0   /* rho = 1, u = 0 everywhere                         */
+#define FPD_INIT_LINEAR_COUETTE  1   /* equilibrium at u_x = U (2 y / H - 1)              */
+
+/* flags */
+#define FPD_FLAG_CLAMP_PHI     0x1u  /* clamp sum_i phi_i to 1 in Eq. (1)                 */
+#define FPD_FLAG_NO_GRAPH      0x2u  /* launch every kernel directly (no graph replay)    */
+#define FPD_FLAG_TIME_KERNELS  0x4u  /* time every kernel with events (implies NO_GRAPH)  */
+
+/* health bits, sticky until fpd_clear_health */
+#define FPD_HEALTH_NAN      0x1u   /* NaN or Inf in a bead position or velocity           */
+#define FPD_HEALTH_STRAIN   0x2u   /* a bond is stretched or compressed by more than 50%  */
+#define FPD_HEALTH_MACH     0x4u   /* a bead moves faster than 0.3 c_s                    */
+#define FPD_HEALTH_WALL     0x8u   /* a bead came within a + xi of a wall                 */
+#define FPD_HEALTH_SUPPORT  0x10u  /* the fiber outgrew the reserved support window       */
+
+#define FPD_MAX_BEADS 256
+
+/* Parameters of one simulation, lattice units.  Names follow the paper: r_eta = eta_s /
+ * eta_f (Sec. II.A remark (1)), xi and a of Eq. (2), k_s, k_b, l_0 of Eq. (9). */
+typedef struct fpd_params {
+    int32_t  nx, ny;        /* lattice squares along x (periodic) and y (between walls)    */
+    double   u_wall;        /* U: bottom wall moves at -U, top wall at +U (|U| < 0.1)       */
+    double   nu_f;          /* fluid kinematic viscosity eta_f / rho (> 0)                  */
+    double   eta_ratio;     /* r_eta = eta_s / eta_f (>= 1)                                 */
+    double   xi;            /* interface thickness xi (> 0)                                 */
+    int32_t  n_beads;       /* N, 0 (no fiber) .. FPD_MAX_BEADS                             */
+    double   radius;        /* bead radius a (> 0)                                          */
+    double   l0;            /* spring rest length l_0 (> 0)                                 */
+    double   k_s, k_b;      /* stretching and bending constants (>= 0)                      */
+    double   s_e, s_eps;    /* MRT rates of the energy moments, in (0, 2)                   */
+    double   s_q_fixed;     /* > 0: heat-flux rate; <= 0: per-node value with
+                               (1/s_nu - 1/2)(1/s_q - 1/2) = 3/16                            */
+    double   cutoff;        /* phi is evaluated within a + cutoff * xi of each bead and
+                               taken as 0 beyond; <= 0 selects 20 (FPD_F64) or 9 (others)    */
+    int32_t  storage;       /* FPD_F64 | FPD_F32 | FPD_F16DEV | FPD_BF16DEV                 */
+    int32_t  init_flow;     /* FPD_INIT_REST | FPD_INIT_LINEAR_COUETTE                      */
+    uint32_t flags;         /* FPD_FLAG_*                                                   */
+} fpd_params;
+
+/* Launch shape of the fused lattice kernel; any field <= 0 keeps the current value. */
+typedef struct fpd_launch {
+    int32_t block_x;          /* threads per block along x: 64, 128 or 256                 */
+    int32_t block_y;          /* thread rows per block: 1, 2, 4 (block_x*block_y <= 1024)  */
+    int32_t rows_per_thread;  /* lattice rows per thread: 1, 2 or 4                         */
+    int32_t xcd_remap;        /* 1: consecutive tiles on one XCD; 2: off                    */
+    int32_t graph_chunk;      /* steps per captured graph (even, >= 2)                      */
+} fpd_launch;
+
+typedef struct fpd_sim fpd_sim;
+
+/* ------------------------------------------------------------- parameters ---- */
+
+/* Fill p with defaults: no fiber, nu_f = 1/6, r_eta = 50, xi = 1, s_e = 1.64,
+ * s_eps = 1.54, magic s_q, FPD_F32, linear Couette start. */
+void fpd_params_default(fpd_params *p);
+
+/* Lattice parameters from the physical groups of Eq. (18): K = 2 k_b / (eta_f gamma
+ * l_c^2), C = l_c / H, Re_ps = rho gamma l_c^2 / (4 eta_f), with gamma = 2U/H and
+ * l_c = N l_0, l_0 = 2a (touching beads, Sec. II.B).  ny = l_c / C, nx = nx_over_ny * ny,
+ * k_s / l_0^2 = 0.1 pi a^2 (explicit-coupling stability; the paper's K_s = 3.33e6 is not
+ * reachable in lattice units).  Fills *out (other fields from fpd_params_default).
+ * Returns FPD_EINVAL when the result violates fpd_create's checks. */
+int fpd_params_from_physical(double re_ps, double confinement, double kappa, int32_t n_beads,
+                             double radius, double eta_ratio, double xi, double u_wall,
+                             int32_t nx_over_ny, fpd_params *out);
+
+/* Bytes of one population buffer for p (the library keeps two). */
+size_t fpd_population_bytes(const fpd_params *p);
+
+/* ------------------------------------------------------------- lifecycle ----- */
+
+/* Validate p (tau_f > 1/2, |U| < 0.1, N <= FPD_MAX_BEADS, sizes >= 1, rates in (0,2)),
+ * allocate device state on the current HIP device, initialise the populations per
+ * p->init_flow.  hip_stream is a hipStream_t (NULL: the library creates its own).
+ * The fiber is absent until fpd_init_fiber. */
+int fpd_create(const fpd_params *p, void *hip_stream, fpd_sim **out);
+
+/* As fpd_create, but the two population buffers are caller-owned device memory of
+ * bytes_each >= fpd_population_bytes(p) bytes each (e.g. torch tensors); they must
+ * outlive the simulation. */
+int fpd_create_with_buffers(const fpd_params *p, void *hip_stream, void *f_a, void *f_b,
+                            size_t bytes_each, fpd_sim **out);
+
+/* Place the fiber: R is host [n_beads][2].  Computes A_i = int phi_i, the forces F_i and
+ * the support window on the device.  Beads closer than a + xi to a wall are rejected
+ * (FPD_EINVAL). */
+int fpd_init_fiber(fpd_sim *s, const double *R);
+
+/* Straight fiber centred at (cx, cy) at angle theta (radians):
+ * R_i = c + (i - (N + 1)/2) l_0 (cos theta, sin theta), i = 1..N. */
+int fpd_init_fiber_line(fpd_sim *s, double cx, double cy, double theta);
+
+/* Enqueue n_steps >= 0 time steps on the simulation's stream (asynchronous). */
+int fpd_step(fpd_sim *s, int64_t n_steps);
+
+/* Wait for the stream; FPD_EUNSTABLE if a health bit is set. */
+int fpd_sync(fpd_sim *s);
+
+/* Health bits (FPD_HEALTH_*) and the largest relative bond strain seen; synchronises. */
+int fpd_health(fpd_sim *s, uint32_t *flags, double *max_strain);
+int fpd_clear_health(fpd_sim *s);
+
+/* Number of steps taken since creation (or the loaded checkpoint). */
+int fpd_step_count(fpd_sim *s, int64_t *steps);
+
+void fpd_destroy(fpd_sim *s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *fpd_last_error(void);
+
+/* -------------------------------------------------------------- read-back ---- */
+
+/* Host arrays [ny][nx], NULL to skip: density rho, velocity u = (j + f^n/2) / rho with the
+ * force density of the current bead state (Guo's macroscopic velocity), viscosity eta^n of
+ * Eq. (1).  Pressure is rho / 3. */
+int fpd_read_fields(fpd_sim *s, double *rho, double *ux, double *uy, double *eta);
+
+/* Host f[9][ny][nx]: the pre-collision (post-stream) populations of the current step,
+ * decoded to float64 whatever the storage. */
+int fpd_read_populations(fpd_sim *s, double *f);
+
+/* Replace the current pre-collision populations with host f[9][ny][nx] (encoded into the
+ * storage format). */
+int fpd_write_populations(fpd_sim *s, const double *f);
+
+/* Host [n_beads][2] each, NULL to skip: R^n, V^n (velocity of the last step), F^n. */
+int fpd_read_beads(fpd_sim *s, double *R, double *V, double *F);
+
+/* ---------------------------------------------------------------- tuning ----- */
+
+int fpd_set_launch(fpd_sim *s, const fpd_launch *cfg);
+
+/* Replace the FPD_FLAG_NO_GRAPH / FPD_FLAG_TIME_KERNELS bits (FPD_FLAG_CLAMP_PHI is fixed
+ * at creation and ignored here); synchronises. */
+int fpd_set_flags(fpd_sim *s, uint32_t flags);
+int fpd_get_launch(fpd_sim *s, fpd_launch *cfg);
+
+/* Kernel timing with FPD_FLAG_TIME_KERNELS: summed event time (ms) and launch count of the
+ * fused lattice kernel and of the bead kernel since the last reset. */
+int fpd_kernel_times(fpd_sim *s, double *ms_lattice, int64_t *n_lattice, double *ms_bead,
+                     int64_t *n_bead);
+int fpd_reset_kernel_times(fpd_sim *s);
+
+/* Device-to-device copy of `bytes` (multiple of 16) on hip_stream, repeated `iters` times
+ * after one warm-up; *gbps receives (read + write bytes) / mean time.  A bandwidth yardstick
+ * for the lattice kernel. */
+int fpd_copy_probe(void *hip_stream, size_t bytes, int32_t iters, double *gbps);
+
+/* ------------------------------------------------------------- checkpoint ---- */
+
+/* Save / restore populations (in storage format), bead state, step count and parameters.
+ * fpd_load requires a simulation created with the same parameters. */
+int fpd_save(fpd_sim *s, const char *path);
+int fpd_load(fpd_sim *s, const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPDLBM_H */

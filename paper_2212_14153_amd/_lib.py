@@ -1,0 +1,302 @@
+"""ctypes binding of ``libfpdlbm.so`` (the C ABI in ``include/fpdlbm.h``).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+Functions keep the C names; :class:`Simulation` is a small convenience wrapper.  The
+library is loaded from this package directory and a missing library is an error (there
+is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpdlbm.so")
+
+FPD_OK, FPD_EINVAL, FPD_ENOMEM, FPD_EUNSTABLE, FPD_EDEVICE, FPD_ESTATE = 0, -1, -2, -3, -4, -5
+FPD_F64, FPD_F32, FPD_F16DEV, FPD_BF16DEV = 0, 1, 2, 3
+FPD_INIT_REST, FPD_INIT_LINEAR_COUETTE = 0, 1
+FPD_FLAG_CLAMP_PHI, FPD_FLAG_NO_GRAPH, FPD_FLAG_TIME_KERNELS = 0x1, 0x2, 0x4
+FPD_HEALTH_NAN, FPD_HEALTH_STRAIN, FPD_HEALTH_MACH, FPD_HEALTH_WALL, FPD_HEALTH_SUPPORT = (
+    0x1, 0x2, 0x4, 0x8, 0x10)
+FPD_MAX_BEADS = 256
+
+STORAGE = {"f64": FPD_F64, "f32": FPD_F32, "f16dev": FPD_F16DEV, "bf16dev": FPD_BF16DEV}
+
+
+class fpd_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("u_wall", ctypes.c_double), ("nu_f", ctypes.c_double),
+        ("eta_ratio", ctypes.c_double), ("xi", ctypes.c_double),
+        ("n_beads", ctypes.c_int32),
+        ("radius", ctypes.c_double), ("l0", ctypes.c_double),
+        ("k_s", ctypes.c_double), ("k_b", ctypes.c_double),
+        ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double),
+        ("s_q_fixed", ctypes.c_double), ("cutoff", ctypes.c_double),
+        ("storage", ctypes.c_int32), ("init_flow", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class fpd_launch(ctypes.Structure):
+    _fields_ = [
+        ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+        ("rows_per_thread", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+        ("graph_chunk", ctypes.c_int32),
+    ]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_SIM = ctypes.c_void_p
+
+# (name, restype, argtypes) for every exported function of include/fpdlbm.h
+SIGNATURES = [
+    ("fpd_params_default", None, [ctypes.POINTER(fpd_params)]),
+    ("fpd_params_from_physical", ctypes.c_int,
+     [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+      ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+      ctypes.POINTER(fpd_params)]),
+    ("fpd_population_bytes", ctypes.c_size_t, [ctypes.POINTER(fpd_params)]),
+    ("fpd_create", ctypes.c_int,
+     [ctypes.POINTER(fpd_params), ctypes.c_void_p, ctypes.POINTER(_SIM)]),
+    ("fpd_create_with_buffers", ctypes.c_int,
+     [ctypes.POINTER(fpd_params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_size_t, ctypes.POINTER(_SIM)]),
+    ("fpd_init_fiber", ctypes.c_int, [_SIM, _D]),
+    ("fpd_init_fiber_line", ctypes.c_int, [_SIM, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    ("fpd_step", ctypes.c_int, [_SIM, ctypes.c_int64]),
+    ("fpd_sync", ctypes.c_int, [_SIM]),
+    ("fpd_health", ctypes.c_int, [_SIM, ctypes.POINTER(ctypes.c_uint32), _D]),
+    ("fpd_clear_health", ctypes.c_int, [_SIM]),
+    ("fpd_step_count", ctypes.c_int, [_SIM, ctypes.POINTER(ctypes.c_int64)]),
+    ("fpd_destroy", None, [_SIM]),
+    ("fpd_last_error", ctypes.c_char_p, []),
+    ("fpd_read_fields", ctypes.c_int, [_SIM, _D, _D, _D, _D]),
+    ("fpd_read_populations", ctypes.c_int, [_SIM, _D]),
+    ("fpd_write_populations", ctypes.c_int, [_SIM, _D]),
+    ("fpd_read_beads", ctypes.c_int, [_SIM, _D, _D, _D]),
+    ("fpd_set_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
+    ("fpd_get_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
+    ("fpd_set_flags", ctypes.c_int, [_SIM, ctypes.c_uint32]),
+    ("fpd_kernel_times", ctypes.c_int,
+     [_SIM, _D, ctypes.POINTER(ctypes.c_int64), _D, ctypes.POINTER(ctypes.c_int64)]),
+    ("fpd_reset_kernel_times", ctypes.c_int, [_SIM]),
+    ("fpd_copy_probe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, _D]),
+    ("fpd_save", ctypes.c_int, [_SIM, ctypes.c_char_p]),
+    ("fpd_load", ctypes.c_int, [_SIM, ctypes.c_char_p]),
+]
+
+_lib = None
+
+
+class FpdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fpd error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+                " or `python paper_2212_14153_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> int:
+    if rc != FPD_OK:
+        raise FpdError(rc, lib().fpd_last_error().decode())
+    return rc
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+# ------------------------------------------------------------ thin C-name wrappers ---
+
+def fpd_params_default() -> fpd_params:
+    p = fpd_params()
+    lib().fpd_params_default(ctypes.byref(p))
+    return p
+
+
+def fpd_params_from_physical(re_ps, confinement, kappa, n_beads, radius, eta_ratio, xi,
+                             u_wall, nx_over_ny) -> fpd_params:
+    p = fpd_params()
+    check(lib().fpd_params_from_physical(re_ps, confinement, kappa, n_beads, radius,
+                                         eta_ratio, xi, u_wall, nx_over_ny, ctypes.byref(p)))
+    return p
+
+
+def fpd_population_bytes(p: fpd_params) -> int:
+    return int(lib().fpd_population_bytes(ctypes.byref(p)))
+
+
+def fpd_copy_probe(stream, nbytes: int, iters: int) -> float:
+    out = ctypes.c_double()
+    check(lib().fpd_copy_probe(stream, nbytes, iters, ctypes.byref(out)))
+    return out.value
+
+
+def params_from_mapping(m, storage=None, **over) -> fpd_params:
+    """Build fpd_params from a mapping with the same field names (extra keys ignored)."""
+    p = fpd_params_default()
+    d = dict(m)
+    d.update(over)
+    for name, _ in fpd_params._fields_:
+        if name in d and name != "storage":
+            setattr(p, name, d[name])
+    st = storage if storage is not None else d.get("storage", "f32")
+    p.storage = STORAGE[st] if isinstance(st, str) else int(st)
+    return p
+
+
+@dataclass
+class LaunchConfig:
+    block_x: int = 64
+    block_y: int = 4
+    rows_per_thread: int = 1
+    xcd_remap: int = 1
+    graph_chunk: int = 64
+
+
+class Simulation:
+    """One simulation on the current HIP device, driven through the C ABI."""
+
+    def __init__(self, params: fpd_params, stream=None, buffers=None):
+        self.p = params
+        h = _SIM()
+        if buffers is None:
+            check(lib().fpd_create(ctypes.byref(params), stream, ctypes.byref(h)))
+        else:
+            a, b, nbytes = buffers
+            check(lib().fpd_create_with_buffers(ctypes.byref(params), stream, a, b, nbytes,
+                                                ctypes.byref(h)))
+        self.h = h
+        self.nx, self.ny, self.n = params.nx, params.ny, params.n_beads
+
+    # lifecycle
+    def close(self):
+        if self.h:
+            lib().fpd_destroy(self.h)
+            self.h = _SIM()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def init_fiber(self, R):
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(self.n, 2)
+        check(lib().fpd_init_fiber(self.h, _ptr(R)))
+
+    def init_fiber_line(self, cx, cy, theta):
+        check(lib().fpd_init_fiber_line(self.h, cx, cy, theta))
+
+    def step(self, n: int):
+        check(lib().fpd_step(self.h, int(n)))
+
+    def sync(self):
+        check(lib().fpd_sync(self.h))
+
+    def health(self):
+        f = ctypes.c_uint32()
+        s = ctypes.c_double()
+        check(lib().fpd_health(self.h, ctypes.byref(f), ctypes.byref(s)))
+        return f.value, s.value
+
+    def clear_health(self):
+        check(lib().fpd_clear_health(self.h))
+
+    @property
+    def steps(self) -> int:
+        v = ctypes.c_int64()
+        check(lib().fpd_step_count(self.h, ctypes.byref(v)))
+        return v.value
+
+    # data
+    def populations(self) -> np.ndarray:
+        f = np.empty((9, self.ny, self.nx))
+        check(lib().fpd_read_populations(self.h, _ptr(f)))
+        return f
+
+    def write_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.ny, self.nx)
+        check(lib().fpd_write_populations(self.h, _ptr(f)))
+
+    def fields(self):
+        out = [np.empty((self.ny, self.nx)) for _ in range(4)]
+        check(lib().fpd_read_fields(self.h, *[_ptr(o) for o in out]))
+        return tuple(out)
+
+    def beads(self):
+        R = np.empty((max(self.n, 0), 2))
+        V = np.empty_like(R)
+        F = np.empty_like(R)
+        if self.n:
+            check(lib().fpd_read_beads(self.h, _ptr(R), _ptr(V), _ptr(F)))
+        return R, V, F
+
+    # tuning / timing
+    def set_launch(self, cfg: LaunchConfig | dict):
+        d = cfg if isinstance(cfg, dict) else cfg.__dict__
+        c = fpd_launch(*(int(d.get(k, 0)) for k, _ in fpd_launch._fields_))
+        check(lib().fpd_set_launch(self.h, ctypes.byref(c)))
+
+    def set_flags(self, flags: int):
+        check(lib().fpd_set_flags(self.h, int(flags)))
+
+    def get_launch(self) -> LaunchConfig:
+        c = fpd_launch()
+        check(lib().fpd_get_launch(self.h, ctypes.byref(c)))
+        return LaunchConfig(c.block_x, c.block_y, c.rows_per_thread, c.xcd_remap, c.graph_chunk)
+
+    def kernel_times(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        na, nb = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().fpd_kernel_times(self.h, ctypes.byref(a), ctypes.byref(na), ctypes.byref(b),
+                                     ctypes.byref(nb)))
+        return a.value, na.value, b.value, nb.value
+
+    def reset_kernel_times(self):
+        check(lib().fpd_reset_kernel_times(self.h))
+
+    def save(self, path: str):
+        check(lib().fpd_save(self.h, path.encode()))
+
+    def load(self, path: str):
+        check(lib().fpd_load(self.h, path.encode()))
+
+
+def simulation_from_workload(w, storage=None, stream=None, flags=0, **over) -> Simulation:
+    """Create a Simulation for a workload (lattice parameters + straight fiber)."""
+    p = params_from_mapping(w.params(), storage=storage if storage else w.storage, flags=flags,
+                            **over)
+    sim = Simulation(p, stream=stream)
+    if p.n_beads > 0:
+        sim.init_fiber(w.beads())
+    return sim

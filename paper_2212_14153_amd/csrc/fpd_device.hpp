@@ -1,0 +1,269 @@
+// fpd_device.hpp -- device-side building blocks of the FPD / MRT-LBM fiber step on gfx950.
+//
+// Lattice: D2Q9, directions e_0 = (0,0), e_1..e_4 = (1,0),(0,1),(-1,0),(0,-1),
+// e_5..e_8 = (1,1),(-1,1),(-1,-1),(1,-1); weights 4/9, 1/9, 1/36.  Node (x, y) sits at the
+// square centre (x + 1/2, y + 1/2) (arXiv:2212.14153, Sec. II.C); walls at y = 0 (moving at
+// -U) and y = ny (moving at +U) (Sec. IV.A); x periodic.
+//
+// Storage: nine SoA planes g_k = f_k - w_k (deviations from the rest equilibrium), row
+// stride padded to 64 elements.  A buffer holds post-collision values; a step pulls them
+// along -e_k (half-way bounce-back at the walls), collides, and writes the next buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fpd_internal.hpp"
+
+namespace fpd {
+
+// ----------------------------------------------------------------- storage codecs ----
+// g = f - w in the storage type; `T` is the arithmetic type of the collision.
+
+template <int ST> struct Codec;
+
+template <> struct Codec<FPD_F64> {
+    using store_t = double;
+    using T = double;
+    __device__ static inline T load(const store_t* p) { return *p; }
+    __device__ static inline void store(store_t* p, T v) { __builtin_nontemporal_store(v, p); }
+    __device__ static inline double to_f64(store_t v) { return v; }
+    __device__ static inline store_t from_f64(double v) { return v; }
+};
+
+template <> struct Codec<FPD_F32> {
+    using store_t = float;
+    using T = float;
+    __device__ static inline T load(const store_t* p) { return *p; }
+    __device__ static inline void store(store_t* p, T v) { __builtin_nontemporal_store(v, p); }
+    __device__ static inline double to_f64(store_t v) { return (double)v; }
+    __device__ static inline store_t from_f64(double v) { return (float)v; }
+};
+
+// binary16 of g * 2^14: |g| < 1 keeps the scaled value far below the binary16 maximum,
+// and the scale lifts the small deviations out of the subnormal range.
+template <> struct Codec<FPD_F16DEV> {
+    using store_t = _Float16;
+    using T = float;
+    static constexpr float kScale = 16384.0f;
+    static constexpr float kInv = 1.0f / 16384.0f;
+    __device__ static inline T load(const store_t* p) { return (float)(*p) * kInv; }
+    __device__ static inline void store(store_t* p, T v) {
+        __builtin_nontemporal_store((_Float16)(v * kScale), p);
+    }
+    __device__ static inline double to_f64(store_t v) { return (double)(float)v * (double)kInv; }
+    __device__ static inline store_t from_f64(double v) { return (_Float16)(float)(v * 16384.0); }
+};
+
+// bfloat16 of g, round to nearest even (deviations are finite here).
+__device__ inline uint16_t f32_to_bf16(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <> struct Codec<FPD_BF16DEV> {
+    using store_t = uint16_t;
+    using T = float;
+    __device__ static inline T load(const store_t* p) { return bf16_to_f32(*p); }
+    __device__ static inline void store(store_t* p, T v) {
+        __builtin_nontemporal_store(f32_to_bf16(v), p);
+    }
+    __device__ static inline double to_f64(store_t v) { return (double)bf16_to_f32(v); }
+    __device__ static inline store_t from_f64(double v) { return f32_to_bf16((float)v); }
+};
+
+// ------------------------------------------------------------------- helpers --------
+
+__device__ inline int imod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Blocks are handed to the 8 XCDs round-robin; give every XCD one contiguous run of tiles
+// so neighbouring tiles (which share cache lines through the x-shifted pulls) meet in the
+// same L2.  A bijection on [0, nblocks).
+__device__ inline int xcd_tile(int bid, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int xcd = bid & 7, local = bid >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + local;
+}
+
+// Columns and rows whose node centres can lie within rc of a bead at (Rx, Ry):
+// columns i0 + [0, w) modulo nx (w <= nx), rows j0..j1 (clipped to the channel).
+__device__ inline void bead_box(double Rx, double Ry, double rc, int nx, int ny, int& i0,
+                                int& w, int& j0, int& j1) {
+    const int lo = (int)floor(Rx - 0.5 - rc);
+    const int hi = (int)ceil(Rx - 0.5 + rc);
+    w = hi - lo + 1;
+    if (w >= nx) {
+        w = nx;
+        i0 = 0;
+    } else {
+        i0 = imod(lo, nx);
+    }
+    const int a = (int)floor(Ry - 0.5 - rc);
+    const int b = (int)ceil(Ry - 0.5 + rc);
+    j0 = a < 0 ? 0 : a;
+    j1 = b > ny - 1 ? ny - 1 : b;
+}
+
+// Do the column sets c0 + [0, cw) and i0 + [0, w) (both modulo nx) intersect?
+__device__ inline bool cols_overlap(int c0, int cw, int i0, int w, int nx) {
+    return imod(c0 - i0, nx) < w || imod(i0 - c0, nx) < cw;
+}
+
+// Minimum-image x distance, written as in the oracle's definition.
+__device__ inline double min_image(double dx, int nx) {
+    return dx - (double)nx * floor(dx / (double)nx + 0.5);
+}
+
+// phi of Eq. (2): 1/2 (tanh((a - r)/xi) + 1).
+__device__ inline double phi_f64(double r, double a, double xi) {
+    return 0.5 * (tanh((a - r) / xi) + 1.0);
+}
+__device__ inline float phi_f32(float r, float a, float inv_xi) {
+    return 0.5f * (tanhf((a - r) * inv_xi) + 1.0f);
+}
+
+template <typename T> struct PhiEval;
+template <> struct PhiEval<double> {
+    __device__ static inline double eval(double dx, double dy, double rc2, double a,
+                                         double xi, double) {
+        const double r2 = dx * dx + dy * dy;
+        if (r2 >= rc2) return 0.0;
+        return phi_f64(sqrt(r2), a, xi);
+    }
+};
+template <> struct PhiEval<float> {
+    __device__ static inline float eval(double dx, double dy, double rc2, double a, double,
+                                        double inv_xi) {
+        const float fx = (float)dx, fy = (float)dy;
+        const float r2 = fx * fx + fy * fy;
+        if (r2 >= (float)rc2) return 0.0f;
+        return phi_f32(sqrtf(r2), (float)a, (float)inv_xi);
+    }
+};
+
+// -------------------------------------------------------------- pull streaming -----
+// g[k] <- post-collision g*_k at x - e_k; x wraps; a population that would come from
+// behind a wall is the node's own reflected g*_{opp(k)} plus 6 w_k rho0 (e_k . u_wall),
+// i.e. +-U/6 on the diagonals (u_wall = -U below, +U above).
+
+template <class Cd>
+__device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx, int ny,
+                            int stride, long long plane, int x, int y,
+                            typename Cd::T u6, typename Cd::T g[9]) {
+    using S = typename Cd::store_t;
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const S* p0 = src;
+    const S* p1 = src + plane;
+    const S* p2 = src + 2 * plane;
+    const S* p3 = src + 3 * plane;
+    const S* p4 = src + 4 * plane;
+    const S* p5 = src + 5 * plane;
+    const S* p6 = src + 6 * plane;
+    const S* p7 = src + 7 * plane;
+    const S* p8 = src + 8 * plane;
+    const int r0 = y * stride;
+    g[0] = Cd::load(p0 + r0 + x);
+    g[1] = Cd::load(p1 + r0 + xm);
+    g[3] = Cd::load(p3 + r0 + xp);
+    if (y > 0) {
+        const int rm = r0 - stride;
+        g[2] = Cd::load(p2 + rm + x);
+        g[5] = Cd::load(p5 + rm + xm);
+        g[6] = Cd::load(p6 + rm + xp);
+    } else {
+        g[2] = Cd::load(p4 + r0 + x);
+        g[5] = Cd::load(p7 + r0 + x) - u6;
+        g[6] = Cd::load(p8 + r0 + x) + u6;
+    }
+    if (y < ny - 1) {
+        const int rp = r0 + stride;
+        g[4] = Cd::load(p4 + rp + x);
+        g[7] = Cd::load(p7 + rp + xp);
+        g[8] = Cd::load(p8 + rp + xm);
+    } else {
+        g[4] = Cd::load(p2 + r0 + x);
+        g[7] = Cd::load(p5 + r0 + x) - u6;
+        g[8] = Cd::load(p6 + r0 + x) + u6;
+    }
+}
+
+// ---------------------------------------------------------- MRT collision ---------
+// Multiple-relaxation-time collision on deviations g = f - w in the Lallemand-Luo moment
+// basis (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy), with Guo's forcing: the velocity is
+// (j + F/2)/rho and the source (I - S/2) applied to the force moments
+//   (0, 6 u.F, -6 u.F, F_x, -F_x, F_y, -F_y, 2(u_x F_x - u_y F_y), u_x F_y + u_y F_x).
+// The moment matrix has entries in {0, +-1, +-2, +-4} and is applied as adds in registers;
+// moments of w are (1, -2, 1, 0, ...), so e and eps are carried as deviations too and no
+// O(1) cancellation enters |m - m_eq|.
+template <typename T>
+__device__ inline void mrt_collide(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s_eps) {
+    const T s14 = (g[1] + g[2]) + (g[3] + g[4]);
+    const T s58 = (g[5] + g[6]) + (g[7] + g[8]);
+    const T drho = g[0] + s14 + s58;
+    const T rho = T(1) + drho;
+    const T d13 = g[1] - g[3], d24 = g[2] - g[4];
+    const T a58 = (g[5] - g[7]), b68 = (g[6] - g[8]);
+    T jx = d13 + a58 - b68;           // g1 - g3 + g5 - g6 - g7 + g8
+    T jy = d24 + a58 + b68;           // g2 - g4 + g5 + g6 - g7 - g8
+    T me = T(2) * s58 - s14 - T(4) * g[0];
+    T meps = s58 - T(2) * s14 + T(4) * g[0];
+    T qx = (a58 - b68) - T(2) * d13;
+    T qy = (a58 + b68) - T(2) * d24;
+    T pxx = (g[1] + g[3]) - (g[2] + g[4]);
+    T pxy = (g[5] + g[7]) - (g[6] + g[8]);
+
+    const T inv_rho = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * inv_rho;
+    const T uy = (jy + T(0.5) * Fy) * inv_rho;
+    const T rux = rho * ux, ruy = rho * uy;
+    const T ru2 = rux * ux + ruy * uy;
+    const T uF = ux * Fx + uy * Fy;
+
+    // m* = m - s (m - m_eq) + (1 - s/2) F_m, moment by moment
+    me = me - s_e * (me - (T(-2) * drho + T(3) * ru2)) + (T(1) - T(0.5) * s_e) * (T(6) * uF);
+    meps = meps - s_eps * (meps - (drho - T(3) * ru2)) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
+    const T hq = T(1) - T(0.5) * s_q;
+    qx = qx - s_q * (qx + rux) - hq * Fx;
+    qy = qy - s_q * (qy + ruy) - hq * Fy;
+    const T hn = T(1) - T(0.5) * s_nu;
+    pxx = pxx - s_nu * (pxx - (rux * ux - ruy * uy)) + hn * T(2) * (ux * Fx - uy * Fy);
+    pxy = pxy - s_nu * (pxy - rux * uy) + hn * (ux * Fy + uy * Fx);
+    jx += Fx;
+    jy += Fy;
+
+    // g = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const T a = drho * T(1.0 / 9.0);
+    const T b = me * T(1.0 / 36.0);
+    const T c = meps * T(1.0 / 36.0);
+    const T d = jx * T(1.0 / 6.0);
+    const T e = qx * T(1.0 / 12.0);
+    const T f = jy * T(1.0 / 6.0);
+    const T h = qy * T(1.0 / 12.0);
+    const T p = pxx * T(0.25);
+    const T q = pxy * T(0.25);
+    const T axis = a - b - T(2) * c;
+    const T diag = a + T(2) * b + c;
+    const T de = d + e, fh = f + h;
+    g[0] = a - T(4) * b + T(4) * c;
+    g[1] = axis + (d - T(2) * e) + p;
+    g[3] = axis - (d - T(2) * e) + p;
+    g[2] = axis + (f - T(2) * h) - p;
+    g[4] = axis - (f - T(2) * h) - p;
+    g[5] = diag + de + fh + q;
+    g[6] = diag - de + fh - q;
+    g[7] = diag - de - fh + q;
+    g[8] = diag + de - fh - q;
+}
+
+// Rest weights, for decoding g back to f.
+__device__ inline double lattice_w(int k) {
+    return k == 0 ? 4.0 / 9.0 : (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+}  // namespace fpd

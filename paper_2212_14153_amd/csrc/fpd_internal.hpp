@@ -1,0 +1,74 @@
+// fpd_internal.hpp -- structures shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fpdlbm.h"
+
+namespace fpd {
+
+constexpr int kMaxBeads = FPD_MAX_BEADS;
+constexpr int kBeadThreads = 256;
+
+// Device-resident fiber state, float64 (bead integration and reductions stay in FP64
+// whatever the population storage).
+struct BeadState {
+    double R[kMaxBeads][2];   // positions R_i^n
+    double V[kMaxBeads][2];   // V_i^n, velocity of the last step
+    double F[kMaxBeads][2];   // F_i^n, Eqs. (10)-(12)
+    double C[kMaxBeads][2];   // F_i^n / A_i^n, the coefficients of Eq. (4)
+    double A[kMaxBeads];      // A_i^n = sum_x phi_i^n(x)
+    int rect[4];              // support window of phi^n: x0 (mod nx), y0, width, height
+    unsigned int health;      // FPD_HEALTH_* bits, sticky
+    unsigned int done;        // blocks of the bead kernel that have finished this launch
+    double max_strain;        // largest |L - l0| / l0 seen
+};
+
+struct Lattice {
+    int nx, ny, stride;       // stride: row pitch in elements (multiple of 64)
+    long long plane;          // elements per direction plane (ny * stride)
+};
+
+// What the kernels need to evaluate phi, eta and the force density near the fiber.
+struct Fiber {
+    BeadState* bs;
+    int n;                    // beads (0: no fiber)
+    double a, xi, inv_xi;     // radius and interface thickness
+    double rc, rc2;           // support radius a + cutoff * xi and its square
+    double nu_f, nu_s;        // fluid and solid kinematic viscosity (rho0 = 1)
+    double s_q_fixed;         // > 0 fixed heat-flux rate, else the magic per-node value
+    int clamp;                // clamp sum phi <= 1
+    void* rect_f;             // force density f^n on the support window, [h][w][2] of T
+    int rect_wmax, rect_hmax; // reserved window
+    double l0, ks_l02, kb;    // spring rest length, k_s / l0^2, k_b
+};
+
+struct StepArgs {
+    const void* src;          // post-collision populations of step n-1
+    void* dst;                // post-collision populations of step n
+    Lattice L;
+    double u6;                // U / 6 (moving-wall momentum on the diagonals)
+    double s_nu_f, s_q_f;     // fluid shear and heat-flux rates away from the fiber
+    double s_e, s_eps;
+    Fiber fib;
+    int tiles_x, n_tiles;     // tiling of the fused lattice kernel
+    int rows_per_block;       // block_y * rows_per_thread
+    int xcd_remap;
+};
+
+// Kernel launchers (fpd_kernels.hip).
+hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
+                       hipStream_t st);
+hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, hipStream_t st);
+hipError_t launch_unstream(int storage, const Lattice& L, double u_wall, const double* f64,
+                           void* dst, hipStream_t st);
+hipError_t launch_stream_out(int storage, const Lattice& L, double u_wall, const void* src,
+                             double* f64, hipStream_t st);
+hipError_t launch_init_eq(const Lattice& L, double u_wall, int init_flow, double* f64,
+                          hipStream_t st);
+hipError_t launch_fields(int storage, const StepArgs& a, double* rho, double* ux,
+                         double* uy, double* eta, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+
+}  // namespace fpd

@@ -1,0 +1,649 @@
+// fpd_kernels.hip -- gfx950 kernels of the FPD / MRT-LBM fiber time step
+// (arXiv:2212.14153, Sec. II.C, integration steps (1)-(3)).
+//
+// One step is two launches:
+//   step_kernel  every node: pull-stream, MRT collision with the local shear rate from
+//                eta^n (Eq. 1) and Guo forcing with f^n (Eq. 4), store.  Tiles that meet
+//                the fiber's support window evaluate phi_i (Eq. 2) from an LDS bead list
+//                and record f^n there for the bead kernel.
+//   bead_kernel  one block per bead: V_i^{n+1} from Eq. (5) over the bead's support box
+//                (FP64 accumulation), R_i^{n+1} = R_i^n + V_i^{n+1}, then A_i^{n+1} at the
+//                new position; the last block to finish computes F^{n+1} (Eqs. 10-12),
+//                F/A, the next support window and the health bits.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fpd_device.hpp"
+
+namespace fpd {
+
+// ------------------------------------------------------------------ reductions ------
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the block in a fixed order (deterministic); result valid in every thread.
+__device__ inline double block_sum(double v, double* scratch) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += scratch[w];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------- bead list for a tile (LDS) ------
+// Ordered compaction of the beads whose support box meets the tile's columns
+// [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
+// beads run in the same order as in a full loop.
+__device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, int cw, int ry0,
+                                   int rh, double (*sR)[2], double (*sC)[2], int* s_wave) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
+    int total = 0;
+    for (int base = 0; base < fib.n; base += nthreads) {
+        const int b = base + tid;
+        bool hit = false;
+        double Rx = 0.0, Ry = 0.0;
+        if (b < fib.n) {
+            Rx = fib.bs->R[b][0];
+            Ry = fib.bs->R[b][1];
+            int i0, w, j0, j1;
+            bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+            hit = (j0 <= j1) && (j0 <= ry0 + rh - 1) && (j1 >= ry0) &&
+                  cols_overlap(cx0, cw, i0, w, nx);
+        }
+        const unsigned long long m = __ballot(hit);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wave] = __popcll(m);
+        __syncthreads();
+        int off = total, chunk = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            if (w < wave) off += s_wave[w];
+            chunk += s_wave[w];
+        }
+        if (hit) {
+            sR[off + before][0] = Rx;
+            sR[off + before][1] = Ry;
+            sC[off + before][0] = fib.bs->C[b][0];
+            sC[off + before][1] = fib.bs->C[b][1];
+        }
+        total += chunk;
+        __syncthreads();
+    }
+    return total;
+}
+
+// ------------------------------------------------------------- fused lattice step ---
+
+template <int ST, int SPT>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
+    using Cd = Codec<ST>;
+    using T = typename Cd::T;
+    using S = typename Cd::store_t;
+    __shared__ double sR[kMaxBeads][2];
+    __shared__ double sC[kMaxBeads][2];
+    __shared__ int s_wave[16];
+
+    const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int bx = blockDim.x;
+    const int x = tx * bx + threadIdx.x;
+    const int ytile = ty * a.rows_per_block;
+    const int ybase = ytile + threadIdx.y * SPT;
+    const int nx = a.L.nx, ny = a.L.ny, stride = a.L.stride;
+    const long long plane = a.L.plane;
+    const S* __restrict__ src = (const S*)a.src;
+    S* __restrict__ dst = (S*)a.dst;
+    const T u6 = (T)a.u6;
+    const T s_e = (T)a.s_e, s_eps = (T)a.s_eps;
+
+    // Block-uniform: does this tile meet the fiber's support window?
+    int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
+    bool fiber_tile = false;
+    if (a.fib.n > 0) {
+        const int* rect = a.fib.bs->rect;
+        wx0 = rect[0];
+        wy0 = rect[1];
+        ww = rect[2];
+        wh = rect[3];
+        fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
+                     ytile + a.rows_per_block - 1 >= wy0 &&
+                     cols_overlap(tx * bx, bx, wx0, ww, nx);
+        if (fiber_tile)
+            nb = gather_beads(a.fib, nx, ny, tx * bx, bx, ytile, a.rows_per_block, sR, sC,
+                              s_wave);
+    }
+
+#pragma unroll
+    for (int r = 0; r < SPT; ++r) {
+        const int y = ybase + r;
+        if (x >= nx || y >= ny) continue;
+        T g[9];
+        pull<Cd>(src, nx, ny, stride, plane, x, y, u6, g);
+        T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
+        if (fiber_tile) {
+            // Step (1) at this node: phi_i^n (Eq. 2), eta^n (Eq. 1), f^n (Eq. 4).
+            const double xc = (double)x + 0.5, yc = (double)y + 0.5;
+            T sphi = T(0);
+            for (int i = 0; i < nb; ++i) {
+                const double dx = min_image(xc - sR[i][0], nx);
+                const double dy = yc - sR[i][1];
+                const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi,
+                                              a.fib.inv_xi);
+                sphi += ph;
+                Fx += ph * (T)sC[i][0];
+                Fy += ph * (T)sC[i][1];
+            }
+            if (a.fib.clamp && sphi > T(1)) sphi = T(1);
+            const T nu_f = (T)a.fib.nu_f;
+            const T eta = nu_f + ((T)a.fib.nu_s - nu_f) * sphi;
+            s_nu = T(1) / (T(3) * eta + T(0.5));
+            s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed
+                                        : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
+            const int wi = imod(x - wx0, nx), wj = y - wy0;
+            if (wi < ww && wj >= 0 && wj < wh) {
+                T* rf = (T*)a.fib.rect_f + 2 * ((long long)wj * a.fib.rect_wmax + wi);
+                rf[0] = Fx;
+                rf[1] = Fy;
+            }
+        }
+        mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
+        S* o = dst + (long long)y * stride + x;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Cd::store(o + k * plane, g[k]);
+    }
+}
+
+// ----------------------------------------------------------------- bead kernel -----
+
+// Forces of Eqs. (10)-(12) on bead t, gathered bond by bond: the stretching energy
+// k_s/(2 l0^2) (L_m - l0)^2 of bond m = (m, m+1) and the bending energy
+// -k_b t_m . t_{m+1} of the pair of bonds (m, m+1), whose forces on the three beads
+// m, m+1, m+2 are k_b times -a_m, a_m - b_m, b_m with
+// a_m = (I - t_m t_m) t_{m+1} / L_m and b_m = (I - t_{m+1} t_{m+1}) t_m / L_{m+1}.
+__device__ inline void bond(const BeadState* bs, int m, double t[2], double& L) {
+    const double dx = bs->R[m + 1][0] - bs->R[m][0];
+    const double dy = bs->R[m + 1][1] - bs->R[m][1];
+    L = sqrt(dx * dx + dy * dy);
+    t[0] = dx / L;
+    t[1] = dy / L;
+}
+
+__device__ inline void proj(const double t[2], const double v[2], double L, double out[2]) {
+    const double vt = v[0] * t[0] + v[1] * t[1];
+    out[0] = (v[0] - vt * t[0]) / L;
+    out[1] = (v[1] - vt * t[1]) / L;
+}
+
+__device__ inline void bead_force(const BeadState* bs, int N, int t, double ks_l02, double l0,
+                                  double kb, double F[2]) {
+    F[0] = 0.0;
+    F[1] = 0.0;
+    double tm[2], tp[2], Lm, Lp, q[2];
+    if (t >= 1) {  // bond (t-1, t): pulls t back towards t-1 when stretched
+        bond(bs, t - 1, tm, Lm);
+        F[0] -= ks_l02 * (Lm - l0) * tm[0];
+        F[1] -= ks_l02 * (Lm - l0) * tm[1];
+    }
+    if (t <= N - 2) {  // bond (t, t+1)
+        bond(bs, t, tp, Lp);
+        F[0] += ks_l02 * (Lp - l0) * tp[0];
+        F[1] += ks_l02 * (Lp - l0) * tp[1];
+    }
+    if (kb == 0.0) return;
+    if (t <= N - 3) {  // pair (t, t+1): bead t is its first bead, gets -k_b a_t
+        double t2[2], L2;
+        bond(bs, t + 1, t2, L2);
+        proj(tp, t2, Lp, q);
+        F[0] -= kb * q[0];
+        F[1] -= kb * q[1];
+    }
+    if (t >= 1 && t <= N - 2) {  // pair (t-1, t): bead t is its middle bead
+        proj(tm, tp, Lm, q);           // a_{t-1}
+        F[0] += kb * q[0];
+        F[1] += kb * q[1];
+        proj(tp, tm, Lp, q);           // b_{t-1}
+        F[0] -= kb * q[0];
+        F[1] -= kb * q[1];
+    }
+    if (t >= 2) {  // pair (t-2, t-1): bead t is its last bead, gets +k_b b_{t-2}
+        double t0[2], L0;
+        bond(bs, t - 2, t0, L0);
+        proj(tm, t0, Lm, q);
+        F[0] += kb * q[0];
+        F[1] += kb * q[1];
+    }
+}
+
+// The block that finishes last: F^{n+1}, F/A, support window, health.
+__device__ void finish_fiber(const StepArgs& a) {
+    const Fiber& fib = a.fib;
+    BeadState* bs = fib.bs;
+    const int N = fib.n, nx = a.L.nx, ny = a.L.ny;
+    __shared__ int s_lo[kBeadThreads], s_hi[kBeadThreads], s_j0[kBeadThreads],
+        s_j1[kBeadThreads];
+    __shared__ unsigned s_h[kBeadThreads];
+    __shared__ double s_strain[kBeadThreads];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < kBeadThreads; t += blockDim.x) {
+        s_lo[t] = 0x7fffffff;
+        s_hi[t] = -0x7fffffff;
+        s_j0[t] = 0x7fffffff;
+        s_j1[t] = -0x7fffffff;
+        s_h[t] = 0u;
+        s_strain[t] = 0.0;
+    }
+    __syncthreads();
+    for (int t = tid; t < N; t += blockDim.x) {
+        double F[2];
+        bead_force(bs, N, t, fib.ks_l02, fib.l0, fib.kb, F);
+        const double A = bs->A[t];
+        bs->F[t][0] = F[0];
+        bs->F[t][1] = F[1];
+        bs->C[t][0] = F[0] / A;
+        bs->C[t][1] = F[1] / A;
+        const double Rx = bs->R[t][0], Ry = bs->R[t][1];
+        const double Vx = bs->V[t][0], Vy = bs->V[t][1];
+        unsigned h = 0u;
+        if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) || !isfinite(A))
+            h |= FPD_HEALTH_NAN;
+        if (Vx * Vx + Vy * Vy > 0.09 / 3.0) h |= FPD_HEALTH_MACH;
+        if (Ry - fib.a - fib.xi < 0.0 || Ry + fib.a + fib.xi > (double)ny) h |= FPD_HEALTH_WALL;
+        double strain = 0.0;
+        if (t <= N - 2) {
+            double tt[2], L;
+            bond(bs, t, tt, L);
+            strain = fabs(L - fib.l0) / fib.l0;
+            if (!(strain <= 0.5)) h |= FPD_HEALTH_STRAIN;
+        }
+        s_h[t] = h;
+        s_strain[t] = strain;
+        if (isfinite(Rx) && isfinite(Ry)) {
+            s_lo[t] = (int)floor(Rx - 0.5 - fib.rc);
+            s_hi[t] = (int)ceil(Rx - 0.5 + fib.rc);
+            s_j0[t] = (int)floor(Ry - 0.5 - fib.rc);
+            s_j1[t] = (int)ceil(Ry - 0.5 + fib.rc);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int lo = 0x7fffffff, hi = -0x7fffffff, j0 = 0x7fffffff, j1 = -0x7fffffff;
+        unsigned h = 0u;
+        double ms = bs->max_strain;
+        for (int t = 0; t < N; ++t) {
+            lo = min(lo, s_lo[t]);
+            hi = max(hi, s_hi[t]);
+            j0 = min(j0, s_j0[t]);
+            j1 = max(j1, s_j1[t]);
+            h |= s_h[t];
+            ms = fmax(ms, s_strain[t]);
+        }
+        int x0 = 0, w = 0, y0 = 0, hgt = 0;
+        if (lo <= hi) {
+            w = hi - lo + 1;
+            if (w >= nx) {
+                w = nx;
+                x0 = 0;
+            } else {
+                x0 = imod(lo, nx);
+            }
+            y0 = j0 < 0 ? 0 : j0;
+            const int y1 = j1 > ny - 1 ? ny - 1 : j1;
+            hgt = y1 >= y0 ? y1 - y0 + 1 : 0;
+        }
+        if (w > fib.rect_wmax || hgt > fib.rect_hmax) {
+            h |= FPD_HEALTH_SUPPORT;
+            w = min(w, fib.rect_wmax);
+            hgt = min(hgt, fib.rect_hmax);
+        }
+        bs->rect[0] = x0;
+        bs->rect[1] = y0;
+        bs->rect[2] = w;
+        bs->rect[3] = hgt;
+        bs->health |= h;
+        bs->max_strain = ms;
+        bs->done = 0u;
+    }
+}
+
+template <int ST>
+__global__ void __launch_bounds__(kBeadThreads) bead_kernel(StepArgs a, int do_velocity) {
+    using Cd = Codec<ST>;
+    using T = typename Cd::T;
+    using S = typename Cd::store_t;
+    __shared__ double scratch[kBeadThreads / 64];
+    __shared__ double s_R[2];
+    __shared__ int s_last;
+    const Fiber& fib = a.fib;
+    BeadState* bs = fib.bs;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int nx = a.L.nx, ny = a.L.ny;
+    double Rx = bs->R[b][0], Ry = bs->R[b][1];
+
+    if (do_velocity) {
+        // Eq. (5): V_i^{n+1} = sum_x phi_i^n (j^{n+1} + f^n / 2) / rho^{n+1} / A_i^n.
+        int i0, w, j0, j1;
+        bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+        const int rows = j1 - j0 + 1;
+        const int total = rows > 0 ? rows * w : 0;
+        const int wx0 = bs->rect[0], wy0 = bs->rect[1], ww = bs->rect[2], wh = bs->rect[3];
+        const T* rf = (const T*)fib.rect_f;
+        const S* cur = (const S*)a.dst;
+        double sx = 0.0, sy = 0.0;
+        for (int t = tid; t < total; t += blockDim.x) {
+            const int jj = j0 + t / w;
+            int ii = i0 + t % w;
+            if (ii >= nx) ii -= nx;
+            const double dx = min_image((double)ii + 0.5 - Rx, nx);
+            const double dy = (double)jj + 0.5 - Ry;
+            const double r2 = dx * dx + dy * dy;
+            if (r2 >= fib.rc2) continue;
+            const double ph = phi_f64(sqrt(r2), fib.a, fib.xi);
+            T g[9];
+            pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii, jj, (T)a.u6, g);
+            double drho = 0.0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) drho += (double)g[k];
+            const double jx = ((double)g[1] - (double)g[3]) + ((double)g[5] - (double)g[6]) -
+                              ((double)g[7] - (double)g[8]);
+            const double jy = ((double)g[2] - (double)g[4]) + ((double)g[5] + (double)g[6]) -
+                              ((double)g[7] + (double)g[8]);
+            // f^n at this node from the window the lattice kernel filled (the window covers
+            // every support box unless it was clamped, which raises FPD_HEALTH_SUPPORT)
+            const int wi = imod(ii - wx0, nx), wj = jj - wy0;
+            double fxn = 0.0, fyn = 0.0;
+            if (wi < ww && wj >= 0 && wj < wh) {
+                const T* fp = rf + 2 * ((long long)wj * fib.rect_wmax + wi);
+                fxn = (double)fp[0];
+                fyn = (double)fp[1];
+            }
+            const double rho = 1.0 + drho;
+            sx += ph * ((jx + 0.5 * fxn) / rho);
+            sy += ph * ((jy + 0.5 * fyn) / rho);
+        }
+        sx = block_sum(sx, scratch);
+        sy = block_sum(sy, scratch);
+        if (tid == 0) {
+            const double A = bs->A[b];
+            const double Vx = sx / A, Vy = sy / A;
+            bs->V[b][0] = Vx;
+            bs->V[b][1] = Vy;
+            s_R[0] = Rx + Vx;  // forward Euler, dt = 1
+            s_R[1] = Ry + Vy;
+            bs->R[b][0] = s_R[0];
+            bs->R[b][1] = s_R[1];
+        }
+        __syncthreads();
+        Rx = s_R[0];
+        Ry = s_R[1];
+    }
+
+    {  // A_i = sum_x phi_i at the (new) position
+        int i0, w, j0, j1;
+        bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+        const int rows = j1 - j0 + 1;
+        const int total = rows > 0 ? rows * w : 0;
+        double s = 0.0;
+        for (int t = tid; t < total; t += blockDim.x) {
+            const int jj = j0 + t / w;
+            int ii = i0 + t % w;
+            if (ii >= nx) ii -= nx;
+            const double dx = min_image((double)ii + 0.5 - Rx, nx);
+            const double dy = (double)jj + 0.5 - Ry;
+            const double r2 = dx * dx + dy * dy;
+            if (r2 < fib.rc2) s += phi_f64(sqrt(r2), fib.a, fib.xi);
+        }
+        s = block_sum(s, scratch);
+        if (tid == 0) bs->A[b] = s;
+    }
+
+    // The last block to get here sees every bead's R, V, A.
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x - 1) ? 1 : 0;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    finish_fiber(a);
+}
+
+// ---------------------------------------------------- conversions and read-back ----
+
+__device__ inline int ex_of(int k) {
+    return (k == 1 || k == 5 || k == 8) ? 1 : ((k == 3 || k == 6 || k == 7) ? -1 : 0);
+}
+__device__ inline int ey_of(int k) {
+    return (k == 2 || k == 5 || k == 6) ? 1 : ((k == 4 || k == 7 || k == 8) ? -1 : 0);
+}
+__device__ inline int opp_of(int k) {
+    return k == 0 ? 0 : (k < 5 ? ((k + 1) & 3) + 1 : ((k - 3) & 3) + 5);
+}
+
+// Post-collision storage whose pull gives the pre-collision f64[9][ny][nx].
+template <int ST>
+__global__ void unstream_kernel(Lattice L, double u_wall, const double* __restrict__ f64,
+                                typename Codec<ST>::store_t* __restrict__ dst) {
+    using Cd = Codec<ST>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= L.nx || y >= L.ny) return;
+    const long long S = (long long)L.nx * L.ny;
+    for (int k = 0; k < 9; ++k) {
+        const int yd = y + ey_of(k);
+        double v;
+        if (yd >= 0 && yd < L.ny) {
+            const int xd = imod(x + ex_of(k), L.nx);
+            v = f64[k * S + (long long)yd * L.nx + xd] - lattice_w(k);
+        } else {
+            const int kb = opp_of(k);
+            const double uw = ey_of(kb) > 0 ? -u_wall : u_wall;
+            v = f64[kb * S + (long long)y * L.nx + x] - lattice_w(kb) -
+                6.0 * lattice_w(kb) * ex_of(kb) * uw;
+        }
+        dst[k * L.plane + (long long)y * L.stride + x] = Cd::from_f64(v);
+    }
+}
+
+template <int ST>
+__global__ void stream_out_kernel(Lattice L, double u_wall, const typename Codec<ST>::store_t* src,
+                                  double* __restrict__ f64) {
+    using Cd = Codec<ST>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= L.nx || y >= L.ny) return;
+    // decode in FP64 so the wall term is added exactly once, in double
+    const int xm = (x == 0) ? L.nx - 1 : x - 1, xp = (x == L.nx - 1) ? 0 : x + 1;
+    const long long P = L.plane;
+    const long long S_ = (long long)L.nx * L.ny;
+    auto at = [&](int k, int xx, int yy) -> double {
+        return Cd::to_f64(src[k * P + (long long)yy * L.stride + xx]);
+    };
+    const double u6 = u_wall / 6.0;
+    double g[9];
+    g[0] = at(0, x, y);
+    g[1] = at(1, xm, y);
+    g[3] = at(3, xp, y);
+    if (y > 0) {
+        g[2] = at(2, x, y - 1);
+        g[5] = at(5, xm, y - 1);
+        g[6] = at(6, xp, y - 1);
+    } else {
+        g[2] = at(4, x, y);
+        g[5] = at(7, x, y) - u6;
+        g[6] = at(8, x, y) + u6;
+    }
+    if (y < L.ny - 1) {
+        g[4] = at(4, x, y + 1);
+        g[7] = at(7, xp, y + 1);
+        g[8] = at(8, xm, y + 1);
+    } else {
+        g[4] = at(2, x, y);
+        g[7] = at(5, x, y) - u6;
+        g[8] = at(6, x, y) + u6;
+    }
+    for (int k = 0; k < 9; ++k) f64[k * S_ + (long long)y * L.nx + x] = lattice_w(k) + g[k];
+}
+
+// Equilibrium f at rho = 1 and u = 0 or u_x = U (2 y / H - 1).
+__global__ void init_eq_kernel(Lattice L, double u_wall, int init_flow, double* f64) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= L.nx || y >= L.ny) return;
+    const double ux = init_flow == FPD_INIT_LINEAR_COUETTE
+                          ? u_wall * (2.0 * ((double)y + 0.5) / (double)L.ny - 1.0)
+                          : 0.0;
+    const long long S = (long long)L.nx * L.ny;
+    for (int k = 0; k < 9; ++k) {
+        const double eu = ex_of(k) * ux;
+        f64[k * S + (long long)y * L.nx + x] =
+            lattice_w(k) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * ux * ux);
+    }
+}
+
+// rho, u = (j + f^n/2)/rho and eta^n at every node from the current state.
+template <int ST>
+__global__ void fields_kernel(StepArgs a, double* rho_o, double* ux_o, double* uy_o,
+                              double* eta_o) {
+    using Cd = Codec<ST>;
+    using T = typename Cd::T;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int nx = a.L.nx, ny = a.L.ny;
+    if (x >= nx || y >= ny) return;
+    T g[9];
+    pull<Cd>((const typename Cd::store_t*)a.src, nx, ny, a.L.stride, a.L.plane, x, y,
+             (T)a.u6, g);
+    double drho = 0.0;
+    for (int k = 0; k < 9; ++k) drho += (double)g[k];
+    const double jx = ((double)g[1] - (double)g[3]) + ((double)g[5] - (double)g[6]) -
+                      ((double)g[7] - (double)g[8]);
+    const double jy = ((double)g[2] - (double)g[4]) + ((double)g[5] + (double)g[6]) -
+                      ((double)g[7] + (double)g[8]);
+    double fx = 0.0, fy = 0.0, sphi = 0.0;
+    const Fiber& fib = a.fib;
+    for (int b = 0; b < fib.n; ++b) {
+        const double dx = min_image((double)x + 0.5 - fib.bs->R[b][0], nx);
+        const double dy = (double)y + 0.5 - fib.bs->R[b][1];
+        const double r2 = dx * dx + dy * dy;
+        if (r2 >= fib.rc2) continue;
+        const double ph = phi_f64(sqrt(r2), fib.a, fib.xi);
+        sphi += ph;
+        fx += ph * fib.bs->C[b][0];
+        fy += ph * fib.bs->C[b][1];
+    }
+    if (fib.clamp && sphi > 1.0) sphi = 1.0;
+    const double rho = 1.0 + drho;
+    const long long s = (long long)y * nx + x;
+    if (rho_o) rho_o[s] = rho;
+    if (ux_o) ux_o[s] = (jx + 0.5 * fx) / rho;
+    if (uy_o) uy_o[s] = (jy + 0.5 * fy) / rho;
+    if (eta_o) eta_o[s] = fib.nu_f + (fib.nu_s - fib.nu_f) * sphi;
+}
+
+__global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t step = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += step) dst[i] = src[i];
+}
+
+// -------------------------------------------------------------------- launchers ----
+
+template <int ST>
+static hipError_t launch_step_t(const StepArgs& a, dim3 block, int spt, hipStream_t st) {
+    const dim3 grid(a.n_tiles);
+    switch (spt) {
+        case 1: hipLaunchKernelGGL((step_kernel<ST, 1>), grid, block, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((step_kernel<ST, 2>), grid, block, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((step_kernel<ST, 4>), grid, block, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int spt, hipStream_t st) {
+    switch (storage) {
+        case FPD_F64: return launch_step_t<FPD_F64>(a, block, spt, st);
+        case FPD_F32: return launch_step_t<FPD_F32>(a, block, spt, st);
+        case FPD_F16DEV: return launch_step_t<FPD_F16DEV>(a, block, spt, st);
+        case FPD_BF16DEV: return launch_step_t<FPD_BF16DEV>(a, block, spt, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, hipStream_t st) {
+    if (a.fib.n <= 0) return hipSuccess;
+    const dim3 grid(a.fib.n), block(kBeadThreads);
+    switch (storage) {
+        case FPD_F64: hipLaunchKernelGGL((bead_kernel<FPD_F64>), grid, block, 0, st, a, do_velocity); break;
+        case FPD_F32: hipLaunchKernelGGL((bead_kernel<FPD_F32>), grid, block, 0, st, a, do_velocity); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((bead_kernel<FPD_F16DEV>), grid, block, 0, st, a, do_velocity); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((bead_kernel<FPD_BF16DEV>), grid, block, 0, st, a, do_velocity); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static dim3 site_grid(const Lattice& L) { return dim3((L.nx + 127) / 128, L.ny); }
+
+hipError_t launch_unstream(int storage, const Lattice& L, double u_wall, const double* f64,
+                           void* dst, hipStream_t st) {
+    const dim3 grid = site_grid(L), block(128);
+    switch (storage) {
+        case FPD_F64: hipLaunchKernelGGL((unstream_kernel<FPD_F64>), grid, block, 0, st, L, u_wall, f64, (double*)dst); break;
+        case FPD_F32: hipLaunchKernelGGL((unstream_kernel<FPD_F32>), grid, block, 0, st, L, u_wall, f64, (float*)dst); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((unstream_kernel<FPD_F16DEV>), grid, block, 0, st, L, u_wall, f64, (_Float16*)dst); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((unstream_kernel<FPD_BF16DEV>), grid, block, 0, st, L, u_wall, f64, (uint16_t*)dst); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_out(int storage, const Lattice& L, double u_wall, const void* src,
+                             double* f64, hipStream_t st) {
+    const dim3 grid = site_grid(L), block(128);
+    switch (storage) {
+        case FPD_F64: hipLaunchKernelGGL((stream_out_kernel<FPD_F64>), grid, block, 0, st, L, u_wall, (const double*)src, f64); break;
+        case FPD_F32: hipLaunchKernelGGL((stream_out_kernel<FPD_F32>), grid, block, 0, st, L, u_wall, (const float*)src, f64); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((stream_out_kernel<FPD_F16DEV>), grid, block, 0, st, L, u_wall, (const _Float16*)src, f64); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((stream_out_kernel<FPD_BF16DEV>), grid, block, 0, st, L, u_wall, (const uint16_t*)src, f64); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_eq(const Lattice& L, double u_wall, int init_flow, double* f64,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(init_eq_kernel, site_grid(L), dim3(128), 0, st, L, u_wall, init_flow, f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int storage, const StepArgs& a, double* rho, double* ux, double* uy,
+                         double* eta, hipStream_t st) {
+    const dim3 grid = site_grid(a.L), block(128);
+    switch (storage) {
+        case FPD_F64: hipLaunchKernelGGL((fields_kernel<FPD_F64>), grid, block, 0, st, a, rho, ux, uy, eta); break;
+        case FPD_F32: hipLaunchKernelGGL((fields_kernel<FPD_F32>), grid, block, 0, st, a, rho, ux, uy, eta); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((fields_kernel<FPD_F16DEV>), grid, block, 0, st, a, rho, ux, uy, eta); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((fields_kernel<FPD_BF16DEV>), grid, block, 0, st, a, rho, ux, uy, eta); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 16;
+    hipLaunchKernelGGL(copy_kernel, dim3(256 * 32), dim3(256), 0, st, (const float4*)src,
+                       (float4*)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace fpd

@@ -1,0 +1,760 @@
+// fpd_runtime.hip -- host side of the C ABI declared in include/fpdlbm.h.
+//
+// One fpd_sim owns (or adopts) two population buffers, a device-resident bead state, the
+// force-density window of the fiber, a HIP stream and the captured graphs that replay
+// chunks of steps.  Every step of the method runs in the kernels of fpd_kernels.hip; this
+// file validates, allocates, launches and copies.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "fpd_internal.hpp"
+
+using namespace fpd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(FPD_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                            \
+    } while (0)
+
+size_t storage_elem(int st) {
+    switch (st) {
+        case FPD_F64: return 8;
+        case FPD_F32: return 4;
+        case FPD_F16DEV:
+        case FPD_BF16DEV: return 2;
+    }
+    return 0;
+}
+
+int padded_stride(int nx) { return (nx + 63) / 64 * 64; }
+
+double default_cutoff(int storage) { return storage == FPD_F64 ? 20.0 : 9.0; }
+
+}  // namespace
+
+struct fpd_sim {
+    fpd_params p;
+    Lattice L;
+    size_t elem = 0, buf_bytes = 0;
+    void* buf[2] = {nullptr, nullptr};
+    bool own_bufs = true;
+    int cur = 0;                 // buffer holding the post-collision state of the last step
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    BeadState* bs = nullptr;
+    void* rect_f = nullptr;
+    int rect_wmax = 0, rect_hmax = 0;
+    double rc = 0.0;
+    bool fiber = false;
+    int64_t steps = 0;
+    fpd_launch launch{};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_chunk = 0;
+    // kernel timing
+    std::vector<hipEvent_t> events;
+    double ms_lat = 0.0, ms_bead = 0.0;
+    int64_t n_lat = 0, n_bead = 0;
+};
+
+namespace {
+
+StepArgs make_args(const fpd_sim* s, int src_idx) {
+    StepArgs a{};
+    a.src = s->buf[src_idx];
+    a.dst = s->buf[1 - src_idx];
+    a.L = s->L;
+    a.u6 = s->p.u_wall / 6.0;
+    const double tau_f = 3.0 * s->p.nu_f + 0.5;
+    a.s_nu_f = 1.0 / tau_f;
+    a.s_q_f = s->p.s_q_fixed > 0.0 ? s->p.s_q_fixed
+                                   : 8.0 * (2.0 - a.s_nu_f) / (8.0 - a.s_nu_f);
+    a.s_e = s->p.s_e;
+    a.s_eps = s->p.s_eps;
+    Fiber& f = a.fib;
+    f.bs = s->bs;
+    f.n = s->fiber ? s->p.n_beads : 0;
+    f.a = s->p.radius;
+    f.xi = s->p.xi;
+    f.inv_xi = 1.0 / s->p.xi;
+    f.rc = s->rc;
+    f.rc2 = s->rc * s->rc;
+    f.nu_f = s->p.nu_f;
+    f.nu_s = s->p.eta_ratio * s->p.nu_f;
+    f.s_q_fixed = s->p.s_q_fixed;
+    f.clamp = (s->p.flags & FPD_FLAG_CLAMP_PHI) ? 1 : 0;
+    f.rect_f = s->rect_f;
+    f.rect_wmax = s->rect_wmax;
+    f.rect_hmax = s->rect_hmax;
+    f.l0 = s->p.l0;
+    f.ks_l02 = s->p.k_s / (s->p.l0 * s->p.l0);
+    f.kb = s->p.k_b;
+    const fpd_launch& c = s->launch;
+    a.rows_per_block = c.block_y * c.rows_per_thread;
+    a.tiles_x = (s->L.nx + c.block_x - 1) / c.block_x;
+    const int tiles_y = (s->L.ny + a.rows_per_block - 1) / a.rows_per_block;
+    a.n_tiles = a.tiles_x * tiles_y;
+    a.xcd_remap = c.xcd_remap == 1 ? 1 : 0;
+    return a;
+}
+
+int validate(const fpd_params* p) {
+    if (!p) return fail(FPD_EINVAL, "params is NULL");
+    if (p->nx < 1 || p->ny < 1) return fail(FPD_EINVAL, "nx, ny must be >= 1");
+    if ((long long)p->ny * padded_stride(p->nx) > 0x7fffffffLL)
+        return fail(FPD_EINVAL, "ny * padded nx must stay below 2^31 nodes per plane");
+    if (!(p->nu_f > 0.0) || !(3.0 * p->nu_f + 0.5 > 0.5))
+        return fail(FPD_EINVAL, "tau_f = 3 nu_f + 1/2 must exceed 1/2 (nu_f = %g)", p->nu_f);
+    if (!(fabs(p->u_wall) < 0.1)) return fail(FPD_EINVAL, "|u_wall| must be < 0.1");
+    if (!(p->s_e > 0.0 && p->s_e < 2.0) || !(p->s_eps > 0.0 && p->s_eps < 2.0))
+        return fail(FPD_EINVAL, "s_e and s_eps must lie in (0, 2)");
+    if (p->s_q_fixed > 0.0 && !(p->s_q_fixed < 2.0))
+        return fail(FPD_EINVAL, "s_q_fixed must lie in (0, 2)");
+    if (storage_elem(p->storage) == 0) return fail(FPD_EINVAL, "unknown storage %d", p->storage);
+    if (p->init_flow != FPD_INIT_REST && p->init_flow != FPD_INIT_LINEAR_COUETTE)
+        return fail(FPD_EINVAL, "unknown init_flow %d", p->init_flow);
+    if (p->n_beads < 0 || p->n_beads > FPD_MAX_BEADS)
+        return fail(FPD_EINVAL, "n_beads must be in [0, %d]", FPD_MAX_BEADS);
+    if (p->n_beads > 0) {
+        if (!(p->radius > 0.0) || !(p->xi > 0.0) || !(p->l0 > 0.0))
+            return fail(FPD_EINVAL, "radius, xi and l0 must be > 0");
+        if (!(p->eta_ratio >= 1.0)) return fail(FPD_EINVAL, "eta_ratio must be >= 1");
+        if (!(p->k_s >= 0.0) || !(p->k_b >= 0.0)) return fail(FPD_EINVAL, "k_s, k_b must be >= 0");
+    }
+    return FPD_OK;
+}
+
+int sync_check(fpd_sim* s) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return FPD_OK;
+}
+
+void drop_graphs(fpd_sim* s) {
+    for (auto& g : s->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    s->graph_chunk = 0;
+}
+
+// One step from buffer `from` (launches only).
+int enqueue_step(fpd_sim* s, int from) {
+    const StepArgs a = make_args(s, from);
+    const dim3 block(s->launch.block_x, s->launch.block_y);
+    HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
+    if (a.fib.n > 0) HIP_TRY(launch_bead(s->p.storage, a, 1, s->stream));
+    return FPD_OK;
+}
+
+int build_graph(fpd_sim* s, int from, int chunk, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int rc = FPD_OK;
+    int b = from;
+    for (int i = 0; i < chunk && rc == FPD_OK; ++i) {
+        rc = enqueue_step(s, b);
+        b = 1 - b;
+    }
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (rc != FPD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    return FPD_OK;
+}
+
+int step_timed(fpd_sim* s, int64_t n) {
+    const bool fib = s->fiber && s->p.n_beads > 0;
+    const size_t per = fib ? 3 : 2;
+    for (int64_t done = 0; done < n;) {
+        const int64_t batch = n - done < 512 ? n - done : 512;
+        const size_t need = (size_t)batch * per;
+        while (s->events.size() < need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            s->events.push_back(e);
+        }
+        for (int64_t i = 0; i < batch; ++i) {
+            const StepArgs a = make_args(s, s->cur);
+            const dim3 block(s->launch.block_x, s->launch.block_y);
+            hipEvent_t* ev = &s->events[(size_t)i * per];
+            HIP_TRY(hipEventRecord(ev[0], s->stream));
+            HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
+            HIP_TRY(hipEventRecord(ev[1], s->stream));
+            if (fib) {
+                HIP_TRY(launch_bead(s->p.storage, a, 1, s->stream));
+                HIP_TRY(hipEventRecord(ev[2], s->stream));
+            }
+            s->cur = 1 - s->cur;
+        }
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        for (int64_t i = 0; i < batch; ++i) {
+            hipEvent_t* ev = &s->events[(size_t)i * per];
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            s->ms_lat += ms;
+            s->n_lat += 1;
+            if (fib) {
+                HIP_TRY(hipEventElapsedTime(&ms, ev[1], ev[2]));
+                s->ms_bead += ms;
+                s->n_bead += 1;
+            }
+        }
+        done += batch;
+    }
+    return FPD_OK;
+}
+
+int fiber_init_device(fpd_sim* s) {
+    const StepArgs a = make_args(s, s->cur);
+    HIP_TRY(launch_bead(s->p.storage, a, 0, s->stream));
+    return FPD_OK;
+}
+
+int upload_populations(fpd_sim* s, const double* host_f) {
+    const size_t n = (size_t)9 * s->p.nx * s->p.ny;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, n * sizeof(double)));
+    hipError_t e = hipSuccess;
+    if (host_f)
+        e = hipMemcpyAsync(d, host_f, n * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    else
+        e = launch_init_eq(s->L, s->p.u_wall, s->p.init_flow, d, s->stream);
+    if (e == hipSuccess)
+        e = launch_unstream(s->p.storage, s->L, s->p.u_wall, d, s->buf[s->cur], s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "population upload: %s", hipGetErrorString(e));
+    return FPD_OK;
+}
+
+bool params_equal(const fpd_params& a, const fpd_params& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.u_wall == b.u_wall && a.nu_f == b.nu_f &&
+           a.eta_ratio == b.eta_ratio && a.xi == b.xi && a.n_beads == b.n_beads &&
+           a.radius == b.radius && a.l0 == b.l0 && a.k_s == b.k_s && a.k_b == b.k_b &&
+           a.s_e == b.s_e && a.s_eps == b.s_eps && a.s_q_fixed == b.s_q_fixed &&
+           a.cutoff == b.cutoff && a.storage == b.storage;
+}
+
+int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t bytes_each,
+                fpd_sim** out) {
+    if (!out) return fail(FPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    fpd_sim* s = new fpd_sim();
+    memset(&s->p, 0, sizeof s->p);
+    s->p = *p;
+    s->L.nx = p->nx;
+    s->L.ny = p->ny;
+    s->L.stride = padded_stride(p->nx);
+    s->L.plane = (long long)p->ny * s->L.stride;
+    s->elem = storage_elem(p->storage);
+    s->buf_bytes = (size_t)9 * (size_t)s->L.plane * s->elem;
+    s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
+    s->launch = fpd_launch{64, 4, 1, 1, 64};
+    auto bail = [&](int code) {
+        fpd_destroy(s);
+        return code;
+    };
+    if (stream) {
+        s->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(FPD_EDEVICE, "hipStreamCreate failed"));
+        s->own_stream = true;
+    }
+    if (fa && fb) {
+        if (bytes_each < s->buf_bytes)
+            return bail(fail(FPD_EINVAL, "buffers of %zu bytes, %zu needed", bytes_each,
+                             s->buf_bytes));
+        s->buf[0] = fa;
+        s->buf[1] = fb;
+        s->own_bufs = false;
+    } else {
+        for (int i = 0; i < 2; ++i)
+            if (hipMalloc(&s->buf[i], s->buf_bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return bail(fail(FPD_ENOMEM, "hipMalloc of %zu bytes failed", s->buf_bytes));
+            }
+    }
+    // padding columns are never read; clear them once so checkpoints are deterministic
+    for (int i = 0; i < 2; ++i)
+        if (hipMemsetAsync(s->buf[i], 0, s->buf_bytes, s->stream) != hipSuccess)
+            return bail(fail(FPD_EDEVICE, "hipMemset failed"));
+    if (hipMalloc((void**)&s->bs, sizeof(BeadState)) != hipSuccess)
+        return bail(fail(FPD_ENOMEM, "bead state allocation failed"));
+    if (hipMemsetAsync(s->bs, 0, sizeof(BeadState), s->stream) != hipSuccess)
+        return bail(fail(FPD_EDEVICE, "hipMemset failed"));
+    if (p->n_beads > 0) {
+        // window large enough for the chain stretched by 50% in any orientation
+        const double span = 1.5 * (p->n_beads - 1) * p->l0 + 2.0 * s->rc + 4.0;
+        s->rect_wmax = (int)ceil(span) < p->nx ? (int)ceil(span) : p->nx;
+        s->rect_hmax = (int)ceil(span) < p->ny ? (int)ceil(span) : p->ny;
+        const size_t tb = p->storage == FPD_F64 ? 8 : 4;
+        if (hipMalloc(&s->rect_f, (size_t)s->rect_wmax * s->rect_hmax * 2 * tb) != hipSuccess)
+            return bail(fail(FPD_ENOMEM, "fiber window allocation failed"));
+        if (hipMemsetAsync(s->rect_f, 0, (size_t)s->rect_wmax * s->rect_hmax * 2 * tb,
+                           s->stream) != hipSuccess)
+            return bail(fail(FPD_EDEVICE, "hipMemset failed"));
+    }
+    rc = upload_populations(s, nullptr);
+    if (rc) return bail(rc);
+    *out = s;
+    return FPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fpd_last_error(void) { return g_err.c_str(); }
+
+void fpd_params_default(fpd_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->nx = 64;
+    p->ny = 32;
+    p->u_wall = 0.0;
+    p->nu_f = 1.0 / 6.0;
+    p->eta_ratio = 50.0;
+    p->xi = 1.0;
+    p->n_beads = 0;
+    p->radius = 2.0;
+    p->l0 = 4.0;
+    p->k_s = 0.0;
+    p->k_b = 0.0;
+    p->s_e = 1.64;
+    p->s_eps = 1.54;
+    p->s_q_fixed = 0.0;
+    p->cutoff = 0.0;
+    p->storage = FPD_F32;
+    p->init_flow = FPD_INIT_LINEAR_COUETTE;
+    p->flags = 0u;
+}
+
+int fpd_params_from_physical(double re_ps, double confinement, double kappa, int32_t n_beads,
+                             double radius, double eta_ratio, double xi, double u_wall,
+                             int32_t nx_over_ny, fpd_params* out) {
+    if (!out) return fail(FPD_EINVAL, "out is NULL");
+    if (!(re_ps > 0.0) || !(confinement > 0.0 && confinement <= 1.0) || !(kappa >= 0.0) ||
+        n_beads < 1 || !(radius > 0.0) || nx_over_ny < 1 || !(u_wall > 0.0))
+        return fail(FPD_EINVAL, "physical parameters out of range");
+    fpd_params_default(out);
+    const double l0 = 2.0 * radius;                        // touching beads, l0 = d
+    const double lc = n_beads * l0;                        // contour length
+    const int ny = (int)lround(lc / confinement);          // C = l_c / H
+    const double gamma = 2.0 * u_wall / ny;                // shear rate of the channel
+    const double nu = gamma * lc * lc / (4.0 * re_ps);     // Re_ps = gamma l_c^2 / (4 nu)
+    out->nx = nx_over_ny * ny;
+    out->ny = ny;
+    out->u_wall = u_wall;
+    out->nu_f = nu;
+    out->eta_ratio = eta_ratio;
+    out->xi = xi;
+    out->n_beads = n_beads;
+    out->radius = radius;
+    out->l0 = l0;
+    out->k_b = kappa * nu * gamma * lc * lc / 2.0;          // K = 2 k_b / (eta_f gamma l_c^2)
+    out->k_s = 0.1 * M_PI * radius * radius * l0 * l0;
+    return validate(out);
+}
+
+size_t fpd_population_bytes(const fpd_params* p) {
+    if (!p || p->nx < 1 || p->ny < 1 || storage_elem(p->storage) == 0) return 0;
+    return (size_t)9 * (size_t)p->ny * padded_stride(p->nx) * storage_elem(p->storage);
+}
+
+int fpd_create(const fpd_params* p, void* hip_stream, fpd_sim** out) {
+    return create_impl(p, hip_stream, nullptr, nullptr, 0, out);
+}
+
+int fpd_create_with_buffers(const fpd_params* p, void* hip_stream, void* f_a, void* f_b,
+                            size_t bytes_each, fpd_sim** out) {
+    if (!f_a || !f_b) return fail(FPD_EINVAL, "buffers must not be NULL");
+    return create_impl(p, hip_stream, f_a, f_b, bytes_each, out);
+}
+
+void fpd_destroy(fpd_sim* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    for (auto e : s->events) (void)hipEventDestroy(e);
+    if (s->own_bufs)
+        for (auto& b : s->buf)
+            if (b) (void)hipFree(b);
+    if (s->bs) (void)hipFree(s->bs);
+    if (s->rect_f) (void)hipFree(s->rect_f);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int fpd_init_fiber(fpd_sim* s, const double* R) {
+    if (!s || !R) return fail(FPD_EINVAL, "NULL argument");
+    const int N = s->p.n_beads;
+    if (N <= 0) return fail(FPD_ESTATE, "the simulation was created without beads");
+    for (int i = 0; i < N; ++i) {
+        const double x = R[2 * i], y = R[2 * i + 1];
+        if (!isfinite(x) || !isfinite(y)) return fail(FPD_EINVAL, "bead %d is not finite", i);
+        if (y - s->p.radius - s->p.xi < 0.0 || y + s->p.radius + s->p.xi > s->p.ny)
+            return fail(FPD_EINVAL, "bead %d lies within a + xi of a wall", i);
+    }
+    for (int i = 0; i + 1 < N; ++i) {
+        const double dx = R[2 * i + 2] - R[2 * i], dy = R[2 * i + 3] - R[2 * i + 1];
+        const double span = sqrt(dx * dx + dy * dy);
+        if (!(span > 0.0)) return fail(FPD_EINVAL, "beads %d and %d coincide", i, i + 1);
+    }
+    // extent check against the reserved window (the device re-checks every step)
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int i = 0; i < N; ++i) {
+        xmin = fmin(xmin, R[2 * i]);
+        xmax = fmax(xmax, R[2 * i]);
+        ymin = fmin(ymin, R[2 * i + 1]);
+        ymax = fmax(ymax, R[2 * i + 1]);
+    }
+    if ((xmax - xmin) + 2.0 * s->rc + 3.0 > s->rect_wmax && s->rect_wmax < s->p.nx)
+        return fail(FPD_EINVAL, "fiber extent exceeds 1.5 (N-1) l0");
+    if ((ymax - ymin) + 2.0 * s->rc + 3.0 > s->rect_hmax && s->rect_hmax < s->p.ny)
+        return fail(FPD_EINVAL, "fiber extent exceeds 1.5 (N-1) l0");
+    int rc0 = sync_check(s);
+    if (rc0) return rc0;
+    BeadState h;
+    memset(&h, 0, sizeof h);
+    HIP_TRY(hipMemcpy(&h, s->bs, sizeof h, hipMemcpyDeviceToHost));
+    for (int i = 0; i < N; ++i) {
+        h.R[i][0] = R[2 * i];
+        h.R[i][1] = R[2 * i + 1];
+        h.V[i][0] = h.V[i][1] = 0.0;
+    }
+    h.done = 0;
+    HIP_TRY(hipMemcpyAsync(s->bs, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
+    s->fiber = true;
+    drop_graphs(s);
+    int rc = fiber_init_device(s);
+    if (rc) return rc;
+    return sync_check(s);
+}
+
+int fpd_init_fiber_line(fpd_sim* s, double cx, double cy, double theta) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    const int N = s->p.n_beads;
+    if (N <= 0) return fail(FPD_ESTATE, "the simulation was created without beads");
+    std::vector<double> R(2 * (size_t)N);
+    for (int i = 1; i <= N; ++i) {
+        const double t = (i - (N + 1) / 2.0) * s->p.l0;
+        R[2 * (i - 1)] = cx + t * cos(theta);
+        R[2 * (i - 1) + 1] = cy + t * sin(theta);
+    }
+    return fpd_init_fiber(s, R.data());
+}
+
+int fpd_step(fpd_sim* s, int64_t n) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    if (n < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
+    if (n == 0) return FPD_OK;
+    if (s->p.n_beads > 0 && !s->fiber)
+        return fail(FPD_ESTATE, "fpd_init_fiber must come before fpd_step");
+    const uint32_t fl = s->p.flags;
+    if (fl & FPD_FLAG_TIME_KERNELS) {
+        int rc = step_timed(s, n);
+        if (rc) return rc;
+        s->steps += n;
+        return FPD_OK;
+    }
+    int64_t left = n;
+    const int chunk = s->launch.graph_chunk;
+    if (!(fl & FPD_FLAG_NO_GRAPH) && chunk >= 2 && left >= chunk) {
+        if (s->graph_chunk != chunk) {
+            drop_graphs(s);
+            s->graph_chunk = chunk;
+        }
+        if (!s->graph[s->cur]) {
+            int rc = build_graph(s, s->cur, chunk, &s->graph[s->cur]);
+            if (rc) return rc;
+        }
+        while (left >= chunk) {
+            HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
+            left -= chunk;  // chunk is even: the state returns to the same buffer
+        }
+    }
+    for (; left > 0; --left) {
+        int rc = enqueue_step(s, s->cur);
+        if (rc) return rc;
+        s->cur = 1 - s->cur;
+    }
+    s->steps += n;
+    return FPD_OK;
+}
+
+int fpd_sync(fpd_sim* s) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    if (s->fiber) {
+        unsigned h = 0;
+        HIP_TRY(hipMemcpy(&h, &s->bs->health, sizeof h, hipMemcpyDeviceToHost));
+        if (h) return fail(FPD_EUNSTABLE, "health flags 0x%x", h);
+    }
+    return FPD_OK;
+}
+
+int fpd_health(fpd_sim* s, uint32_t* flags, double* max_strain) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    unsigned h = 0;
+    double ms = 0.0;
+    HIP_TRY(hipMemcpy(&h, &s->bs->health, sizeof h, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&ms, &s->bs->max_strain, sizeof ms, hipMemcpyDeviceToHost));
+    if (flags) *flags = h;
+    if (max_strain) *max_strain = ms;
+    return FPD_OK;
+}
+
+int fpd_clear_health(fpd_sim* s) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    const unsigned zero = 0;
+    const double dz = 0.0;
+    HIP_TRY(hipMemcpy(&s->bs->health, &zero, sizeof zero, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&s->bs->max_strain, &dz, sizeof dz, hipMemcpyHostToDevice));
+    return FPD_OK;
+}
+
+int fpd_step_count(fpd_sim* s, int64_t* steps) {
+    if (!s || !steps) return fail(FPD_EINVAL, "NULL argument");
+    *steps = s->steps;
+    return FPD_OK;
+}
+
+int fpd_read_fields(fpd_sim* s, double* rho, double* ux, double* uy, double* eta) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    const size_t S = (size_t)s->p.nx * s->p.ny;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, 4 * S * sizeof(double)));
+    const StepArgs a = make_args(s, s->cur);
+    hipError_t e = launch_fields(s->p.storage, a, d, d + S, d + 2 * S, d + 3 * S, s->stream);
+    double* outs[4] = {rho, ux, uy, eta};
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        if (outs[i])
+            e = hipMemcpyAsync(outs[i], d + i * S, S * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "read_fields: %s", hipGetErrorString(e));
+    return FPD_OK;
+}
+
+int fpd_read_populations(fpd_sim* s, double* f) {
+    if (!s || !f) return fail(FPD_EINVAL, "NULL argument");
+    const size_t n = (size_t)9 * s->p.nx * s->p.ny;
+    double* d = nullptr;
+    HIP_TRY(hipMalloc(&d, n * sizeof(double)));
+    hipError_t e = launch_stream_out(s->p.storage, s->L, s->p.u_wall, s->buf[s->cur], d, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "read_populations: %s", hipGetErrorString(e));
+    return FPD_OK;
+}
+
+int fpd_write_populations(fpd_sim* s, const double* f) {
+    if (!s || !f) return fail(FPD_EINVAL, "NULL argument");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    return upload_populations(s, f);
+}
+
+int fpd_read_beads(fpd_sim* s, double* R, double* V, double* F) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    const int N = s->p.n_beads;
+    if (N == 0) return FPD_OK;
+    int rc = sync_check(s);
+    if (rc) return rc;
+    std::vector<double> h(2 * (size_t)kMaxBeads * 3);
+    HIP_TRY(hipMemcpy(h.data(), s->bs->R, sizeof(double) * 2 * kMaxBeads * 3,
+                      hipMemcpyDeviceToHost));
+    for (int i = 0; i < N; ++i)
+        for (int c = 0; c < 2; ++c) {
+            if (R) R[2 * i + c] = h[2 * i + c];
+            if (V) V[2 * i + c] = h[2 * kMaxBeads + 2 * i + c];
+            if (F) F[2 * i + c] = h[4 * kMaxBeads + 2 * i + c];
+        }
+    return FPD_OK;
+}
+
+int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
+    if (!s || !c) return fail(FPD_EINVAL, "NULL argument");
+    fpd_launch n = s->launch;
+    if (c->block_x > 0) n.block_x = c->block_x;
+    if (c->block_y > 0) n.block_y = c->block_y;
+    if (c->rows_per_thread > 0) n.rows_per_thread = c->rows_per_thread;
+    if (c->xcd_remap > 0) n.xcd_remap = c->xcd_remap;
+    if (c->graph_chunk > 0) n.graph_chunk = c->graph_chunk;
+    if (n.block_x != 64 && n.block_x != 128 && n.block_x != 256)
+        return fail(FPD_EINVAL, "block_x must be 64, 128 or 256");
+    if (n.block_y != 1 && n.block_y != 2 && n.block_y != 4)
+        return fail(FPD_EINVAL, "block_y must be 1, 2 or 4");
+    if (n.block_x * n.block_y > 256) return fail(FPD_EINVAL, "at most 256 threads per block");
+    if (n.rows_per_thread != 1 && n.rows_per_thread != 2 && n.rows_per_thread != 4)
+        return fail(FPD_EINVAL, "rows_per_thread must be 1, 2 or 4");
+    if (n.graph_chunk < 2 || (n.graph_chunk & 1))
+        return fail(FPD_EINVAL, "graph_chunk must be even and >= 2");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    s->launch = n;
+    drop_graphs(s);
+    return FPD_OK;
+}
+
+int fpd_set_flags(fpd_sim* s, uint32_t flags) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    const uint32_t keep = s->p.flags & FPD_FLAG_CLAMP_PHI;
+    s->p.flags = keep | (flags & (FPD_FLAG_NO_GRAPH | FPD_FLAG_TIME_KERNELS));
+    drop_graphs(s);
+    return FPD_OK;
+}
+
+int fpd_get_launch(fpd_sim* s, fpd_launch* c) {
+    if (!s || !c) return fail(FPD_EINVAL, "NULL argument");
+    *c = s->launch;
+    return FPD_OK;
+}
+
+int fpd_kernel_times(fpd_sim* s, double* ms_lattice, int64_t* n_lattice, double* ms_bead,
+                     int64_t* n_bead) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    if (ms_lattice) *ms_lattice = s->ms_lat;
+    if (n_lattice) *n_lattice = s->n_lat;
+    if (ms_bead) *ms_bead = s->ms_bead;
+    if (n_bead) *n_bead = s->n_bead;
+    return FPD_OK;
+}
+
+int fpd_reset_kernel_times(fpd_sim* s) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    s->ms_lat = s->ms_bead = 0.0;
+    s->n_lat = s->n_bead = 0;
+    return FPD_OK;
+}
+
+int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) {
+    if (bytes == 0 || (bytes & 15) || iters < 1 || !gbps)
+        return fail(FPD_EINVAL, "bytes must be a positive multiple of 16, iters >= 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return fail(FPD_ENOMEM, "copy probe allocation");
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipFree(a);
+        return fail(FPD_ENOMEM, "copy probe allocation");
+    }
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, st);
+    if (e == hipSuccess) e = launch_copy(a, b, bytes, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < iters && e == hipSuccess; ++i) e = launch_copy(a, b, bytes, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "copy probe: %s", hipGetErrorString(e));
+    *gbps = 2.0 * (double)bytes * iters / (ms * 1e-3) / 1e9;
+    return FPD_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint -------
+
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '1'};
+
+int fpd_save(fpd_sim* s, const char* path) {
+    if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    std::vector<char> pops(s->buf_bytes);
+    BeadState h;
+    HIP_TRY(hipMemcpy(pops.data(), s->buf[s->cur], s->buf_bytes, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&h, s->bs, sizeof h, hipMemcpyDeviceToHost));
+    FILE* fp = fopen(path, "wb");
+    if (!fp) return fail(FPD_EINVAL, "cannot open %s for writing", path);
+    const uint8_t fib = s->fiber ? 1 : 0;
+    bool ok = fwrite(kMagic, 1, 8, fp) == 8 && fwrite(&s->p, sizeof s->p, 1, fp) == 1 &&
+              fwrite(&s->steps, sizeof s->steps, 1, fp) == 1 && fwrite(&fib, 1, 1, fp) == 1 &&
+              fwrite(&s->buf_bytes, sizeof s->buf_bytes, 1, fp) == 1 &&
+              fwrite(pops.data(), 1, pops.size(), fp) == pops.size() &&
+              fwrite(&h, sizeof h, 1, fp) == 1;
+    ok = (fclose(fp) == 0) && ok;
+    if (!ok) return fail(FPD_EDEVICE, "write to %s failed", path);
+    return FPD_OK;
+}
+
+int fpd_load(fpd_sim* s, const char* path) {
+    if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    FILE* fp = fopen(path, "rb");
+    if (!fp) return fail(FPD_EINVAL, "cannot open %s", path);
+    char magic[8];
+    fpd_params p;
+    int64_t steps = 0;
+    uint8_t fib = 0;
+    size_t bytes = 0;
+    bool ok = fread(magic, 1, 8, fp) == 8 && memcmp(magic, kMagic, 8) == 0 &&
+              fread(&p, sizeof p, 1, fp) == 1 && fread(&steps, sizeof steps, 1, fp) == 1 &&
+              fread(&fib, 1, 1, fp) == 1 && fread(&bytes, sizeof bytes, 1, fp) == 1;
+    if (!ok || bytes != s->buf_bytes || !params_equal(p, s->p)) {
+        fclose(fp);
+        return fail(FPD_EINVAL, "%s does not match this simulation", path);
+    }
+    std::vector<char> pops(bytes);
+    BeadState h;
+    ok = fread(pops.data(), 1, bytes, fp) == bytes && fread(&h, sizeof h, 1, fp) == 1;
+    fclose(fp);
+    if (!ok) return fail(FPD_EINVAL, "%s is truncated", path);
+    HIP_TRY(hipMemcpy(s->buf[s->cur], pops.data(), bytes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->bs, &h, sizeof h, hipMemcpyHostToDevice));
+    s->steps = steps;
+    s->fiber = fib != 0;
+    return FPD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+"""The C-ABI library loads on a machine without a GPU and exports every symbol that
+include/fpdlbm.h declares; host-only entry points behave (no device work here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fpdlbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpd_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2212_14153_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_expected_entry_points():
+    names = declared_functions()
+    for must in ("fpd_create", "fpd_step", "fpd_read_fields", "fpd_read_beads",
+                 "fpd_init_fiber", "fpd_read_populations", "fpd_destroy", "fpd_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2212_14153_amd import _lib
+    bound = {name for name, _, _ in _lib.SIGNATURES}
+    assert set(declared_functions()) == bound
+
+
+def test_params_struct_layout_matches_header():
+    """The ctypes mirror has the field order of the C struct (checked by name)."""
+    from paper_2212_14153_amd import _lib
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct fpd_params {"):text.index("} fpd_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b([a-z_0-9]+)\s*[,;]", body)
+    assert fields == [n for n, _ in _lib.fpd_params._fields_]
+
+
+def test_params_default_and_physical_mapping(L):
+    from paper_2212_14153_amd import _lib
+    import workloads
+    p = _lib.fpd_params_default()
+    assert p.s_e == 1.64 and p.s_eps == 1.54 and p.storage == _lib.FPD_F32
+    q = _lib.fpd_params_from_physical(5.0, 320 / 2048, 3.3, 40, 4.0, 50.0, 1.0, 0.01, 4)
+    assert (q.nx, q.ny) == (8192, 2048)
+    w = workloads.c3_large("f32")
+    assert q.nu_f == pytest.approx(w.nu_f, rel=1e-12)
+    assert q.k_b == pytest.approx(w.k_b, rel=1e-12)
+    assert q.k_s == pytest.approx(w.k_s, rel=1e-12)
+
+
+def test_invalid_parameters_are_rejected_without_a_device(L):
+    from paper_2212_14153_amd import _lib
+    with pytest.raises(_lib.FpdError) as e:
+        _lib.fpd_params_from_physical(-1.0, 0.2, 1.0, 5, 2.0, 50, 1, 0.01, 2)
+    assert e.value.code == _lib.FPD_EINVAL
+    p = _lib.fpd_params_default()
+    p.nu_f = 0.0
+    h = ctypes.c_void_p()
+    assert L.fpd_create(ctypes.byref(p), None, ctypes.byref(h)) == _lib.FPD_EINVAL
+    assert b"tau_f" in L.fpd_last_error()
+
+
+def test_population_bytes(L):
+    from paper_2212_14153_amd import _lib
+    p = _lib.fpd_params_default()
+    p.nx, p.ny, p.storage = 100, 7, _lib.FPD_F16DEV
+    assert _lib.fpd_population_bytes(p) == 9 * 7 * 128 * 2

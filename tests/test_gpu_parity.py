@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances:
+  * FPD_F64: populations and bead positions agree to round-off (1e-12 relative after 100
+    steps, 1e-10 lu for beads after 1000 steps); differences come only from summation
+    order and FMA contraction.
+  * FPD_F32: populations within 1e-5 relative after 100 steps and bead positions within
+    1e-4 lattice units after 1000 steps (the accuracy the FP32 path is held to).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2212_14153_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+
+def orc_params(w):
+    return oracle.OracleParams.from_mapping(w.params())
+
+
+def gpu_sim(w, storage, **over):
+    return _lib.simulation_from_workload(w, storage=storage, **over)
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def print_case(name, w, storage):
+    print(f"[case] {name} {w.nx}x{w.ny} N={w.n_beads} storage={storage}", flush=True)
+
+
+def small_fiber(nx, ny, n, seed, storage="f64", theta=None, l0=3.0, a=1.5):
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0, math.pi) if theta is None else theta
+    reach = 0.5 * (n - 1) * l0 * abs(math.sin(th)) + a + 1.0 + 0.5
+    cy = rng.uniform(reach, ny - reach) if ny > 2 * reach else ny / 2
+    return workloads.Workload(
+        name=f"rand{seed}", nx=nx, ny=ny, u_wall=0.02, nu_f=0.05, eta_ratio=20.0, xi=0.8,
+        n_beads=n, radius=a, l0=l0, k_s=0.05 * l0 * l0, k_b=2e-3, theta0=th,
+        cx=rng.uniform(0, nx), cy=cy, steps=0, storage=storage)
+
+
+# ------------------------------------------------------------------ state and I/O ---
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-16), ("f32", 1e-7)])
+def test_initial_populations_match_oracle(storage, tol):
+    w = workloads.c1_small_fp64().with_(n_beads=0)
+    print_case("init", w, storage)
+    with gpu_sim(w, storage) as sim:
+        f = sim.populations()
+    ref = oracle.init(orc_params(w), 1)
+    assert np.max(np.abs(f - ref)) <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 0.0), ("f32", 1e-8), ("f16dev", 1e-6),
+                                         ("bf16dev", 2e-4)])
+def test_write_read_roundtrip(storage, tol):
+    w = workloads.c1_small_fp64().with_(nx=37, ny=11, n_beads=0)
+    print_case("roundtrip", w, storage)
+    f = oracle.init(orc_params(w), 1) + workloads.perturbation((9, 11, 37), 1e-3, seed=5)
+    with gpu_sim(w, storage) as sim:
+        sim.write_populations(f)
+        g = sim.populations()
+    assert np.max(np.abs(g - f)) <= tol
+
+
+# -------------------------------------------------------------- lattice-only steps ---
+
+@pytest.mark.parametrize("nx,ny", [(64, 32), (67, 13), (130, 7), (5, 3), (1, 4), (9, 1)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_lattice_steps_without_fiber(nx, ny, storage):
+    w = workloads.c1_small_fp64().with_(nx=nx, ny=ny, n_beads=0, u_wall=0.03, nu_f=0.02)
+    print_case("lattice", w, storage)
+    p = orc_params(w)
+    f0 = oracle.init(p, 1) + workloads.perturbation((9, ny, nx), 2e-3, seed=nx * 100 + ny)
+    st = oracle.make_state(p, 1)
+    st.f[:] = f0
+    oracle.run(st, 100)
+    with gpu_sim(w, storage) as sim:
+        sim.write_populations(f0)
+        sim.step(100)
+        sim.sync()
+        f = sim.populations()
+    tol = 1e-12 if storage == "f64" else 1e-5
+    assert rel_err(f, st.f) <= tol
+
+
+# --------------------------------------------------------------- coupled fiber step ---
+
+def run_both(w, storage, steps, record=None):
+    p = orc_params(w)
+    st = oracle.make_state(p, w.init_flow, w.beads())
+    traj = oracle.run(st, steps, trajectory=record is not None)
+    with gpu_sim(w, storage) as sim:
+        sim.step(steps)
+        sim.sync()
+        f = sim.populations()
+        R, V, F = sim.beads()
+    return st, traj, f, R, V, F
+
+
+def test_c1_fp64_populations_after_100_steps():
+    w = workloads.c1_small_fp64()
+    print_case("c1-100", w, "f64")
+    st, _, f, R, V, F = run_both(w, "f64", 100)
+    assert rel_err(f, st.f) <= 1e-12
+    assert np.max(np.abs(R - st.R)) <= 1e-12
+    assert np.max(np.abs(V - st.V)) <= 1e-14
+    assert np.allclose(F, oracle.bead_forces(orc_params(w), st.R), rtol=1e-9, atol=1e-16)
+
+
+def test_c1_fp64_beads_after_1000_steps():
+    w = workloads.c1_small_fp64()
+    print_case("c1-1000", w, "f64")
+    st, _, f, R, V, F = run_both(w, "f64", 1000)
+    assert np.max(np.abs(R - st.R)) <= 1e-10
+    assert rel_err(f, st.f) <= 1e-10
+
+
+def test_c1_fp32_populations_after_100_steps():
+    w = workloads.c1_small_fp64()
+    print_case("c1-100", w, "f32")
+    st, _, f, R, V, F = run_both(w, "f32", 100)
+    assert rel_err(f, st.f) <= 1e-5
+
+
+def test_c1_fp32_beads_after_1000_steps():
+    w = workloads.c1_small_fp64()
+    print_case("c1-1000", w, "f32")
+    st, _, f, R, V, F = run_both(w, "f32", 1000)
+    assert np.max(np.abs(R - st.R)) <= 1e-4
+
+
+@pytest.mark.parametrize("nx,ny,n,seed", [(67, 29, 3, 1), (130, 40, 6, 2), (48, 23, 1, 3),
+                                          (40, 31, 2, 4), (200, 45, 9, 5)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_ragged_lattices_with_fiber(nx, ny, n, seed, storage, tol):
+    w = small_fiber(nx, ny, n, seed, storage)
+    print_case(f"ragged-seed{seed}", w, storage)
+    st, _, f, R, V, F = run_both(w, storage, 60)
+    assert rel_err(f, st.f) <= tol
+    assert np.max(np.abs(R - st.R)) <= (1e-11 if storage == "f64" else 1e-6)
+
+
+def test_fiber_straddling_the_periodic_boundary():
+    w = small_fiber(96, 40, 5, 7, "f64", theta=0.2).with_(cx=1.0)
+    print_case("wrap", w, "f64")
+    st, _, f, R, V, F = run_both(w, "f64", 80)
+    assert rel_err(f, st.f) <= 1e-11
+    assert np.max(np.abs(R - st.R)) <= 1e-11
+
+
+def test_fields_match_oracle():
+    w = workloads.c1_small_fp64()
+    print_case("fields", w, "f64")
+    p = orc_params(w)
+    st = oracle.make_state(p, 1, w.beads())
+    oracle.run(st, 50)
+    rho_o, ux_o, uy_o, eta_o = oracle.macro(p, st.f, st.R)
+    with gpu_sim(w, "f64") as sim:
+        sim.step(50)
+        rho, ux, uy, eta = sim.fields()
+    assert np.max(np.abs(rho - rho_o)) <= 1e-13
+    assert np.max(np.abs(ux - ux_o)) <= 1e-13
+    assert np.max(np.abs(uy - uy_o)) <= 1e-13
+    assert np.max(np.abs(eta - eta_o) / eta_o) <= 1e-12
+
+
+# ------------------------------------------------------------ launch and replay paths ---
+
+LAUNCHES = [
+    dict(block_x=64, block_y=4, rows_per_thread=1, xcd_remap=1),
+    dict(block_x=128, block_y=2, rows_per_thread=2, xcd_remap=2),
+    dict(block_x=256, block_y=1, rows_per_thread=4, xcd_remap=1),
+    dict(block_x=64, block_y=1, rows_per_thread=2, xcd_remap=2),
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_launch_shapes_and_graph_replay_are_bitwise_identical(storage):
+    w = small_fiber(150, 37, 6, 11, storage)
+    print_case("launch-shapes", w, storage)
+    outs = []
+    for i, cfg in enumerate(LAUNCHES):
+        for flags in (0, _lib.FPD_FLAG_NO_GRAPH):
+            with gpu_sim(w, storage, flags=flags) as sim:
+                sim.set_launch(dict(cfg, graph_chunk=8))
+                sim.step(3)        # direct launches
+                sim.step(16)       # two graph replays unless NO_GRAPH
+                sim.step(5)
+                sim.sync()
+                outs.append((sim.populations(), sim.beads()[0]))
+    for f, R in outs[1:]:
+        assert np.array_equal(f, outs[0][0])
+        assert np.array_equal(R, outs[0][1])
+
+
+def test_timed_path_matches_untimed():
+    w = workloads.c1_small_fp64()
+    print_case("timed", w, "f32")
+    with gpu_sim(w, "f32", flags=_lib.FPD_FLAG_TIME_KERNELS) as a, gpu_sim(w, "f32") as b:
+        a.step(40)
+        b.step(40)
+        assert np.array_equal(a.populations(), b.populations())
+        ms_l, n_l, ms_b, n_b = a.kernel_times()
+        assert n_l == 40 and n_b == 40 and ms_l > 0 and ms_b > 0
+
+
+def test_repeat_runs_are_deterministic():
+    w = small_fiber(120, 44, 8, 13, "f64")
+    print_case("determinism", w, "f64")
+    res = []
+    for _ in range(2):
+        with gpu_sim(w, "f64") as sim:
+            sim.step(70)
+            res.append((sim.populations(), sim.beads()))
+    assert np.array_equal(res[0][0], res[1][0])
+    for a, b in zip(res[0][1], res[1][1]):
+        assert np.array_equal(a, b)
+
+
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    w = workloads.c1_small_fp64()
+    print_case("checkpoint", w, "f32")
+    path = str(tmp_path / "c1.fpd")
+    with gpu_sim(w, "f32") as a:
+        a.step(200)
+        fa, Ra = a.populations(), a.beads()[0]
+    with gpu_sim(w, "f32") as b:
+        b.step(100)
+        b.save(path)
+    with gpu_sim(w, "f32") as c:
+        c.load(path)
+        assert c.steps == 100
+        c.step(100)
+        assert np.array_equal(c.populations(), fa)
+        assert np.array_equal(c.beads()[0], Ra)
+
+
+def test_zero_steps_is_a_no_op():
+    w = workloads.c1_small_fp64()
+    with gpu_sim(w, "f64") as sim:
+        f0 = sim.populations()
+        sim.step(0)
+        assert np.array_equal(sim.populations(), f0)
+        assert sim.steps == 0
+
+
+# ------------------------------------------------------------------- health ---------
+
+def test_nan_populations_raise_unstable_and_stay_local():
+    w = workloads.c1_small_fp64()
+    print_case("health", w, "f32")
+    with gpu_sim(w, "f32") as bad, gpu_sim(w, "f32") as good:
+        f = bad.populations()
+        f[:, 14:18, 30:34] = np.nan
+        bad.write_populations(f)
+        bad.step(5)
+        good.step(5)
+        with pytest.raises(_lib.FpdError) as e:
+            bad.sync()
+        assert e.value.code == _lib.FPD_EUNSTABLE
+        good.sync()
+        flags, strain = bad.health()
+        assert flags & _lib.FPD_HEALTH_NAN
+
+
+def test_invalid_fiber_is_rejected():
+    w = workloads.c1_small_fp64()
+    with gpu_sim(w.with_(n_beads=5), "f32") as sim:
+        R = w.beads().copy()
+        R[0, 1] = 0.5          # inside the wall layer
+        with pytest.raises(_lib.FpdError) as e:
+            sim.init_fiber(R)
+        assert e.value.code == _lib.FPD_EINVAL
