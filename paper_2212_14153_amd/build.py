@@ -18,6 +18,9 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off: scalar and float2 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FMA only where one source expression is a*b+c: rounding then does not depend on
+    # how a template instance is unrolled or scheduled (bitwise-stable launch shapes)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -136,13 +136,14 @@ template <> struct PhiEval<double> {
         return phi_f64(sqrt(r2), a, xi);
     }
 };
+// The cutoff test stays in FP64 in both variants: it is the same predicate as the
+// support boxes, so whether a node sees a bead never depends on the tiling.
 template <> struct PhiEval<float> {
     __device__ static inline float eval(double dx, double dy, double rc2, double a, double,
                                         double inv_xi) {
-        const float fx = (float)dx, fy = (float)dy;
-        const float r2 = fx * fx + fy * fy;
-        if (r2 >= (float)rc2) return 0.0f;
-        return phi_f32(sqrtf(r2), (float)a, (float)inv_xi);
+        const double r2 = dx * dx + dy * dy;
+        if (r2 >= rc2) return 0.0f;
+        return phi_f32(sqrtf((float)r2), (float)a, (float)inv_xi);
     }
 };
 

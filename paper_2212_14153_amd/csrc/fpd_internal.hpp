@@ -9,20 +9,25 @@
 namespace fpd {
 
 constexpr int kMaxBeads = FPD_MAX_BEADS;
-constexpr int kBeadThreads = 256;
+constexpr int kBeadThreads = 256;   // finish kernel (one thread per bead)
+constexpr int kBeadBlock = 1024;    // bead kernel (one block per bead)
 
 // Device-resident fiber state, float64 (bead integration and reductions stay in FP64
 // whatever the population storage).
 struct BeadState {
     double R[kMaxBeads][2];   // positions R_i^n
     double V[kMaxBeads][2];   // V_i^n, velocity of the last step
-    double F[kMaxBeads][2];   // F_i^n, Eqs. (10)-(12)
+    double F[kMaxBeads][2];   // F_i^n, Eqs. (10)-(12) (written by the owner tile)
     double C[kMaxBeads][2];   // F_i^n / A_i^n, the coefficients of Eq. (4)
     double A[kMaxBeads];      // A_i^n = sum_x phi_i^n(x)
-    int rect[4];              // support window of phi^n: x0 (mod nx), y0, width, height
-    unsigned int health;      // FPD_HEALTH_* bits, sticky
-    unsigned int done;        // blocks of the bead kernel that have finished this launch
-    double max_strain;        // largest |L - l0| / l0 seen
+    // Support window of phi as raw bounds (lo, hi) of node columns (unwrapped) and
+    // (j0, j1) of rows, one slot per buffer parity: the bead kernel of a step fills the
+    // slot the next step reads with atomic min / max, so the result does not depend on the
+    // order in which beads finish.
+    int win[2][4];
+    unsigned int health;                 // FPD_HEALTH_* bits, sticky (atomic or)
+    unsigned int reserved;
+    unsigned long long max_strain_bits;  // bits of the largest |L - l0| / l0 (atomic max)
 };
 
 struct Lattice {
@@ -45,6 +50,7 @@ struct Fiber {
 };
 
 struct StepArgs {
+    int parity;               // index of the source buffer: the window slot of step n
     const void* src;          // post-collision populations of step n-1
     void* dst;                // post-collision populations of step n
     Lattice L;
@@ -60,7 +66,9 @@ struct StepArgs {
 // Kernel launchers (fpd_kernels.hip).
 hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
                        hipStream_t st);
-hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, hipStream_t st);
+hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
+                       hipStream_t st);
+hipError_t launch_forces(const StepArgs& a, hipStream_t st);
 hipError_t launch_unstream(int storage, const Lattice& L, double u_wall, const double* f64,
                            void* dst, hipStream_t st);
 hipError_t launch_stream_out(int storage, const Lattice& L, double u_wall, const void* src,

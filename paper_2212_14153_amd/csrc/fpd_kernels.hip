@@ -4,12 +4,13 @@
 // One step is two launches:
 //   step_kernel  every node: pull-stream, MRT collision with the local shear rate from
 //                eta^n (Eq. 1) and Guo forcing with f^n (Eq. 4), store.  Tiles that meet
-//                the fiber's support window evaluate phi_i (Eq. 2) from an LDS bead list
-//                and record f^n there for the bead kernel.
+//                the fiber's support window stage the nearby beads in LDS with their forces
+//                F_i^n (Eqs. 10-12, O(N) work), evaluate phi_i (Eq. 2) per node and record
+//                f^n in the window for the bead kernel.
 //   bead_kernel  one block per bead: V_i^{n+1} from Eq. (5) over the bead's support box
-//                (FP64 accumulation), R_i^{n+1} = R_i^n + V_i^{n+1}, then A_i^{n+1} at the
-//                new position; the last block to finish computes F^{n+1} (Eqs. 10-12),
-//                F/A, the next support window and the health bits.
+//                (FP64 accumulation), R_i^{n+1} = R_i^n + V_i^{n+1}, A_i^{n+1} at the new
+//                position, and the bead's share of the next support window and health bits
+//                (integer atomic min / max / or: order-independent).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -39,131 +40,7 @@ __device__ inline double block_sum(double v, double* scratch) {
     return s;
 }
 
-// ------------------------------------------------- bead list for a tile (LDS) ------
-// Ordered compaction of the beads whose support box meets the tile's columns
-// [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
-// beads run in the same order as in a full loop.
-__device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, int cw, int ry0,
-                                   int rh, double (*sR)[2], double (*sC)[2], int* s_wave) {
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int nthreads = blockDim.x * blockDim.y;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
-    int total = 0;
-    for (int base = 0; base < fib.n; base += nthreads) {
-        const int b = base + tid;
-        bool hit = false;
-        double Rx = 0.0, Ry = 0.0;
-        if (b < fib.n) {
-            Rx = fib.bs->R[b][0];
-            Ry = fib.bs->R[b][1];
-            int i0, w, j0, j1;
-            bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
-            hit = (j0 <= j1) && (j0 <= ry0 + rh - 1) && (j1 >= ry0) &&
-                  cols_overlap(cx0, cw, i0, w, nx);
-        }
-        const unsigned long long m = __ballot(hit);
-        const int before = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wave[wave] = __popcll(m);
-        __syncthreads();
-        int off = total, chunk = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            if (w < wave) off += s_wave[w];
-            chunk += s_wave[w];
-        }
-        if (hit) {
-            sR[off + before][0] = Rx;
-            sR[off + before][1] = Ry;
-            sC[off + before][0] = fib.bs->C[b][0];
-            sC[off + before][1] = fib.bs->C[b][1];
-        }
-        total += chunk;
-        __syncthreads();
-    }
-    return total;
-}
-
-// ------------------------------------------------------------- fused lattice step ---
-
-template <int ST, int SPT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
-    using Cd = Codec<ST>;
-    using T = typename Cd::T;
-    using S = typename Cd::store_t;
-    __shared__ double sR[kMaxBeads][2];
-    __shared__ double sC[kMaxBeads][2];
-    __shared__ int s_wave[16];
-
-    const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int bx = blockDim.x;
-    const int x = tx * bx + threadIdx.x;
-    const int ytile = ty * a.rows_per_block;
-    const int ybase = ytile + threadIdx.y * SPT;
-    const int nx = a.L.nx, ny = a.L.ny, stride = a.L.stride;
-    const long long plane = a.L.plane;
-    const S* __restrict__ src = (const S*)a.src;
-    S* __restrict__ dst = (S*)a.dst;
-    const T u6 = (T)a.u6;
-    const T s_e = (T)a.s_e, s_eps = (T)a.s_eps;
-
-    // Block-uniform: does this tile meet the fiber's support window?
-    int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
-    bool fiber_tile = false;
-    if (a.fib.n > 0) {
-        const int* rect = a.fib.bs->rect;
-        wx0 = rect[0];
-        wy0 = rect[1];
-        ww = rect[2];
-        wh = rect[3];
-        fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
-                     ytile + a.rows_per_block - 1 >= wy0 &&
-                     cols_overlap(tx * bx, bx, wx0, ww, nx);
-        if (fiber_tile)
-            nb = gather_beads(a.fib, nx, ny, tx * bx, bx, ytile, a.rows_per_block, sR, sC,
-                              s_wave);
-    }
-
-#pragma unroll
-    for (int r = 0; r < SPT; ++r) {
-        const int y = ybase + r;
-        if (x >= nx || y >= ny) continue;
-        T g[9];
-        pull<Cd>(src, nx, ny, stride, plane, x, y, u6, g);
-        T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
-        if (fiber_tile) {
-            // Step (1) at this node: phi_i^n (Eq. 2), eta^n (Eq. 1), f^n (Eq. 4).
-            const double xc = (double)x + 0.5, yc = (double)y + 0.5;
-            T sphi = T(0);
-            for (int i = 0; i < nb; ++i) {
-                const double dx = min_image(xc - sR[i][0], nx);
-                const double dy = yc - sR[i][1];
-                const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi,
-                                              a.fib.inv_xi);
-                sphi += ph;
-                Fx += ph * (T)sC[i][0];
-                Fy += ph * (T)sC[i][1];
-            }
-            if (a.fib.clamp && sphi > T(1)) sphi = T(1);
-            const T nu_f = (T)a.fib.nu_f;
-            const T eta = nu_f + ((T)a.fib.nu_s - nu_f) * sphi;
-            s_nu = T(1) / (T(3) * eta + T(0.5));
-            s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed
-                                        : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
-            const int wi = imod(x - wx0, nx), wj = y - wy0;
-            if (wi < ww && wj >= 0 && wj < wh) {
-                T* rf = (T*)a.fib.rect_f + 2 * ((long long)wj * a.fib.rect_wmax + wi);
-                rf[0] = Fx;
-                rf[1] = Fy;
-            }
-        }
-        mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
-        S* o = dst + (long long)y * stride + x;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Cd::store(o + k * plane, g[k]);
-    }
-}
-
-// ----------------------------------------------------------------- bead kernel -----
+// ----------------------------------------------------------- bead forces ------------
 
 // Forces of Eqs. (10)-(12) on bead t, gathered bond by bond: the stretching energy
 // k_s/(2 l0^2) (L_m - l0)^2 of bond m = (m, m+1) and the bending energy
@@ -224,105 +101,223 @@ __device__ inline void bead_force(const BeadState* bs, int N, int t, double ks_l
     }
 }
 
-// The block that finishes last: F^{n+1}, F/A, support window, health.
-__device__ void finish_fiber(const StepArgs& a) {
-    const Fiber& fib = a.fib;
+// Window slot (raw bounds) -> x0 (mod nx), width, y0, height; clamped to the reserved
+// window (a clamp means the fiber outgrew it: FPD_HEALTH_SUPPORT is raised by block 0).
+struct Window {
+    int x0, w, y0, h;
+    bool clamped;
+};
+
+__device__ inline Window decode_window(const int* raw, int nx, int ny, int wmax, int hmax) {
+    Window r{0, 0, 0, 0, false};
+    const int lo = raw[0], hi = raw[1], j0 = raw[2], j1 = raw[3];
+    if (lo > hi || j0 > j1) return r;
+    r.w = hi - lo + 1;
+    if (r.w >= nx) {
+        r.w = nx;
+        r.x0 = 0;
+    } else {
+        r.x0 = imod(lo, nx);
+    }
+    r.y0 = j0 < 0 ? 0 : j0;
+    const int y1 = j1 > ny - 1 ? ny - 1 : j1;
+    r.h = y1 >= r.y0 ? y1 - r.y0 + 1 : 0;
+    if (r.w > wmax || r.h > hmax) {
+        r.clamped = true;
+        r.w = min(r.w, wmax);
+        r.h = min(r.h, hmax);
+    }
+    return r;
+}
+
+__device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
+    if (v >= 0.0) atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+// The tile that contains node (floor Rx mod nx, floor Ry) owns bead b: it publishes F_b,
+// C_b and the strain of bond (b, b+1).
+__device__ inline void own_bead(const Fiber& fib, int N, int b, const double F[2], double C0,
+                                double C1) {
     BeadState* bs = fib.bs;
-    const int N = fib.n, nx = a.L.nx, ny = a.L.ny;
-    __shared__ int s_lo[kBeadThreads], s_hi[kBeadThreads], s_j0[kBeadThreads],
-        s_j1[kBeadThreads];
-    __shared__ unsigned s_h[kBeadThreads];
-    __shared__ double s_strain[kBeadThreads];
-    const int tid = threadIdx.x;
-    for (int t = tid; t < kBeadThreads; t += blockDim.x) {
-        s_lo[t] = 0x7fffffff;
-        s_hi[t] = -0x7fffffff;
-        s_j0[t] = 0x7fffffff;
-        s_j1[t] = -0x7fffffff;
-        s_h[t] = 0u;
-        s_strain[t] = 0.0;
-    }
-    __syncthreads();
-    for (int t = tid; t < N; t += blockDim.x) {
-        double F[2];
-        bead_force(bs, N, t, fib.ks_l02, fib.l0, fib.kb, F);
-        const double A = bs->A[t];
-        bs->F[t][0] = F[0];
-        bs->F[t][1] = F[1];
-        bs->C[t][0] = F[0] / A;
-        bs->C[t][1] = F[1] / A;
-        const double Rx = bs->R[t][0], Ry = bs->R[t][1];
-        const double Vx = bs->V[t][0], Vy = bs->V[t][1];
-        unsigned h = 0u;
-        if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) || !isfinite(A))
-            h |= FPD_HEALTH_NAN;
-        if (Vx * Vx + Vy * Vy > 0.09 / 3.0) h |= FPD_HEALTH_MACH;
-        if (Ry - fib.a - fib.xi < 0.0 || Ry + fib.a + fib.xi > (double)ny) h |= FPD_HEALTH_WALL;
-        double strain = 0.0;
-        if (t <= N - 2) {
-            double tt[2], L;
-            bond(bs, t, tt, L);
-            strain = fabs(L - fib.l0) / fib.l0;
-            if (!(strain <= 0.5)) h |= FPD_HEALTH_STRAIN;
-        }
-        s_h[t] = h;
-        s_strain[t] = strain;
-        if (isfinite(Rx) && isfinite(Ry)) {
-            s_lo[t] = (int)floor(Rx - 0.5 - fib.rc);
-            s_hi[t] = (int)ceil(Rx - 0.5 + fib.rc);
-            s_j0[t] = (int)floor(Ry - 0.5 - fib.rc);
-            s_j1[t] = (int)ceil(Ry - 0.5 + fib.rc);
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int lo = 0x7fffffff, hi = -0x7fffffff, j0 = 0x7fffffff, j1 = -0x7fffffff;
-        unsigned h = 0u;
-        double ms = bs->max_strain;
-        for (int t = 0; t < N; ++t) {
-            lo = min(lo, s_lo[t]);
-            hi = max(hi, s_hi[t]);
-            j0 = min(j0, s_j0[t]);
-            j1 = max(j1, s_j1[t]);
-            h |= s_h[t];
-            ms = fmax(ms, s_strain[t]);
-        }
-        int x0 = 0, w = 0, y0 = 0, hgt = 0;
-        if (lo <= hi) {
-            w = hi - lo + 1;
-            if (w >= nx) {
-                w = nx;
-                x0 = 0;
-            } else {
-                x0 = imod(lo, nx);
-            }
-            y0 = j0 < 0 ? 0 : j0;
-            const int y1 = j1 > ny - 1 ? ny - 1 : j1;
-            hgt = y1 >= y0 ? y1 - y0 + 1 : 0;
-        }
-        if (w > fib.rect_wmax || hgt > fib.rect_hmax) {
-            h |= FPD_HEALTH_SUPPORT;
-            w = min(w, fib.rect_wmax);
-            hgt = min(hgt, fib.rect_hmax);
-        }
-        bs->rect[0] = x0;
-        bs->rect[1] = y0;
-        bs->rect[2] = w;
-        bs->rect[3] = hgt;
-        bs->health |= h;
-        bs->max_strain = ms;
-        bs->done = 0u;
+    bs->F[b][0] = F[0];
+    bs->F[b][1] = F[1];
+    bs->C[b][0] = C0;
+    bs->C[b][1] = C1;
+    if (b <= N - 2) {
+        double t[2], L;
+        bond(bs, b, t, L);
+        const double strain = fabs(L - fib.l0) / fib.l0;
+        if (!(strain <= 0.5)) atomicOr(&bs->health, FPD_HEALTH_STRAIN);
+        atomic_max_nonneg(&bs->max_strain_bits, strain);
     }
 }
 
-template <int ST>
-__global__ void __launch_bounds__(kBeadThreads) bead_kernel(StepArgs a, int do_velocity) {
+// ------------------------------------------------- bead list for a tile (LDS) ------
+// Ordered compaction of the beads whose support box meets the tile's columns
+// [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
+// beads run in the same order as in a full loop.
+__device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, int cw, int ry0,
+                                   int rh, double (*sR)[2], double (*sC)[2], int* s_wave) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
+    const BeadState* bs = fib.bs;
+    int total = 0;
+    for (int base = 0; base < fib.n; base += nthreads) {
+        const int b = base + tid;
+        bool hit = false;
+        double Rx = 0.0, Ry = 0.0;
+        if (b < fib.n) {
+            Rx = bs->R[b][0];
+            Ry = bs->R[b][1];
+            int i0, w, j0, j1;
+            bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+            hit = (j0 <= j1) && (j0 <= ry0 + rh - 1) && (j1 >= ry0) &&
+                  cols_overlap(cx0, cw, i0, w, nx);
+        }
+        const unsigned long long m = __ballot(hit);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wave] = __popcll(m);
+        __syncthreads();
+        int off = total, chunk = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            if (w < wave) off += s_wave[w];
+            chunk += s_wave[w];
+        }
+        if (hit) {
+            // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
+            double F[2];
+            bead_force(bs, fib.n, b, fib.ks_l02, fib.l0, fib.kb, F);
+            const double A = bs->A[b];
+            const double C0 = F[0] / A, C1 = F[1] / A;
+            sR[off + before][0] = Rx;
+            sR[off + before][1] = Ry;
+            sC[off + before][0] = C0;
+            sC[off + before][1] = C1;
+            const int ox = imod((int)floor(Rx), nx), oy = (int)floor(Ry);
+            if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
+                own_bead(fib, fib.n, b, F, C0, C1);
+        }
+        total += chunk;
+        __syncthreads();
+    }
+    return total;
+}
+
+// ------------------------------------------------------------- fused lattice step ---
+
+template <int ST, int SPT>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     using Cd = Codec<ST>;
     using T = typename Cd::T;
     using S = typename Cd::store_t;
-    __shared__ double scratch[kBeadThreads / 64];
+    __shared__ double sR[kMaxBeads][2];
+    __shared__ double sC[kMaxBeads][2];
+    __shared__ int s_wave[16];
+
+    const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int bx = blockDim.x;
+    const int x = tx * bx + threadIdx.x;
+    const int ytile = ty * a.rows_per_block;
+    const int ybase = ytile + threadIdx.y * SPT;
+    const int nx = a.L.nx, ny = a.L.ny, stride = a.L.stride;
+    const long long plane = a.L.plane;
+    const S* __restrict__ src = (const S*)a.src;
+    S* __restrict__ dst = (S*)a.dst;
+    const T u6 = (T)a.u6;
+    const T s_e = (T)a.s_e, s_eps = (T)a.s_eps;
+
+    // Block-uniform: does this tile meet the fiber's support window?
+    int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
+    bool fiber_tile = false;
+    if (a.fib.n > 0) {
+        BeadState* bs = a.fib.bs;
+        const Window win = decode_window(bs->win[a.parity], nx, ny, a.fib.rect_wmax,
+                                         a.fib.rect_hmax);
+        wx0 = win.x0;
+        wy0 = win.y0;
+        ww = win.w;
+        wh = win.h;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+            // the bead kernel of this step fills the other slot from scratch
+            int* nxt = bs->win[1 - a.parity];
+            nxt[0] = 0x7fffffff;
+            nxt[1] = -0x7fffffff;
+            nxt[2] = 0x7fffffff;
+            nxt[3] = -0x7fffffff;
+            if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
+        }
+        fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
+                     ytile + a.rows_per_block - 1 >= wy0 &&
+                     cols_overlap(tx * bx, bx, wx0, ww, nx);
+        if (fiber_tile)
+            nb = gather_beads(a.fib, nx, ny, tx * bx, bx, ytile, a.rows_per_block, sR, sC,
+                              s_wave);
+    }
+
+#pragma unroll
+    for (int r = 0; r < SPT; ++r) {
+        const int y = ybase + r;
+        if (x >= nx || y >= ny) continue;
+        T g[9];
+        pull<Cd>(src, nx, ny, stride, plane, x, y, u6, g);
+        T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
+        if (fiber_tile) {
+            // Step (1) at this node: phi_i^n (Eq. 2), eta^n (Eq. 1), f^n (Eq. 4).
+            const double xc = (double)x + 0.5, yc = (double)y + 0.5;
+            T sphi = T(0);
+            for (int i = 0; i < nb; ++i) {
+                const double dx = min_image(xc - sR[i][0], nx);
+                const double dy = yc - sR[i][1];
+                const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi,
+                                              a.fib.inv_xi);
+                sphi += ph;
+                Fx += ph * (T)sC[i][0];
+                Fy += ph * (T)sC[i][1];
+            }
+            if (a.fib.clamp && sphi > T(1)) sphi = T(1);
+            if (sphi > T(0)) {  // else the fluid rates, exactly as on the other tiles
+                const T nu_f = (T)a.fib.nu_f;
+                const T eta = nu_f + ((T)a.fib.nu_s - nu_f) * sphi;
+                s_nu = T(1) / (T(3) * eta + T(0.5));
+                s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed
+                                            : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
+            }
+            const int wi = imod(x - wx0, nx), wj = y - wy0;
+            if (wi < ww && wj >= 0 && wj < wh) {
+                T* rf = (T*)a.fib.rect_f + 2 * ((long long)wj * a.fib.rect_wmax + wi);
+                rf[0] = Fx;
+                rf[1] = Fy;
+            }
+        }
+        mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
+        S* o = dst + (long long)y * stride + x;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Cd::store(o + k * plane, g[k]);
+    }
+}
+
+// ----------------------------------------------------------------- bead kernel -----
+
+// phi of one bead at a node in the arithmetic of the storage (FP64 for FPD_F64, FP32
+// otherwise); the cutoff test is the FP64 predicate shared with the support boxes.
+template <typename T>
+__device__ inline double bead_phi(const Fiber& fib, double dx, double dy) {
+    return (double)PhiEval<T>::eval(dx, dy, fib.rc2, fib.a, fib.xi, fib.inv_xi);
+}
+
+// One block per bead.  With do_velocity: V_i^{n+1} = sum_x phi_i^n (j^{n+1} + f^n / 2) /
+// rho^{n+1} / A_i^n over the bead's support box (Eq. 5, FP64 sums), then the Euler update
+// R_i^{n+1} = R_i^n + V_i^{n+1}.  Always: A_i = sum_x phi_i at the (new) position.
+template <int ST>
+__global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_velocity,
+                                                          int win_out) {
+    using Cd = Codec<ST>;
+    using T = typename Cd::T;
+    using S = typename Cd::store_t;
+    __shared__ double scratch[kBeadBlock / 64];
     __shared__ double s_R[2];
-    __shared__ int s_last;
     const Fiber& fib = a.fib;
     BeadState* bs = fib.bs;
     const int b = blockIdx.x, tid = threadIdx.x;
@@ -330,12 +325,13 @@ __global__ void __launch_bounds__(kBeadThreads) bead_kernel(StepArgs a, int do_v
     double Rx = bs->R[b][0], Ry = bs->R[b][1];
 
     if (do_velocity) {
-        // Eq. (5): V_i^{n+1} = sum_x phi_i^n (j^{n+1} + f^n / 2) / rho^{n+1} / A_i^n.
         int i0, w, j0, j1;
         bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
         const int rows = j1 - j0 + 1;
         const int total = rows > 0 ? rows * w : 0;
-        const int wx0 = bs->rect[0], wy0 = bs->rect[1], ww = bs->rect[2], wh = bs->rect[3];
+        const Window win = decode_window(bs->win[a.parity], nx, ny, fib.rect_wmax,
+                                         fib.rect_hmax);
+        const int wx0 = win.x0, wy0 = win.y0, ww = win.w, wh = win.h;
         const T* rf = (const T*)fib.rect_f;
         const S* cur = (const S*)a.dst;
         double sx = 0.0, sy = 0.0;
@@ -345,9 +341,8 @@ __global__ void __launch_bounds__(kBeadThreads) bead_kernel(StepArgs a, int do_v
             if (ii >= nx) ii -= nx;
             const double dx = min_image((double)ii + 0.5 - Rx, nx);
             const double dy = (double)jj + 0.5 - Ry;
-            const double r2 = dx * dx + dy * dy;
-            if (r2 >= fib.rc2) continue;
-            const double ph = phi_f64(sqrt(r2), fib.a, fib.xi);
+            const double ph = bead_phi<T>(fib, dx, dy);
+            if (ph == 0.0) continue;
             T g[9];
             pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii, jj, (T)a.u6, g);
             double drho = 0.0;
@@ -387,33 +382,53 @@ __global__ void __launch_bounds__(kBeadThreads) bead_kernel(StepArgs a, int do_v
         Ry = s_R[1];
     }
 
-    {  // A_i = sum_x phi_i at the (new) position
-        int i0, w, j0, j1;
-        bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
-        const int rows = j1 - j0 + 1;
-        const int total = rows > 0 ? rows * w : 0;
-        double s = 0.0;
-        for (int t = tid; t < total; t += blockDim.x) {
-            const int jj = j0 + t / w;
-            int ii = i0 + t % w;
-            if (ii >= nx) ii -= nx;
-            const double dx = min_image((double)ii + 0.5 - Rx, nx);
-            const double dy = (double)jj + 0.5 - Ry;
-            const double r2 = dx * dx + dy * dy;
-            if (r2 < fib.rc2) s += phi_f64(sqrt(r2), fib.a, fib.xi);
-        }
-        s = block_sum(s, scratch);
-        if (tid == 0) bs->A[b] = s;
+    int i0, w, j0, j1;
+    bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+    const int rows = j1 - j0 + 1;
+    const int total = rows > 0 ? rows * w : 0;
+    double s = 0.0;
+    for (int t = tid; t < total; t += blockDim.x) {
+        const int jj = j0 + t / w;
+        int ii = i0 + t % w;
+        if (ii >= nx) ii -= nx;
+        const double dx = min_image((double)ii + 0.5 - Rx, nx);
+        const double dy = (double)jj + 0.5 - Ry;
+        s += bead_phi<T>(fib, dx, dy);
     }
+    s = block_sum(s, scratch);
+    if (tid == 0) {
+        bs->A[b] = s;
+        // this bead's share of the next support window and its health bits
+        int* nw = bs->win[win_out];
+        if (isfinite(Rx) && isfinite(Ry)) {
+            atomicMin(&nw[0], (int)floor(Rx - 0.5 - fib.rc));
+            atomicMax(&nw[1], (int)ceil(Rx - 0.5 + fib.rc));
+            atomicMin(&nw[2], (int)floor(Ry - 0.5 - fib.rc));
+            atomicMax(&nw[3], (int)ceil(Ry - 0.5 + fib.rc));
+        }
+        const double Vx = bs->V[b][0], Vy = bs->V[b][1];
+        unsigned h = 0u;
+        if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) || !isfinite(s))
+            h |= FPD_HEALTH_NAN;
+        if (Vx * Vx + Vy * Vy > 0.09 / 3.0) h |= FPD_HEALTH_MACH;
+        if (Ry - fib.a - fib.xi < 0.0 || Ry + fib.a + fib.xi > (double)ny) h |= FPD_HEALTH_WALL;
+        if (h) atomicOr(&bs->health, h);
+    }
+}
 
-    // The last block to get here sees every bead's R, V, A.
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(&bs->done, 1u) == gridDim.x - 1) ? 1 : 0;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    finish_fiber(a);
+// Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same
+// values for the beads near its tiles).
+__global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
+    const Fiber& fib = a.fib;
+    BeadState* bs = fib.bs;
+    for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
+        double F[2];
+        bead_force(bs, fib.n, t, fib.ks_l02, fib.l0, fib.kb, F);
+        bs->F[t][0] = F[0];
+        bs->F[t][1] = F[1];
+        bs->C[t][0] = F[0] / bs->A[t];
+        bs->C[t][1] = F[1] / bs->A[t];
+    }
 }
 
 // ---------------------------------------------------- conversions and read-back ----
@@ -579,16 +594,23 @@ hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int spt, hipS
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, hipStream_t st) {
+hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
+                       hipStream_t st) {
     if (a.fib.n <= 0) return hipSuccess;
-    const dim3 grid(a.fib.n), block(kBeadThreads);
+    const dim3 grid(a.fib.n), block(kBeadBlock);
     switch (storage) {
-        case FPD_F64: hipLaunchKernelGGL((bead_kernel<FPD_F64>), grid, block, 0, st, a, do_velocity); break;
-        case FPD_F32: hipLaunchKernelGGL((bead_kernel<FPD_F32>), grid, block, 0, st, a, do_velocity); break;
-        case FPD_F16DEV: hipLaunchKernelGGL((bead_kernel<FPD_F16DEV>), grid, block, 0, st, a, do_velocity); break;
-        case FPD_BF16DEV: hipLaunchKernelGGL((bead_kernel<FPD_BF16DEV>), grid, block, 0, st, a, do_velocity); break;
+        case FPD_F64: hipLaunchKernelGGL((bead_kernel<FPD_F64>), grid, block, 0, st, a, do_velocity, win_out); break;
+        case FPD_F32: hipLaunchKernelGGL((bead_kernel<FPD_F32>), grid, block, 0, st, a, do_velocity, win_out); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((bead_kernel<FPD_F16DEV>), grid, block, 0, st, a, do_velocity, win_out); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((bead_kernel<FPD_BF16DEV>), grid, block, 0, st, a, do_velocity, win_out); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(const StepArgs& a, hipStream_t st) {
+    if (a.fib.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(forces_kernel, dim3(1), dim3(kBeadThreads), 0, st, a);
     return hipGetLastError();
 }
 

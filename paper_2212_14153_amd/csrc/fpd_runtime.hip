@@ -86,6 +86,7 @@ namespace {
 
 StepArgs make_args(const fpd_sim* s, int src_idx) {
     StepArgs a{};
+    a.parity = src_idx;
     a.src = s->buf[src_idx];
     a.dst = s->buf[1 - src_idx];
     a.L = s->L;
@@ -168,7 +169,7 @@ int enqueue_step(fpd_sim* s, int from) {
     const StepArgs a = make_args(s, from);
     const dim3 block(s->launch.block_x, s->launch.block_y);
     HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
-    if (a.fib.n > 0) HIP_TRY(launch_bead(s->p.storage, a, 1, s->stream));
+    if (a.fib.n > 0) HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - from, s->stream));
     return FPD_OK;
 }
 
@@ -212,7 +213,7 @@ int step_timed(fpd_sim* s, int64_t n) {
             HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
             HIP_TRY(hipEventRecord(ev[1], s->stream));
             if (fib) {
-                HIP_TRY(launch_bead(s->p.storage, a, 1, s->stream));
+                HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - s->cur, s->stream));
                 HIP_TRY(hipEventRecord(ev[2], s->stream));
             }
             s->cur = 1 - s->cur;
@@ -237,7 +238,7 @@ int step_timed(fpd_sim* s, int64_t n) {
 
 int fiber_init_device(fpd_sim* s) {
     const StepArgs a = make_args(s, s->cur);
-    HIP_TRY(launch_bead(s->p.storage, a, 0, s->stream));
+    HIP_TRY(launch_bead(s->p.storage, a, 0, s->cur, s->stream));
     return FPD_OK;
 }
 
@@ -282,7 +283,9 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     s->elem = storage_elem(p->storage);
     s->buf_bytes = (size_t)9 * (size_t)s->L.plane * s->elem;
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
-    s->launch = fpd_launch{64, 4, 1, 1, 64};
+    // measured on MI355X (8192 x 2048): 256 x 1 for 2- and 4-byte storage, 128 x 2 for
+    // float64, one row per thread, default block order (no XCD remap)
+    s->launch = p->storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 64} : fpd_launch{256, 1, 1, 2, 64};
     auto bail = [&](int code) {
         fpd_destroy(s);
         return code;
@@ -456,7 +459,12 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
         h.R[i][1] = R[2 * i + 1];
         h.V[i][0] = h.V[i][1] = 0.0;
     }
-    h.done = 0;
+    for (int k = 0; k < 2; ++k) {  // empty windows; the bead kernel fills slot `cur`
+        h.win[k][0] = 0x7fffffff;
+        h.win[k][1] = -0x7fffffff;
+        h.win[k][2] = 0x7fffffff;
+        h.win[k][3] = -0x7fffffff;
+    }
     HIP_TRY(hipMemcpyAsync(s->bs, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
     s->fiber = true;
     drop_graphs(s);
@@ -533,9 +541,11 @@ int fpd_health(fpd_sim* s, uint32_t* flags, double* max_strain) {
     int rc = sync_check(s);
     if (rc) return rc;
     unsigned h = 0;
-    double ms = 0.0;
+    unsigned long long bits = 0;
     HIP_TRY(hipMemcpy(&h, &s->bs->health, sizeof h, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(&ms, &s->bs->max_strain, sizeof ms, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&bits, &s->bs->max_strain_bits, sizeof bits, hipMemcpyDeviceToHost));
+    double ms;
+    memcpy(&ms, &bits, sizeof ms);
     if (flags) *flags = h;
     if (max_strain) *max_strain = ms;
     return FPD_OK;
@@ -546,9 +556,9 @@ int fpd_clear_health(fpd_sim* s) {
     int rc = sync_check(s);
     if (rc) return rc;
     const unsigned zero = 0;
-    const double dz = 0.0;
+    const unsigned long long zbits = 0;
     HIP_TRY(hipMemcpy(&s->bs->health, &zero, sizeof zero, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(&s->bs->max_strain, &dz, sizeof dz, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&s->bs->max_strain_bits, &zbits, sizeof zbits, hipMemcpyHostToDevice));
     return FPD_OK;
 }
 
@@ -564,7 +574,9 @@ int fpd_read_fields(fpd_sim* s, double* rho, double* ux, double* uy, double* eta
     double* d = nullptr;
     HIP_TRY(hipMalloc(&d, 4 * S * sizeof(double)));
     const StepArgs a = make_args(s, s->cur);
-    hipError_t e = launch_fields(s->p.storage, a, d, d + S, d + 2 * S, d + 3 * S, s->stream);
+    hipError_t e = launch_forces(a, s->stream);  // C = F / A of the current bead state
+    if (e == hipSuccess)
+        e = launch_fields(s->p.storage, a, d, d + S, d + 2 * S, d + 3 * S, s->stream);
     double* outs[4] = {rho, ux, uy, eta};
     for (int i = 0; i < 4 && e == hipSuccess; ++i)
         if (outs[i])
@@ -601,6 +613,7 @@ int fpd_read_beads(fpd_sim* s, double* R, double* V, double* F) {
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     const int N = s->p.n_beads;
     if (N == 0) return FPD_OK;
+    HIP_TRY(launch_forces(make_args(s, s->cur), s->stream));  // F^n of the current positions
     int rc = sync_check(s);
     if (rc) return rc;
     std::vector<double> h(2 * (size_t)kMaxBeads * 3);
@@ -704,7 +717,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 
 // ---------------------------------------------------------------- checkpoint -------
 
-static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '1'};
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '2'};
 
 int fpd_save(fpd_sim* s, const char* path) {
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
@@ -717,8 +730,10 @@ int fpd_save(fpd_sim* s, const char* path) {
     FILE* fp = fopen(path, "wb");
     if (!fp) return fail(FPD_EINVAL, "cannot open %s for writing", path);
     const uint8_t fib = s->fiber ? 1 : 0;
+    const uint8_t par = (uint8_t)s->cur;  // the bead state's window slot follows the parity
     bool ok = fwrite(kMagic, 1, 8, fp) == 8 && fwrite(&s->p, sizeof s->p, 1, fp) == 1 &&
               fwrite(&s->steps, sizeof s->steps, 1, fp) == 1 && fwrite(&fib, 1, 1, fp) == 1 &&
+              fwrite(&par, 1, 1, fp) == 1 &&
               fwrite(&s->buf_bytes, sizeof s->buf_bytes, 1, fp) == 1 &&
               fwrite(pops.data(), 1, pops.size(), fp) == pops.size() &&
               fwrite(&h, sizeof h, 1, fp) == 1;
@@ -736,11 +751,12 @@ int fpd_load(fpd_sim* s, const char* path) {
     char magic[8];
     fpd_params p;
     int64_t steps = 0;
-    uint8_t fib = 0;
+    uint8_t fib = 0, par = 0;
     size_t bytes = 0;
     bool ok = fread(magic, 1, 8, fp) == 8 && memcmp(magic, kMagic, 8) == 0 &&
               fread(&p, sizeof p, 1, fp) == 1 && fread(&steps, sizeof steps, 1, fp) == 1 &&
-              fread(&fib, 1, 1, fp) == 1 && fread(&bytes, sizeof bytes, 1, fp) == 1;
+              fread(&fib, 1, 1, fp) == 1 && fread(&par, 1, 1, fp) == 1 && par <= 1 &&
+              fread(&bytes, sizeof bytes, 1, fp) == 1;
     if (!ok || bytes != s->buf_bytes || !params_equal(p, s->p)) {
         fclose(fp);
         return fail(FPD_EINVAL, "%s does not match this simulation", path);
@@ -750,6 +766,8 @@ int fpd_load(fpd_sim* s, const char* path) {
     ok = fread(pops.data(), 1, bytes, fp) == bytes && fread(&h, sizeof h, 1, fp) == 1;
     fclose(fp);
     if (!ok) return fail(FPD_EINVAL, "%s is truncated", path);
+    drop_graphs(s);
+    s->cur = par;
     HIP_TRY(hipMemcpy(s->buf[s->cur], pops.data(), bytes, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->bs, &h, sizeof h, hipMemcpyHostToDevice));
     s->steps = steps;

@@ -58,8 +58,10 @@ def test_initial_populations_match_oracle(storage, tol):
     assert np.max(np.abs(f - ref)) <= tol
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 0.0), ("f32", 1e-8), ("f16dev", 1e-6),
-                                         ("bf16dev", 2e-4)])
+# f32 / f16dev / bf16dev store g = f - w with 24 / 11 / 8 significant bits; |g| < 6e-3 here
+@pytest.mark.parametrize("storage,tol", [("f64", 0.0), ("f32", 6e-3 * 2.0 ** -24),
+                                         ("f16dev", 6e-3 * 2.0 ** -11),
+                                         ("bf16dev", 6e-3 * 2.0 ** -8)])
 def test_write_read_roundtrip(storage, tol):
     w = workloads.c1_small_fp64().with_(nx=37, ny=11, n_beads=0)
     print_case("roundtrip", w, storage)
@@ -112,7 +114,8 @@ def test_c1_fp64_populations_after_100_steps():
     assert rel_err(f, st.f) <= 1e-12
     assert np.max(np.abs(R - st.R)) <= 1e-12
     assert np.max(np.abs(V - st.V)) <= 1e-14
-    assert np.allclose(F, oracle.bead_forces(orc_params(w), st.R), rtol=1e-9, atol=1e-16)
+    Fo = oracle.bead_forces(orc_params(w), st.R)
+    assert np.max(np.abs(F - Fo)) <= 1e-9 * np.abs(Fo).max()
 
 
 def test_c1_fp64_beads_after_1000_steps():
@@ -225,20 +228,21 @@ def test_repeat_runs_are_deterministic():
         assert np.array_equal(a, b)
 
 
-def test_checkpoint_resume_is_bitwise(tmp_path):
+@pytest.mark.parametrize("first", [100, 101])
+def test_checkpoint_resume_is_bitwise(tmp_path, first):
     w = workloads.c1_small_fp64()
-    print_case("checkpoint", w, "f32")
+    print_case(f"checkpoint-{first}", w, "f32")
     path = str(tmp_path / "c1.fpd")
     with gpu_sim(w, "f32") as a:
         a.step(200)
         fa, Ra = a.populations(), a.beads()[0]
     with gpu_sim(w, "f32") as b:
-        b.step(100)
+        b.step(first)
         b.save(path)
     with gpu_sim(w, "f32") as c:
         c.load(path)
-        assert c.steps == 100
-        c.step(100)
+        assert c.steps == first
+        c.step(200 - first)
         assert np.array_equal(c.populations(), fa)
         assert np.array_equal(c.beads()[0], Ra)
 
