@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_VALUE))
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
     args = ap.parse_args()

@@ -105,6 +105,7 @@ typedef struct fpd_launch {
     int32_t rows_per_thread;  /* lattice rows per thread: 1, 2 or 4                         */
     int32_t xcd_remap;        /* 1: consecutive tiles on one XCD; 2: off                    */
     int32_t graph_chunk;      /* steps per captured graph (even, >= 2)                      */
+    int32_t x_chunks;         /* consecutive block_x-wide chunks of a row per block: 1..32  */
 } fpd_launch;
 
 typedef struct fpd_sim fpd_sim;

@@ -14,7 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfpdlbm.so")
+# FPD_LIBRARY may name another build of the same library (A/B timing of kernel variants)
+LIB_PATH = os.environ.get("FPD_LIBRARY") or os.path.join(HERE, "libfpdlbm.so")
 
 FPD_OK, FPD_EINVAL, FPD_ENOMEM, FPD_EUNSTABLE, FPD_EDEVICE, FPD_ESTATE = 0, -1, -2, -3, -4, -5
 FPD_F64, FPD_F32, FPD_F16DEV, FPD_BF16DEV = 0, 1, 2, 3
@@ -46,7 +47,7 @@ class fpd_launch(ctypes.Structure):
     _fields_ = [
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-        ("graph_chunk", ctypes.c_int32),
+        ("graph_chunk", ctypes.c_int32), ("x_chunks", ctypes.c_int32),
     ]
 
 
@@ -173,8 +174,9 @@ class LaunchConfig:
     block_x: int = 64
     block_y: int = 4
     rows_per_thread: int = 1
-    xcd_remap: int = 1
+    xcd_remap: int = 2
     graph_chunk: int = 64
+    x_chunks: int = 1
 
 
 class Simulation:
@@ -273,7 +275,8 @@ class Simulation:
     def get_launch(self) -> LaunchConfig:
         c = fpd_launch()
         check(lib().fpd_get_launch(self.h, ctypes.byref(c)))
-        return LaunchConfig(c.block_x, c.block_y, c.rows_per_thread, c.xcd_remap, c.graph_chunk)
+        return LaunchConfig(c.block_x, c.block_y, c.rows_per_thread, c.xcd_remap, c.graph_chunk,
+                            c.x_chunks)
 
     def kernel_times(self):
         a, b = ctypes.c_double(), ctypes.c_double()

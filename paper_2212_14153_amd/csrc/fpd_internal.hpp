@@ -59,6 +59,7 @@ struct StepArgs {
     double s_e, s_eps;
     Fiber fib;
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
+    int x_chunks;             // block_x-wide chunks per tile row (tile width block_x * x_chunks)
     int rows_per_block;       // block_y * rows_per_thread
     int xcd_remap;
 };

@@ -218,7 +218,8 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int bx = blockDim.x;
-    const int x = tx * bx + threadIdx.x;
+    const int tw = bx * a.x_chunks;            // tile width: x_chunks chunks of one row
+    const int xtile = tx * tw;
     const int ytile = ty * a.rows_per_block;
     const int ybase = ytile + threadIdx.y * SPT;
     const int nx = a.L.nx, ny = a.L.ny, stride = a.L.stride;
@@ -250,12 +251,14 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         }
         fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
                      ytile + a.rows_per_block - 1 >= wy0 &&
-                     cols_overlap(tx * bx, bx, wx0, ww, nx);
+                     cols_overlap(xtile, tw, wx0, ww, nx);
         if (fiber_tile)
-            nb = gather_beads(a.fib, nx, ny, tx * bx, bx, ytile, a.rows_per_block, sR, sC,
+            nb = gather_beads(a.fib, nx, ny, xtile, tw, ytile, a.rows_per_block, sR, sC,
                               s_wave);
     }
 
+    for (int c = 0; c < a.x_chunks; ++c) {
+    const int x = xtile + c * bx + threadIdx.x;
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
         const int y = ybase + r;
@@ -295,6 +298,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         S* o = dst + (long long)y * stride + x;
 #pragma unroll
         for (int k = 0; k < 9; ++k) Cd::store(o + k * plane, g[k]);
+    }
     }
 }
 

@@ -117,7 +117,9 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.kb = s->p.k_b;
     const fpd_launch& c = s->launch;
     a.rows_per_block = c.block_y * c.rows_per_thread;
-    a.tiles_x = (s->L.nx + c.block_x - 1) / c.block_x;
+    a.x_chunks = c.x_chunks;
+    const int tile_w = c.block_x * c.x_chunks;
+    a.tiles_x = (s->L.nx + tile_w - 1) / tile_w;
     const int tiles_y = (s->L.ny + a.rows_per_block - 1) / a.rows_per_block;
     a.n_tiles = a.tiles_x * tiles_y;
     a.xcd_remap = c.xcd_remap == 1 ? 1 : 0;
@@ -285,7 +287,8 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
     // measured on MI355X (8192 x 2048): 256 x 1 for 2- and 4-byte storage, 128 x 2 for
     // float64, one row per thread, default block order (no XCD remap)
-    s->launch = p->storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 64} : fpd_launch{256, 1, 1, 2, 64};
+    s->launch = p->storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 64, 1}
+                                      : fpd_launch{256, 1, 1, 2, 64, 1};
     auto bail = [&](int code) {
         fpd_destroy(s);
         return code;
@@ -636,6 +639,7 @@ int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
     if (c->rows_per_thread > 0) n.rows_per_thread = c->rows_per_thread;
     if (c->xcd_remap > 0) n.xcd_remap = c->xcd_remap;
     if (c->graph_chunk > 0) n.graph_chunk = c->graph_chunk;
+    if (c->x_chunks > 0) n.x_chunks = c->x_chunks;
     if (n.block_x != 64 && n.block_x != 128 && n.block_x != 256)
         return fail(FPD_EINVAL, "block_x must be 64, 128 or 256");
     if (n.block_y != 1 && n.block_y != 2 && n.block_y != 4)
@@ -645,6 +649,7 @@ int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
         return fail(FPD_EINVAL, "rows_per_thread must be 1, 2 or 4");
     if (n.graph_chunk < 2 || (n.graph_chunk & 1))
         return fail(FPD_EINVAL, "graph_chunk must be even and >= 2");
+    if (n.x_chunks < 1 || n.x_chunks > 32) return fail(FPD_EINVAL, "x_chunks must be in 1..32");
     int rc = sync_check(s);
     if (rc) return rc;
     s->launch = n;
