@@ -105,7 +105,6 @@ typedef struct fpd_launch {
     int32_t rows_per_thread;  /* lattice rows per thread: 1, 2 or 4                         */
     int32_t xcd_remap;        /* 1: consecutive tiles on one XCD; 2: off                    */
     int32_t graph_chunk;      /* steps per captured graph (even, >= 2)                      */
-    int32_t x_chunks;         /* consecutive block_x-wide chunks of a row per block: 1..32  */
 } fpd_launch;
 
 typedef struct fpd_sim fpd_sim;
@@ -214,6 +213,64 @@ int fpd_copy_probe(void *hip_stream, size_t bytes, int32_t iters, double *gbps);
  * fpd_load requires a simulation created with the same parameters. */
 int fpd_save(fpd_sim *s, const char *path);
 int fpd_load(fpd_sim *s, const char *path);
+
+/* ------------------------------------------------------------------ batch ---- */
+/* A batch holds independent simulations of different lattice sizes (one storage format)
+ * and advances all active ones together: each step is one persistent lattice kernel over
+ * every (simulation, tile) pair and one persistent bead kernel over every (simulation,
+ * bead) pair, replayed from a captured graph.  The parameter-sweep workload of the paper
+ * (Sec. IV: stiffness, Re_ps 1-10, confinement) is the intended use.  Per-simulation
+ * arithmetic is the single-simulation path's, so a result is bitwise the same alone and
+ * in any mix. */
+
+typedef struct fpd_batch fpd_batch;
+
+#define FPD_SIM_ACTIVE  0   /* still running                                             */
+#define FPD_SIM_DONE    1   /* reached its step target; results readable until release   */
+#define FPD_SIM_FAILED  2   /* evicted by a health check (FPD_HEALTH_* bits set)          */
+
+/* Device bytes one simulation of p occupies in a batch (populations, fiber window, bead
+ * state). */
+size_t fpd_sim_footprint(const fpd_params *p);
+
+/* hbm_budget_bytes caps the sum of footprints of held simulations; max_slots caps their
+ * number (<= 4096); storage is one of FPD_F64..FPD_BF16DEV for every member. */
+int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage,
+                     void *hip_stream, fpd_batch **out);
+
+/* Launch shape of the batch's lattice kernel (graph_chunk: steps per replayed graph). */
+int fpd_batch_set_launch(fpd_batch *b, const fpd_launch *cfg);
+
+/* Admit one simulation: p->storage must be the batch's; R is host [n_beads][2] (NULL when
+ * n_beads = 0); it will run n_steps >= 0 steps.  FPD_ENOMEM when no slot is free or the
+ * footprint would exceed the budget (nothing is allocated then).  *sim_id > 0. */
+int fpd_batch_add(fpd_batch *b, const fpd_params *p, const double *R, int64_t n_steps,
+                  int64_t *sim_id);
+
+/* Advance every active simulation by min(max_steps, smallest remaining count) steps
+ * (*advanced receives it; 0 when none is active), then check health: a simulation with a
+ * health bit set becomes FPD_SIM_FAILED, the others continue.  Synchronises. */
+int fpd_batch_run(fpd_batch *b, int64_t max_steps, int64_t *advanced);
+
+/* Simulations that became DONE or FAILED since the last poll: ids[i], status[i]
+ * (up to cap; *n receives the count). */
+int fpd_batch_poll(fpd_batch *b, int64_t *ids, int32_t *status, int32_t cap, int32_t *n);
+
+/* Read-back of a held simulation (same conventions as the single-simulation calls). */
+int fpd_batch_read_beads(fpd_batch *b, int64_t sim_id, double *R, double *V, double *F);
+int fpd_batch_read_populations(fpd_batch *b, int64_t sim_id, double *f);
+int fpd_batch_read_fields(fpd_batch *b, int64_t sim_id, double *rho, double *ux, double *uy,
+                          double *eta);
+int fpd_batch_sim_info(fpd_batch *b, int64_t sim_id, int64_t *steps, int32_t *status,
+                       uint32_t *health);
+
+/* Free a held simulation (any status). */
+int fpd_batch_release(fpd_batch *b, int64_t sim_id);
+
+/* Active and held simulation counts and device bytes in use. */
+int fpd_batch_stats(fpd_batch *b, int32_t *active, int32_t *held, size_t *bytes_in_use);
+
+void fpd_batch_destroy(fpd_batch *b);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,7 @@ class fpd_launch(ctypes.Structure):
     _fields_ = [
         ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
         ("rows_per_thread", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-        ("graph_chunk", ctypes.c_int32), ("x_chunks", ctypes.c_int32),
+        ("graph_chunk", ctypes.c_int32),
     ]
 
 
@@ -89,7 +89,30 @@ SIGNATURES = [
     ("fpd_copy_probe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, _D]),
     ("fpd_save", ctypes.c_int, [_SIM, ctypes.c_char_p]),
     ("fpd_load", ctypes.c_int, [_SIM, ctypes.c_char_p]),
+    ("fpd_sim_footprint", ctypes.c_size_t, [ctypes.POINTER(fpd_params)]),
+    ("fpd_batch_create", ctypes.c_int,
+     [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_SIM)]),
+    ("fpd_batch_set_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
+    ("fpd_batch_add", ctypes.c_int,
+     [_SIM, ctypes.POINTER(fpd_params), _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    ("fpd_batch_run", ctypes.c_int, [_SIM, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    ("fpd_batch_poll", ctypes.c_int,
+     [_SIM, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+      ctypes.POINTER(ctypes.c_int32)]),
+    ("fpd_batch_read_beads", ctypes.c_int, [_SIM, ctypes.c_int64, _D, _D, _D]),
+    ("fpd_batch_read_populations", ctypes.c_int, [_SIM, ctypes.c_int64, _D]),
+    ("fpd_batch_read_fields", ctypes.c_int, [_SIM, ctypes.c_int64, _D, _D, _D, _D]),
+    ("fpd_batch_sim_info", ctypes.c_int,
+     [_SIM, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+      ctypes.POINTER(ctypes.c_uint32)]),
+    ("fpd_batch_release", ctypes.c_int, [_SIM, ctypes.c_int64]),
+    ("fpd_batch_stats", ctypes.c_int,
+     [_SIM, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+      ctypes.POINTER(ctypes.c_size_t)]),
+    ("fpd_batch_destroy", None, [_SIM]),
 ]
+
+FPD_SIM_ACTIVE, FPD_SIM_DONE, FPD_SIM_FAILED = 0, 1, 2
 
 _lib = None
 
@@ -176,7 +199,6 @@ class LaunchConfig:
     rows_per_thread: int = 1
     xcd_remap: int = 2
     graph_chunk: int = 64
-    x_chunks: int = 1
 
 
 class Simulation:
@@ -275,8 +297,7 @@ class Simulation:
     def get_launch(self) -> LaunchConfig:
         c = fpd_launch()
         check(lib().fpd_get_launch(self.h, ctypes.byref(c)))
-        return LaunchConfig(c.block_x, c.block_y, c.rows_per_thread, c.xcd_remap, c.graph_chunk,
-                            c.x_chunks)
+        return LaunchConfig(c.block_x, c.block_y, c.rows_per_thread, c.xcd_remap, c.graph_chunk)
 
     def kernel_times(self):
         a, b = ctypes.c_double(), ctypes.c_double()
@@ -303,3 +324,108 @@ def simulation_from_workload(w, storage=None, stream=None, flags=0, **over) -> S
     if p.n_beads > 0:
         sim.init_fiber(w.beads())
     return sim
+
+
+def fpd_sim_footprint(p: fpd_params) -> int:
+    return int(lib().fpd_sim_footprint(ctypes.byref(p)))
+
+
+class Batch:
+    """A batch of independent simulations advanced together (C ABI fpd_batch_*)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, storage="f32", stream=None):
+        h = _SIM()
+        st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        check(lib().fpd_batch_create(int(hbm_budget), int(max_slots), st, stream,
+                                     ctypes.byref(h)))
+        self.h = h
+        self.storage = st
+        self.shapes = {}
+
+    def close(self):
+        if self.h:
+            lib().fpd_batch_destroy(self.h)
+            self.h = _SIM()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_launch(self, cfg):
+        d = cfg if isinstance(cfg, dict) else cfg.__dict__
+        c = fpd_launch(*(int(d.get(k, 0)) for k, _ in fpd_launch._fields_))
+        check(lib().fpd_batch_set_launch(self.h, ctypes.byref(c)))
+
+    def add(self, params: fpd_params, R, n_steps: int) -> int:
+        """Admit a simulation; raises FpdError (code FPD_ENOMEM) when it does not fit."""
+        sid = ctypes.c_int64()
+        Rp = None
+        if params.n_beads > 0:
+            R = np.ascontiguousarray(R, dtype=np.float64).reshape(params.n_beads, 2)
+            Rp = _ptr(R)
+        check(lib().fpd_batch_add(self.h, ctypes.byref(params), Rp, int(n_steps),
+                                  ctypes.byref(sid)))
+        self.shapes[sid.value] = (params.nx, params.ny, params.n_beads)
+        return sid.value
+
+    def try_add(self, params: fpd_params, R, n_steps: int):
+        try:
+            return self.add(params, R, n_steps)
+        except FpdError as e:
+            if e.code == FPD_ENOMEM:
+                return None
+            raise
+
+    def run(self, max_steps: int) -> int:
+        adv = ctypes.c_int64()
+        check(lib().fpd_batch_run(self.h, int(max_steps), ctypes.byref(adv)))
+        return adv.value
+
+    def poll(self, cap: int = 4096):
+        ids = (ctypes.c_int64 * cap)()
+        st = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        check(lib().fpd_batch_poll(self.h, ids, st, cap, ctypes.byref(n)))
+        return [(ids[i], st[i]) for i in range(n.value)]
+
+    def beads(self, sid: int):
+        nx, ny, n = self.shapes[sid]
+        R, V, F = (np.empty((n, 2)) for _ in range(3))
+        if n:
+            check(lib().fpd_batch_read_beads(self.h, sid, _ptr(R), _ptr(V), _ptr(F)))
+        return R, V, F
+
+    def populations(self, sid: int):
+        nx, ny, n = self.shapes[sid]
+        f = np.empty((9, ny, nx))
+        check(lib().fpd_batch_read_populations(self.h, sid, _ptr(f)))
+        return f
+
+    def fields(self, sid: int):
+        nx, ny, n = self.shapes[sid]
+        out = [np.empty((ny, nx)) for _ in range(4)]
+        check(lib().fpd_batch_read_fields(self.h, sid, *[_ptr(o) for o in out]))
+        return tuple(out)
+
+    def info(self, sid: int):
+        steps, status, health = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_uint32()
+        check(lib().fpd_batch_sim_info(self.h, sid, ctypes.byref(steps), ctypes.byref(status),
+                                       ctypes.byref(health)))
+        return steps.value, status.value, health.value
+
+    def release(self, sid: int):
+        check(lib().fpd_batch_release(self.h, sid))
+        self.shapes.pop(sid, None)
+
+    def stats(self):
+        a, h, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        check(lib().fpd_batch_stats(self.h, ctypes.byref(a), ctypes.byref(h), ctypes.byref(b)))
+        return a.value, h.value, b.value

@@ -92,8 +92,21 @@ __device__ inline int xcd_tile(int bid, int nblocks) {
 
 // Columns and rows whose node centres can lie within rc of a bead at (Rx, Ry):
 // columns i0 + [0, w) modulo nx (w <= nx), rows j0..j1 (clipped to the channel).
+// A bead that is not finite or has left any sensible range (a simulation that blew up)
+// gets an empty box, so no index is ever formed from it.
+__device__ inline bool bead_sane(double Rx, double Ry) {
+    return fabs(Rx) < 1.0e9 && fabs(Ry) < 1.0e9;  // false for NaN too
+}
+
 __device__ inline void bead_box(double Rx, double Ry, double rc, int nx, int ny, int& i0,
                                 int& w, int& j0, int& j1) {
+    if (!bead_sane(Rx, Ry)) {
+        i0 = 0;
+        w = 0;
+        j0 = 0;
+        j1 = -1;
+        return;
+    }
     const int lo = (int)floor(Rx - 0.5 - rc);
     const int hi = (int)ceil(Rx - 0.5 + rc);
     w = hi - lo + 1;

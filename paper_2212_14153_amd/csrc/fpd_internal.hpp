@@ -59,9 +59,19 @@ struct StepArgs {
     double s_e, s_eps;
     Fiber fib;
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
-    int x_chunks;             // block_x-wide chunks per tile row (tile width block_x * x_chunks)
     int rows_per_block;       // block_y * rows_per_thread
     int xcd_remap;
+};
+
+// A batch step: per simulation two StepArgs (the step parities of a chunk), prefix sums of
+// lattice tiles and of beads, and counts {simulations, tiles, beads}; all in device memory
+// so that a captured graph stays valid while simulations join and leave.
+struct BatchArgs {
+    const StepArgs* args;     // [2 * n]
+    const int* tile_off;      // [n + 1]
+    const int* bead_off;      // [n + 1]
+    const int* counts;        // [3]
+    int gpar;                 // parity of this step within the chunk
 };
 
 // Kernel launchers (fpd_kernels.hip).
@@ -70,6 +80,9 @@ hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
                        hipStream_t st);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);
+hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int rows_per_thread,
+                             int grid_lattice, int grid_bead, hipStream_t st);
+hipError_t health_gather(BeadState* const* states, unsigned* out, int n, hipStream_t st);
 hipError_t launch_unstream(int storage, const Lattice& L, double u_wall, const double* f64,
                            void* dst, hipStream_t st);
 hipError_t launch_stream_out(int storage, const Lattice& L, double u_wall, const void* src,

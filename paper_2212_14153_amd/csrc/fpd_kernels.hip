@@ -47,58 +47,58 @@ __device__ inline double block_sum(double v, double* scratch) {
 // -k_b t_m . t_{m+1} of the pair of bonds (m, m+1), whose forces on the three beads
 // m, m+1, m+2 are k_b times -a_m, a_m - b_m, b_m with
 // a_m = (I - t_m t_m) t_{m+1} / L_m and b_m = (I - t_{m+1} t_{m+1}) t_m / L_{m+1}.
-__device__ inline void bond(const BeadState* bs, int m, double t[2], double& L) {
-    const double dx = bs->R[m + 1][0] - bs->R[m][0];
-    const double dy = bs->R[m + 1][1] - bs->R[m][1];
-    L = sqrt(dx * dx + dy * dy);
-    t[0] = dx / L;
-    t[1] = dy / L;
+// Tangents t_m and lengths L_m of all bonds, computed once per block into LDS (one thread
+// per bond) so that the per-bead gathers below keep few values in registers.
+struct Bonds {
+    double t[kMaxBeads][2];
+    double L[kMaxBeads];
+};
+
+__device__ inline void fill_bonds(const BeadState* bs, int N, Bonds& B) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    for (int m = tid; m < N - 1; m += nthreads) {
+        const double dx = bs->R[m + 1][0] - bs->R[m][0];
+        const double dy = bs->R[m + 1][1] - bs->R[m][1];
+        const double L = sqrt(dx * dx + dy * dy);
+        B.t[m][0] = dx / L;
+        B.t[m][1] = dy / L;
+        B.L[m] = L;
+    }
+    __syncthreads();
 }
 
-__device__ inline void proj(const double t[2], const double v[2], double L, double out[2]) {
-    const double vt = v[0] * t[0] + v[1] * t[1];
-    out[0] = (v[0] - vt * t[0]) / L;
-    out[1] = (v[1] - vt * t[1]) / L;
+// k_b (I - t_u t_u) t_v / L_u added with sign `sg` to F.
+__device__ inline void add_proj(const Bonds& B, int u, int v, double sg_kb, double F[2]) {
+    const double t0 = B.t[u][0], t1 = B.t[u][1];
+    const double v0 = B.t[v][0], v1 = B.t[v][1];
+    const double vt = v0 * t0 + v1 * t1;
+    const double inv = sg_kb / B.L[u];
+    F[0] += (v0 - vt * t0) * inv;
+    F[1] += (v1 - vt * t1) * inv;
 }
 
-__device__ inline void bead_force(const BeadState* bs, int N, int t, double ks_l02, double l0,
+__device__ inline void bead_force(const Bonds& B, int N, int t, double ks_l02, double l0,
                                   double kb, double F[2]) {
     F[0] = 0.0;
     F[1] = 0.0;
-    double tm[2], tp[2], Lm, Lp, q[2];
     if (t >= 1) {  // bond (t-1, t): pulls t back towards t-1 when stretched
-        bond(bs, t - 1, tm, Lm);
-        F[0] -= ks_l02 * (Lm - l0) * tm[0];
-        F[1] -= ks_l02 * (Lm - l0) * tm[1];
+        const double s = ks_l02 * (B.L[t - 1] - l0);
+        F[0] -= s * B.t[t - 1][0];
+        F[1] -= s * B.t[t - 1][1];
     }
     if (t <= N - 2) {  // bond (t, t+1)
-        bond(bs, t, tp, Lp);
-        F[0] += ks_l02 * (Lp - l0) * tp[0];
-        F[1] += ks_l02 * (Lp - l0) * tp[1];
+        const double s = ks_l02 * (B.L[t] - l0);
+        F[0] += s * B.t[t][0];
+        F[1] += s * B.t[t][1];
     }
     if (kb == 0.0) return;
-    if (t <= N - 3) {  // pair (t, t+1): bead t is its first bead, gets -k_b a_t
-        double t2[2], L2;
-        bond(bs, t + 1, t2, L2);
-        proj(tp, t2, Lp, q);
-        F[0] -= kb * q[0];
-        F[1] -= kb * q[1];
+    if (t <= N - 3) add_proj(B, t, t + 1, -kb, F);          // pair (t, t+1): -k_b a_t
+    if (t >= 1 && t <= N - 2) {                             // pair (t-1, t): middle bead
+        add_proj(B, t - 1, t, kb, F);                       //   + k_b a_{t-1}
+        add_proj(B, t, t - 1, -kb, F);                      //   - k_b b_{t-1}
     }
-    if (t >= 1 && t <= N - 2) {  // pair (t-1, t): bead t is its middle bead
-        proj(tm, tp, Lm, q);           // a_{t-1}
-        F[0] += kb * q[0];
-        F[1] += kb * q[1];
-        proj(tp, tm, Lp, q);           // b_{t-1}
-        F[0] -= kb * q[0];
-        F[1] -= kb * q[1];
-    }
-    if (t >= 2) {  // pair (t-2, t-1): bead t is its last bead, gets +k_b b_{t-2}
-        double t0[2], L0;
-        bond(bs, t - 2, t0, L0);
-        proj(tm, t0, Lm, q);
-        F[0] += kb * q[0];
-        F[1] += kb * q[1];
-    }
+    if (t >= 2) add_proj(B, t - 1, t - 2, kb, F);           // pair (t-2, t-1): + k_b b_{t-2}
 }
 
 // Window slot (raw bounds) -> x0 (mod nx), width, y0, height; clamped to the reserved
@@ -136,17 +136,15 @@ __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
 
 // The tile that contains node (floor Rx mod nx, floor Ry) owns bead b: it publishes F_b,
 // C_b and the strain of bond (b, b+1).
-__device__ inline void own_bead(const Fiber& fib, int N, int b, const double F[2], double C0,
-                                double C1) {
+__device__ inline void own_bead(const Fiber& fib, const Bonds& B, int N, int b,
+                                const double F[2], double C0, double C1) {
     BeadState* bs = fib.bs;
     bs->F[b][0] = F[0];
     bs->F[b][1] = F[1];
     bs->C[b][0] = C0;
     bs->C[b][1] = C1;
     if (b <= N - 2) {
-        double t[2], L;
-        bond(bs, b, t, L);
-        const double strain = fabs(L - fib.l0) / fib.l0;
+        const double strain = fabs(B.L[b] - fib.l0) / fib.l0;
         if (!(strain <= 0.5)) atomicOr(&bs->health, FPD_HEALTH_STRAIN);
         atomic_max_nonneg(&bs->max_strain_bits, strain);
     }
@@ -157,11 +155,13 @@ __device__ inline void own_bead(const Fiber& fib, int N, int b, const double F[2
 // [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
 // beads run in the same order as in a full loop.
 __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, int cw, int ry0,
-                                   int rh, double (*sR)[2], double (*sC)[2], int* s_wave) {
+                                   int rh, double (*sR)[2], double (*sC)[2], int* s_wave,
+                                   Bonds& B) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthreads = blockDim.x * blockDim.y;
     const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
     const BeadState* bs = fib.bs;
+    fill_bonds(bs, fib.n, B);
     int total = 0;
     for (int base = 0; base < fib.n; base += nthreads) {
         const int b = base + tid;
@@ -187,7 +187,7 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, in
         if (hit) {
             // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
             double F[2];
-            bead_force(bs, fib.n, b, fib.ks_l02, fib.l0, fib.kb, F);
+            bead_force(B, fib.n, b, fib.ks_l02, fib.l0, fib.kb, F);
             const double A = bs->A[b];
             const double C0 = F[0] / A, C1 = F[1] / A;
             sR[off + before][0] = Rx;
@@ -196,7 +196,7 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, in
             sC[off + before][1] = C1;
             const int ox = imod((int)floor(Rx), nx), oy = (int)floor(Ry);
             if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
-                own_bead(fib, fib.n, b, F, C0, C1);
+                own_bead(fib, B, fib.n, b, F, C0, C1);
         }
         total += chunk;
         __syncthreads();
@@ -206,20 +206,30 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, in
 
 // ------------------------------------------------------------- fused lattice step ---
 
+// LDS of a lattice tile: the beads near it and their Eq. (4) coefficients.
+struct TileLds {
+    double R[kMaxBeads][2];
+    double C[kMaxBeads][2];
+    Bonds bonds;
+    int wave[16];
+};
+
+// One tile (block_x nodes on rows_per_block rows) of one simulation.
+// Must be reached by every thread of the block (it synchronises when the tile meets the
+// fiber).  The tile numbered 0 also resets the window slot the bead kernel fills next.
 template <int ST, int SPT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
+__device__ inline void lattice_tile(const StepArgs& a, int tile, TileLds& lds) {
     using Cd = Codec<ST>;
     using T = typename Cd::T;
     using S = typename Cd::store_t;
-    __shared__ double sR[kMaxBeads][2];
-    __shared__ double sC[kMaxBeads][2];
-    __shared__ int s_wave[16];
-
-    const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    double (*sR)[2] = lds.R;
+    double (*sC)[2] = lds.C;
+    int* s_wave = lds.wave;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int bx = blockDim.x;
-    const int tw = bx * a.x_chunks;            // tile width: x_chunks chunks of one row
+    const int tw = bx;
     const int xtile = tx * tw;
+    const int x = xtile + threadIdx.x;
     const int ytile = ty * a.rows_per_block;
     const int ybase = ytile + threadIdx.y * SPT;
     const int nx = a.L.nx, ny = a.L.ny, stride = a.L.stride;
@@ -240,7 +250,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
         wy0 = win.y0;
         ww = win.w;
         wh = win.h;
-        if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+        if (tile == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
             // the bead kernel of this step fills the other slot from scratch
             int* nxt = bs->win[1 - a.parity];
             nxt[0] = 0x7fffffff;
@@ -254,11 +264,9 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
                      cols_overlap(xtile, tw, wx0, ww, nx);
         if (fiber_tile)
             nb = gather_beads(a.fib, nx, ny, xtile, tw, ytile, a.rows_per_block, sR, sC,
-                              s_wave);
+                              s_wave, lds.bonds);
     }
 
-    for (int c = 0; c < a.x_chunks; ++c) {
-    const int x = xtile + c * bx + threadIdx.x;
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
         const int y = ybase + r;
@@ -299,6 +307,47 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) Cd::store(o + k * plane, g[k]);
     }
+}
+
+template <int ST, int SPT>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
+    __shared__ TileLds lds;
+    const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    lattice_tile<ST, SPT>(a, tile, lds);
+}
+
+// Index of the simulation that owns work item `item`: the largest s with off[s] <= item.
+__device__ inline int find_sim(const int* off, int n, int item) {
+    int lo = 0, hi = n;  // off[lo] <= item < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The argument table is read-only while a batch kernel runs: viewing it in the constant
+// address space lets the per-simulation arguments come in through scalar loads.
+typedef const StepArgs __attribute__((address_space(4))) ConstStepArgs;
+
+__device__ inline StepArgs load_args(const StepArgs* table, int i) {
+    const ConstStepArgs* c = (const ConstStepArgs*)table;
+    StepArgs a;
+    __builtin_memcpy(&a, c + i, sizeof(StepArgs));
+    return a;
+}
+
+// Persistent lattice kernel over a batch of simulations of different sizes: a fixed grid
+// walks the (simulation, tile) items in a static stride (no queue, no waiting).
+template <int ST, int SPT>
+__global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
+    __shared__ TileLds lds;
+    const int n = b.counts[0], total = b.counts[1];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = find_sim(b.tile_off, n, item);
+        const StepArgs a = load_args(b.args, 2 * s + b.gpar);
+        lattice_tile<ST, SPT>(a, item - b.tile_off[s], lds);
+        __syncthreads();  // the LDS bead list is rebuilt by the next item
     }
 }
 
@@ -315,16 +364,14 @@ __device__ inline double bead_phi(const Fiber& fib, double dx, double dy) {
 // rho^{n+1} / A_i^n over the bead's support box (Eq. 5, FP64 sums), then the Euler update
 // R_i^{n+1} = R_i^n + V_i^{n+1}.  Always: A_i = sum_x phi_i at the (new) position.
 template <int ST>
-__global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_velocity,
-                                                          int win_out) {
+__device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int win_out,
+                                  double* scratch, double* s_R) {
     using Cd = Codec<ST>;
     using T = typename Cd::T;
     using S = typename Cd::store_t;
-    __shared__ double scratch[kBeadBlock / 64];
-    __shared__ double s_R[2];
     const Fiber& fib = a.fib;
     BeadState* bs = fib.bs;
-    const int b = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int nx = a.L.nx, ny = a.L.ny;
     double Rx = bs->R[b][0], Ry = bs->R[b][1];
 
@@ -332,7 +379,7 @@ __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_vel
         int i0, w, j0, j1;
         bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
         const int rows = j1 - j0 + 1;
-        const int total = rows > 0 ? rows * w : 0;
+        const int total = (rows > 0 && w > 0) ? rows * w : 0;
         const Window win = decode_window(bs->win[a.parity], nx, ny, fib.rect_wmax,
                                          fib.rect_hmax);
         const int wx0 = win.x0, wy0 = win.y0, ww = win.w, wh = win.h;
@@ -389,7 +436,7 @@ __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_vel
     int i0, w, j0, j1;
     bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
     const int rows = j1 - j0 + 1;
-    const int total = rows > 0 ? rows * w : 0;
+    const int total = (rows > 0 && w > 0) ? rows * w : 0;
     double s = 0.0;
     for (int t = tid; t < total; t += blockDim.x) {
         const int jj = j0 + t / w;
@@ -404,7 +451,7 @@ __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_vel
         bs->A[b] = s;
         // this bead's share of the next support window and its health bits
         int* nw = bs->win[win_out];
-        if (isfinite(Rx) && isfinite(Ry)) {
+        if (bead_sane(Rx, Ry)) {
             atomicMin(&nw[0], (int)floor(Rx - 0.5 - fib.rc));
             atomicMax(&nw[1], (int)ceil(Rx - 0.5 + fib.rc));
             atomicMin(&nw[2], (int)floor(Ry - 0.5 - fib.rc));
@@ -420,14 +467,38 @@ __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_vel
     }
 }
 
+template <int ST>
+__global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_velocity,
+                                                          int win_out) {
+    __shared__ double scratch[kBeadBlock / 64];
+    __shared__ double s_R[2];
+    bead_block<ST>(a, blockIdx.x, do_velocity, win_out, scratch, s_R);
+}
+
+// Persistent bead kernel over a batch: (simulation, bead) items in a static stride.
+template <int ST>
+__global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
+    __shared__ double scratch[kBeadBlock / 64];
+    __shared__ double s_R[2];
+    const int n = b.counts[0], total = b.counts[2];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int s = find_sim(b.bead_off, n, item);
+        const StepArgs a = load_args(b.args, 2 * s + b.gpar);
+        bead_block<ST>(a, item - b.bead_off[s], 1, 1 - a.parity, scratch, s_R);
+        __syncthreads();
+    }
+}
+
 // Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same
 // values for the beads near its tiles).
 __global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
+    __shared__ Bonds B;
     const Fiber& fib = a.fib;
     BeadState* bs = fib.bs;
+    fill_bonds(bs, fib.n, B);
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
-        bead_force(bs, fib.n, t, fib.ks_l02, fib.l0, fib.kb, F);
+        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, F);
         bs->F[t][0] = F[0];
         bs->F[t][1] = F[1];
         bs->C[t][0] = F[0] / bs->A[t];
@@ -612,6 +683,32 @@ hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_
     return hipGetLastError();
 }
 
+template <int ST>
+static hipError_t launch_batch_t(const BatchArgs& b, dim3 block, int spt, int grid_lat,
+                                 int grid_bead, hipStream_t st) {
+    switch (spt) {
+        case 1: hipLaunchKernelGGL((batch_step_kernel<ST, 1>), dim3(grid_lat), block, 0, st, b); break;
+        case 2: hipLaunchKernelGGL((batch_step_kernel<ST, 2>), dim3(grid_lat), block, 0, st, b); break;
+        case 4: hipLaunchKernelGGL((batch_step_kernel<ST, 4>), dim3(grid_lat), block, 0, st, b); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_bead_kernel<ST>), dim3(grid_bead), dim3(kBeadBlock), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int spt,
+                             int grid_lat, int grid_bead, hipStream_t st) {
+    switch (storage) {
+        case FPD_F64: return launch_batch_t<FPD_F64>(b, block, spt, grid_lat, grid_bead, st);
+        case FPD_F32: return launch_batch_t<FPD_F32>(b, block, spt, grid_lat, grid_bead, st);
+        case FPD_F16DEV: return launch_batch_t<FPD_F16DEV>(b, block, spt, grid_lat, grid_bead, st);
+        case FPD_BF16DEV: return launch_batch_t<FPD_BF16DEV>(b, block, spt, grid_lat, grid_bead, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_forces(const StepArgs& a, hipStream_t st) {
     if (a.fib.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(forces_kernel, dim3(1), dim3(kBeadThreads), 0, st, a);
@@ -669,6 +766,21 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
     const size_t n = bytes / 16;
     hipLaunchKernelGGL(copy_kernel, dim3(256 * 32), dim3(256), 0, st, (const float4*)src,
                        (float4*)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace fpd
+
+namespace fpd {
+
+__global__ void health_gather_kernel(BeadState* const* states, unsigned* out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = states[i] ? states[i]->health : 0u;
+}
+
+hipError_t health_gather(BeadState* const* states, unsigned* out, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(health_gather_kernel, dim3((n + 255) / 256), dim3(256), 0, st, states, out, n);
     return hipGetLastError();
 }
 

@@ -117,9 +117,7 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.kb = s->p.k_b;
     const fpd_launch& c = s->launch;
     a.rows_per_block = c.block_y * c.rows_per_thread;
-    a.x_chunks = c.x_chunks;
-    const int tile_w = c.block_x * c.x_chunks;
-    a.tiles_x = (s->L.nx + tile_w - 1) / tile_w;
+    a.tiles_x = (s->L.nx + c.block_x - 1) / c.block_x;
     const int tiles_y = (s->L.ny + a.rows_per_block - 1) / a.rows_per_block;
     a.n_tiles = a.tiles_x * tiles_y;
     a.xcd_remap = c.xcd_remap == 1 ? 1 : 0;
@@ -287,8 +285,8 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
     // measured on MI355X (8192 x 2048): 256 x 1 for 2- and 4-byte storage, 128 x 2 for
     // float64, one row per thread, default block order (no XCD remap)
-    s->launch = p->storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 64, 1}
-                                      : fpd_launch{256, 1, 1, 2, 64, 1};
+    s->launch = p->storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 64}
+                                      : fpd_launch{256, 1, 1, 2, 64};
     auto bail = [&](int code) {
         fpd_destroy(s);
         return code;
@@ -639,7 +637,6 @@ int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
     if (c->rows_per_thread > 0) n.rows_per_thread = c->rows_per_thread;
     if (c->xcd_remap > 0) n.xcd_remap = c->xcd_remap;
     if (c->graph_chunk > 0) n.graph_chunk = c->graph_chunk;
-    if (c->x_chunks > 0) n.x_chunks = c->x_chunks;
     if (n.block_x != 64 && n.block_x != 128 && n.block_x != 256)
         return fail(FPD_EINVAL, "block_x must be 64, 128 or 256");
     if (n.block_y != 1 && n.block_y != 2 && n.block_y != 4)
@@ -649,7 +646,6 @@ int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
         return fail(FPD_EINVAL, "rows_per_thread must be 1, 2 or 4");
     if (n.graph_chunk < 2 || (n.graph_chunk & 1))
         return fail(FPD_EINVAL, "graph_chunk must be even and >= 2");
-    if (n.x_chunks < 1 || n.x_chunks > 32) return fail(FPD_EINVAL, "x_chunks must be in 1..32");
     int rc = sync_check(s);
     if (rc) return rc;
     s->launch = n;
@@ -777,6 +773,415 @@ int fpd_load(fpd_sim* s, const char* path) {
     HIP_TRY(hipMemcpy(s->bs, &h, sizeof h, hipMemcpyHostToDevice));
     s->steps = steps;
     s->fiber = fib != 0;
+    return FPD_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== batches ====
+
+namespace {
+
+struct BatchEntry {
+    fpd_sim* sim = nullptr;
+    int64_t id = 0;
+    int64_t remaining = 0;
+    int status = FPD_SIM_ACTIVE;
+    bool reported = false;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct fpd_batch {
+    size_t budget = 0, used = 0;
+    int max_slots = 0, storage = FPD_F32;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    fpd_launch launch{};
+    std::vector<BatchEntry> entries;
+    int64_t next_id = 1;
+    // device work tables and their pinned host mirrors
+    StepArgs* d_args = nullptr;
+    int* d_tile_off = nullptr;
+    int* d_bead_off = nullptr;
+    int* d_counts = nullptr;
+    BeadState** d_states = nullptr;
+    unsigned* d_health = nullptr;
+    StepArgs* h_args = nullptr;
+    int* h_tile_off = nullptr;
+    int* h_bead_off = nullptr;
+    int* h_counts = nullptr;
+    BeadState** h_states = nullptr;
+    unsigned* h_health = nullptr;
+    std::vector<int> table;  // entry index of table row r
+    bool dirty = true;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+    int grid_lat = 0, grid_bead = 0;
+};
+
+namespace {
+
+void batch_drop_graph(fpd_batch* b) {
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->graph_chunk = 0;
+}
+
+BatchEntry* find_entry(fpd_batch* b, int64_t id) {
+    for (auto& e : b->entries)
+        if (e.id == id) return &e;
+    return nullptr;
+}
+
+size_t footprint_of(const fpd_params* p) {
+    const size_t pop = fpd_population_bytes(p);
+    size_t rect = 0;
+    if (p->n_beads > 0) {
+        const double rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
+        const double span = 1.5 * (p->n_beads - 1) * p->l0 + 2.0 * rc + 4.0;
+        const size_t w = (size_t)fmin(ceil(span), (double)p->nx);
+        const size_t h = (size_t)fmin(ceil(span), (double)p->ny);
+        rect = w * h * 2 * (p->storage == FPD_F64 ? 8 : 4);
+    }
+    return 2 * pop + rect + sizeof(BeadState);
+}
+
+// Rebuild the work tables for the active simulations (call with the stream idle).
+int batch_rebuild(fpd_batch* b) {
+    b->table.clear();
+    int tiles = 0, beads = 0, r = 0;
+    b->h_tile_off[0] = 0;
+    b->h_bead_off[0] = 0;
+    for (size_t i = 0; i < b->entries.size(); ++i) {
+        BatchEntry& e = b->entries[i];
+        if (e.status != FPD_SIM_ACTIVE || e.remaining <= 0) continue;
+        fpd_sim* s = e.sim;
+        b->h_args[2 * r] = make_args(s, s->cur);
+        b->h_args[2 * r + 1] = make_args(s, 1 - s->cur);
+        tiles += b->h_args[2 * r].n_tiles;
+        beads += b->h_args[2 * r].fib.n;
+        b->h_tile_off[r + 1] = tiles;
+        b->h_bead_off[r + 1] = beads;
+        b->h_states[r] = s->bs;
+        b->table.push_back((int)i);
+        ++r;
+    }
+    b->h_counts[0] = r;
+    b->h_counts[1] = tiles;
+    b->h_counts[2] = beads;
+    if (r > 0) {
+        HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(StepArgs) * 2 * r,
+                               hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->d_tile_off, b->h_tile_off, sizeof(int) * (r + 1),
+                               hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->d_bead_off, b->h_bead_off, sizeof(int) * (r + 1),
+                               hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->d_states, b->h_states, sizeof(BeadState*) * r,
+                               hipMemcpyHostToDevice, b->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_counts, b->h_counts, sizeof(int) * 3, hipMemcpyHostToDevice,
+                           b->stream));
+    b->dirty = false;
+    return FPD_OK;
+}
+
+int batch_enqueue(fpd_batch* b, int gpar) {
+    BatchArgs a{b->d_args, b->d_tile_off, b->d_bead_off, b->d_counts, gpar};
+    const dim3 block(b->launch.block_x, b->launch.block_y);
+    HIP_TRY(launch_batch_step(b->storage, a, block, b->launch.rows_per_thread, b->grid_lat,
+                              b->grid_bead, b->stream));
+    return FPD_OK;
+}
+
+int batch_build_graph(fpd_batch* b, int chunk) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = FPD_OK;
+    for (int i = 0; i < chunk && rc == FPD_OK; ++i) rc = batch_enqueue(b, i & 1);
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc != FPD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "batch graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
+    b->graph_chunk = chunk;
+    return FPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fpd_sim_footprint(const fpd_params* p) {
+    if (!p || validate(p) != FPD_OK) return 0;
+    return footprint_of(p);
+}
+
+int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage,
+                     void* hip_stream, fpd_batch** out) {
+    if (!out) return fail(FPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 4096) return fail(FPD_EINVAL, "max_slots must be in 1..4096");
+    if (storage_elem(storage) == 0) return fail(FPD_EINVAL, "unknown storage %d", storage);
+    fpd_batch* b = new fpd_batch();
+    b->budget = hbm_budget_bytes;
+    b->max_slots = max_slots;
+    b->storage = storage;
+    b->launch = storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 32} : fpd_launch{256, 1, 1, 2, 32};
+    auto bail = [&](int code) {
+        fpd_batch_destroy(b);
+        return code;
+    };
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(FPD_EDEVICE, "hipStreamCreate failed"));
+        b->own_stream = true;
+    }
+    const size_t n = (size_t)max_slots;
+    bool ok = hipMalloc((void**)&b->d_args, sizeof(StepArgs) * 2 * n) == hipSuccess &&
+              hipMalloc((void**)&b->d_tile_off, sizeof(int) * (n + 1)) == hipSuccess &&
+              hipMalloc((void**)&b->d_bead_off, sizeof(int) * (n + 1)) == hipSuccess &&
+              hipMalloc((void**)&b->d_counts, sizeof(int) * 3) == hipSuccess &&
+              hipMalloc((void**)&b->d_states, sizeof(BeadState*) * n) == hipSuccess &&
+              hipMalloc((void**)&b->d_health, sizeof(unsigned) * n) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_args, sizeof(StepArgs) * 2 * n, 0) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_tile_off, sizeof(int) * (n + 1), 0) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_bead_off, sizeof(int) * (n + 1), 0) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_counts, sizeof(int) * 3, 0) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_states, sizeof(BeadState*) * n, 0) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_health, sizeof(unsigned) * n, 0) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return bail(fail(FPD_ENOMEM, "batch table allocation failed"));
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return bail(fail(FPD_EDEVICE, "device query failed"));
+    b->grid_lat = cus * 8;   // 256-thread blocks: up to 8 per CU
+    b->grid_bead = cus * 2;  // 1024-thread blocks: 2 per CU
+    int rc = batch_rebuild(b);
+    if (rc) return bail(rc);
+    *out = b;
+    return FPD_OK;
+}
+
+void fpd_batch_destroy(fpd_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (auto& e : b->entries) fpd_destroy(e.sim);
+    b->entries.clear();
+    (void)hipFree(b->d_args);
+    (void)hipFree(b->d_tile_off);
+    (void)hipFree(b->d_bead_off);
+    (void)hipFree(b->d_counts);
+    (void)hipFree(b->d_states);
+    (void)hipFree(b->d_health);
+    (void)hipHostFree(b->h_args);
+    (void)hipHostFree(b->h_tile_off);
+    (void)hipHostFree(b->h_bead_off);
+    (void)hipHostFree(b->h_counts);
+    (void)hipHostFree(b->h_states);
+    (void)hipHostFree(b->h_health);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int fpd_batch_set_launch(fpd_batch* b, const fpd_launch* c) {
+    if (!b || !c) return fail(FPD_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (auto& e : b->entries) {
+        int rc = fpd_set_launch(e.sim, c);
+        if (rc) return rc;
+    }
+    fpd_launch n = b->launch;
+    if (c->block_x > 0) n.block_x = c->block_x;
+    if (c->block_y > 0) n.block_y = c->block_y;
+    if (c->rows_per_thread > 0) n.rows_per_thread = c->rows_per_thread;
+    if (c->xcd_remap > 0) n.xcd_remap = c->xcd_remap;
+    if (c->graph_chunk > 0) n.graph_chunk = c->graph_chunk;
+    if (n.block_x * n.block_y > 256 || (n.graph_chunk & 1) || n.graph_chunk < 2)
+        return fail(FPD_EINVAL, "invalid batch launch");
+    b->launch = n;
+    batch_drop_graph(b);
+    b->dirty = true;
+    return FPD_OK;
+}
+
+int fpd_batch_add(fpd_batch* b, const fpd_params* p, const double* R, int64_t n_steps,
+                  int64_t* sim_id) {
+    if (!b || !p || !sim_id) return fail(FPD_EINVAL, "NULL argument");
+    if (n_steps < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
+    int rc = validate(p);
+    if (rc) return rc;
+    if (p->storage != b->storage) return fail(FPD_EINVAL, "storage differs from the batch's");
+    if (p->n_beads > 0 && !R) return fail(FPD_EINVAL, "bead positions are required");
+    const size_t need = footprint_of(p);
+    if ((int)b->entries.size() >= b->max_slots) return fail(FPD_ENOMEM, "no free slot");
+    if (b->used + need > b->budget)
+        return fail(FPD_ENOMEM, "HBM budget: %zu + %zu > %zu bytes", b->used, need, b->budget);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    fpd_sim* s = nullptr;
+    rc = create_impl(p, b->stream, nullptr, nullptr, 0, &s);
+    if (rc) return rc;
+    rc = fpd_set_launch(s, &b->launch);
+    if (rc == FPD_OK && p->n_beads > 0) rc = fpd_init_fiber(s, R);
+    if (rc) {
+        fpd_destroy(s);
+        return rc;
+    }
+    BatchEntry e;
+    e.sim = s;
+    e.id = b->next_id++;
+    e.remaining = n_steps;
+    e.status = n_steps == 0 ? FPD_SIM_DONE : FPD_SIM_ACTIVE;
+    e.bytes = need;
+    b->entries.push_back(e);
+    b->used += need;
+    b->dirty = true;
+    *sim_id = e.id;
+    return FPD_OK;
+}
+
+int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
+    if (!b) return fail(FPD_EINVAL, "NULL batch");
+    if (advanced) *advanced = 0;
+    if (max_steps <= 0) return FPD_OK;
+    int64_t steps = max_steps;
+    int active = 0;
+    for (auto& e : b->entries)
+        if (e.status == FPD_SIM_ACTIVE && e.remaining > 0) {
+            ++active;
+            if (e.remaining < steps) steps = e.remaining;
+        }
+    if (active == 0) return FPD_OK;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (b->dirty) {
+        int rc = batch_rebuild(b);
+        if (rc) return rc;
+    }
+    int64_t left = steps;
+    const int chunk = b->launch.graph_chunk;
+    if (left >= chunk) {
+        if (b->graph_chunk != chunk) {
+            batch_drop_graph(b);
+            int rc = batch_build_graph(b, chunk);
+            if (rc) return rc;
+        }
+        while (left >= chunk) {
+            HIP_TRY(hipGraphLaunch(b->graph, b->stream));
+            left -= chunk;
+        }
+    }
+    for (int i = 0; left > 0; --left, ++i) {
+        int rc = batch_enqueue(b, i & 1);
+        if (rc) return rc;
+    }
+    // bookkeeping and health
+    const int rows = (int)b->table.size();
+    HIP_TRY(health_gather(b->d_states, b->d_health, rows, b->stream));
+    if (rows > 0)
+        HIP_TRY(hipMemcpyAsync(b->h_health, b->d_health, sizeof(unsigned) * rows,
+                               hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int r = 0; r < rows; ++r) {
+        BatchEntry& e = b->entries[b->table[r]];
+        e.remaining -= steps;
+        e.sim->steps += steps;
+        if (steps & 1) e.sim->cur ^= 1;
+        if (b->h_health[r]) {
+            e.status = FPD_SIM_FAILED;
+        } else if (e.remaining == 0) {
+            e.status = FPD_SIM_DONE;
+        }
+        if (e.status != FPD_SIM_ACTIVE) b->dirty = true;
+    }
+    if (steps & 1) b->dirty = true;
+    if (advanced) *advanced = steps;
+    return FPD_OK;
+}
+
+int fpd_batch_poll(fpd_batch* b, int64_t* ids, int32_t* status, int32_t cap, int32_t* n) {
+    if (!b || !n) return fail(FPD_EINVAL, "NULL argument");
+    int k = 0;
+    for (auto& e : b->entries) {
+        if (k >= cap) break;
+        if (e.status != FPD_SIM_ACTIVE && !e.reported) {
+            if (ids) ids[k] = e.id;
+            if (status) status[k] = e.status;
+            e.reported = true;
+            ++k;
+        }
+    }
+    *n = k;
+    return FPD_OK;
+}
+
+int fpd_batch_read_beads(fpd_batch* b, int64_t id, double* R, double* V, double* F) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    return fpd_read_beads(e->sim, R, V, F);
+}
+
+int fpd_batch_read_populations(fpd_batch* b, int64_t id, double* f) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    return fpd_read_populations(e->sim, f);
+}
+
+int fpd_batch_read_fields(fpd_batch* b, int64_t id, double* rho, double* ux, double* uy,
+                          double* eta) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    return fpd_read_fields(e->sim, rho, ux, uy, eta);
+}
+
+int fpd_batch_sim_info(fpd_batch* b, int64_t id, int64_t* steps, int32_t* status,
+                       uint32_t* health) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    if (steps) *steps = e->sim->steps;
+    if (status) *status = e->status;
+    if (health) {
+        double ms;
+        int rc = fpd_health(e->sim, health, &ms);
+        if (rc) return rc;
+    }
+    return FPD_OK;
+}
+
+int fpd_batch_release(fpd_batch* b, int64_t id) {
+    if (!b) return fail(FPD_EINVAL, "NULL batch");
+    for (size_t i = 0; i < b->entries.size(); ++i)
+        if (b->entries[i].id == id) {
+            HIP_TRY(hipStreamSynchronize(b->stream));
+            fpd_destroy(b->entries[i].sim);
+            b->used -= b->entries[i].bytes;
+            b->entries.erase(b->entries.begin() + (long)i);
+            b->dirty = true;
+            return FPD_OK;
+        }
+    return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+}
+
+int fpd_batch_stats(fpd_batch* b, int32_t* active, int32_t* held, size_t* bytes_in_use) {
+    if (!b) return fail(FPD_EINVAL, "NULL batch");
+    int a = 0;
+    for (auto& e : b->entries)
+        if (e.status == FPD_SIM_ACTIVE) ++a;
+    if (active) *active = a;
+    if (held) *held = (int)b->entries.size();
+    if (bytes_in_use) *bytes_in_use = b->used;
     return FPD_OK;
 }
 

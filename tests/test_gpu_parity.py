@@ -182,8 +182,8 @@ LAUNCHES = [
     dict(block_x=128, block_y=2, rows_per_thread=2, xcd_remap=2),
     dict(block_x=256, block_y=1, rows_per_thread=4, xcd_remap=1),
     dict(block_x=64, block_y=1, rows_per_thread=2, xcd_remap=2),
-    dict(block_x=64, block_y=2, rows_per_thread=1, xcd_remap=2, x_chunks=3),
-    dict(block_x=256, block_y=1, rows_per_thread=1, xcd_remap=1, x_chunks=8),
+    dict(block_x=256, block_y=1, rows_per_thread=1, xcd_remap=2),
+    dict(block_x=128, block_y=2, rows_per_thread=1, xcd_remap=2),
 ]
 
 
