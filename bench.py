@@ -9,6 +9,14 @@ near the fiber) and the per-bead kernel (Eq. 5 reduction, Euler update, A_i, for
 Prints ONE JSON line with MLUPS (whole step, inputs resident in HBM), the lattice kernel's
 HBM roofline (algorithmic 18 * sizeof(population) bytes per node per step over its event
 time) and a CPU baseline (the FP64 oracle on a bounded sample of the same workload).
+
+Other modes (each prints one JSON line):
+  --mode batch   256 parameter-sweep simulations (uneven lattices 128x64..1024x512, 5-30
+                 beads) advanced together by the persistent batch kernels, against the plain
+                 path (the same simulations one at a time, per-step launches, no graph);
+  --mode serve   Poisson arrivals (50 requests/s) of sweep simulations served with
+                 continuous batching in FP16/BF16 deviation storage: p50/p99 time-to-result
+                 and simulations per second, against a single-simulation FIFO server.
 """
 from __future__ import annotations
 
@@ -87,6 +95,148 @@ def cpu_baseline(w, steps):
     }
 
 
+def sweep_params(_lib, ws, storage, steps_override=None):
+    return [_lib.params_from_mapping(w.params(), storage=storage) for w in ws]
+
+
+def run_plain_path(_lib, ws, storage, steps, stream):
+    """The plain path: one simulation at a time, one launch per kernel, no graph."""
+    times, finals = [], []
+    for w in ws:
+        sim = _lib.simulation_from_workload(w, storage=storage, stream=stream,
+                                            flags=_lib.FPD_FLAG_NO_GRAPH)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        times.append(time.perf_counter() - t0)
+        finals.append(sim.beads()[0])
+        sim.close()
+    return times, finals
+
+
+def main_batch(args):
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2212_14153_amd import _lib, autotune
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    storage = args.storage
+    ws = workloads.sweep_sims(args.sims, steps=args.sweep_steps, storage=storage)
+    params = sweep_params(_lib, ws, storage)
+    nodes = sum(w.nx * w.ny for w in ws)
+    budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
+    log(f"batch: {len(ws)} simulations, {nodes / 1e6:.1f}M nodes, {args.sweep_steps} steps "
+        f"each, storage {storage}, {budget / 1e9:.2f} GB")
+
+    def make_batch():
+        b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
+        for p, w in zip(params, ws):
+            b.add(p, w.beads(), 1 << 40)
+        return b
+
+    cfg, table = (None, None)
+    if not args.no_autotune:
+        cfg, table = autotune.tune_batch(make_batch, storage, nodes)
+        log(f"autotuned launch {cfg}")
+    b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
+    if cfg:
+        b.set_launch(dict(cfg, graph_chunk=32))
+    ids = [b.add(p, w.beads(), args.sweep_steps) for p, w in zip(params, ws)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    finish = {}
+    while len(finish) < len(ids):
+        if b.run(args.sweep_steps) == 0:
+            break
+        t = time.perf_counter() - t0
+        for sid, st in b.poll():
+            finish[sid] = (t, st)
+    wall = time.perf_counter() - t0
+    ok = sum(1 for t, st in finish.values() if st == _lib.FPD_SIM_DONE)
+    k = min(args.plain_sims, len(ws))
+    batch_R = [b.beads(sid)[0] for sid in ids[:k]]
+    b.close()
+    log(f"batched: {wall:.2f} s for {len(ids)} simulations ({ok} done)")
+    plain_t, plain_R = run_plain_path(_lib, ws[:k], storage, args.sweep_steps, stream.cuda_stream)
+    plain_per_sim = float(np.mean(plain_t))
+    diff = max(float(np.max(np.abs(a - c))) for a, c in zip(batch_R, plain_R))
+    lat = np.array([t for t, _ in finish.values()])
+    out = {
+        "metric": "batched sims/s", "value": round(ok / wall, 3), "unit": "sims/s",
+        "n_gpus": 1, "steps": args.sweep_steps, "warmup": 0, "ms_per_step": round(wall / args.sweep_steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": storage,
+        "data": "synthetic",
+        "config": {"workload": f"sweep of {len(ws)} simulations (seed 14153), {args.sweep_steps} steps each",
+                   "nodes_total": nodes, "launch": cfg, "parallelism": "single GPU"},
+        "aggregate_mlups": round(nodes * args.sweep_steps / wall / 1e6, 1),
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "plain_path": {"sims_per_s": round(1.0 / plain_per_sim, 3), "sample_sims": k,
+                       "seconds_per_sim": round(plain_per_sim, 4)},
+        "speedup_vs_plain": round((ok / wall) * plain_per_sim, 2),
+        "max_bead_diff_vs_plain_lu": diff,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main_serve(args):
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2212_14153_amd import _lib, autotune, serve
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    storage = args.storage if args.storage in ("f16dev", "bf16dev") else "f16dev"
+    n_req = args.requests + args.serve_warmup
+    ws = workloads.sweep_sims(n_req, seed=50, steps=args.sweep_steps, storage=storage)
+    arrivals = workloads.poisson_arrivals(n_req, rate=args.rate, seed=50)
+    params = sweep_params(_lib, ws, storage)
+    reqs = [serve.Request(i, p, w.beads(), args.sweep_steps, float(t))
+            for i, (p, w, t) in enumerate(zip(params, ws, arrivals))]
+    log(f"serve: {n_req} requests at {args.rate}/s ({args.serve_warmup} warm-up), "
+        f"{args.sweep_steps} steps each, storage {storage}")
+    srv = serve.Server(storage, hbm_budget=args.hbm_budget_gb << 30, max_slots=args.slots,
+                       chunk=args.chunk, stream=stream.cuda_stream,
+                       launch=dict(graph_chunk=32))
+    done = srv.serve(reqs)
+    srv.close()
+    summ = serve.summarize(done, warmup=args.serve_warmup)
+    log(f"served: p50 {summ['p50_s']:.2f} s, p99 {summ['p99_s']:.2f} s, "
+        f"{summ['sims_per_s']:.1f} sims/s")
+    # plain path: measured service times of a sample, a FIFO single-simulation server replayed
+    # on the same arrivals with service time linear in nodes x steps
+    k = min(args.plain_sims, len(ws))
+    pt, pR = run_plain_path(_lib, ws[:k], storage, args.sweep_steps, stream.cuda_stream)
+    sizes = np.array([w.nx * w.ny for w in ws[:k]], dtype=float)
+    A = np.stack([np.ones(k), sizes], axis=1)
+    coef, *_ = np.linalg.lstsq(A, np.array(pt), rcond=None)
+    svc = coef[0] + coef[1] * np.array([w.nx * w.ny for w in ws], dtype=float)
+    lat_plain = serve.fifo_replay(arrivals, svc)[args.serve_warmup:]
+    # alone vs in the mix: the served results of the sampled requests equal the plain runs
+    by_id = {r.rid: r for r in done}
+    diff = max(float(np.max(np.abs(by_id[i].beads - pR[i]))) for i in range(k))
+    out = {
+        "metric": "served sims/s at p50/p99 time-to-result", "value": round(summ["sims_per_s"], 3),
+        "unit": "sims/s", "n_gpus": 1, "steps": args.sweep_steps, "warmup": args.serve_warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": storage, "data": "synthetic",
+        "config": {"workload": f"Poisson {args.rate}/s sweep requests (seed 50), {args.sweep_steps} steps",
+                   "requests": args.requests, "chunk": args.chunk, "slots": args.slots,
+                   "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
+        "p50_s": round(summ["p50_s"], 3), "p99_s": round(summ["p99_s"], 3),
+        "mean_s": round(summ["mean_s"], 3), "span_s": round(summ["span_s"], 2),
+        "completed": summ["completed"],
+        "plain_path": {"p50_s": round(float(np.percentile(lat_plain, 50)), 3),
+                       "p99_s": round(float(np.percentile(lat_plain, 99)), 3),
+                       "sims_per_s": round(1.0 / float(np.mean(svc)), 3),
+                       "service_model": "FIFO replay, service time fitted on "
+                                        f"{k} measured single-simulation runs"},
+        "max_bead_diff_alone_vs_mix_lu": diff,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +247,17 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--sims", type=int, default=256)
+    ap.add_argument("--sweep-steps", type=int, default=20000)
+    ap.add_argument("--plain-sims", type=int, default=8)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--slots", type=int, default=512)
+    ap.add_argument("--chunk", type=int, default=200)
+    ap.add_argument("--hbm-budget-gb", type=int, default=64)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -105,6 +266,10 @@ def main():
               f"{world}); independent simulations shard across GPUs with no exchange, and "
               "no multi-GPU figure is produced here.", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        return main_batch(args)
+    if args.mode == "serve":
+        return main_serve(args)
 
     import torch
     from paper_2212_14153_amd import _lib

@@ -1,0 +1,128 @@
+"""Continuous-batching server for parameter-sweep simulations.
+
+Requests (a simulation's parameters, its initial fiber and a step count) arrive over time.
+The loop keeps one device batch (``Batch``, the C ABI's fpd_batch): whenever slots and HBM
+budget allow, waiting requests are admitted between chunks of steps, so work that arrives
+while others run overlaps with them on the device; finished simulations are read back and
+released at once, which frees room for the next ones.  Each result is bitwise the result of
+the same simulation run alone (per-simulation arithmetic does not depend on the mix).
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+
+
+@dataclass
+class Request:
+    rid: int
+    params: object                 # _lib.fpd_params
+    R: np.ndarray                  # initial bead positions [N, 2]
+    steps: int
+    arrival: float                 # seconds since the server started
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    status: int = -1
+    beads: np.ndarray = field(default=None)   # final R
+    sim_id: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """Admission by slots and HBM footprint; chunked execution; read-back on completion."""
+
+    def __init__(self, storage: str, hbm_budget: int, max_slots: int, chunk: int = 200,
+                 stream=None, launch=None, clock=time.perf_counter, batch=None):
+        # `batch` may be any object with the Batch methods used below (try_add, run, poll,
+        # beads, release, set_launch, close); by default the device batch of the C ABI
+        self.batch = batch if batch is not None else _lib.Batch(hbm_budget, max_slots,
+                                                                 storage=storage, stream=stream)
+        if launch:
+            self.batch.set_launch(launch)
+        self.chunk = int(chunk)
+        self.clock = clock
+        self.t0 = None
+        self.waiting = collections.deque()
+        self.running = {}
+        self.done = []
+
+    def close(self):
+        self.batch.close()
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def _admit(self):
+        while self.waiting:
+            req = self.waiting[0]
+            sid = self.batch.try_add(req.params, req.R, req.steps)
+            if sid is None:
+                if not self.running:
+                    raise RuntimeError(f"request {req.rid} does not fit an empty batch")
+                break
+            self.waiting.popleft()
+            req.sim_id = sid
+            req.admitted = self.now()
+            self.running[sid] = req
+
+    def _collect(self):
+        for sid, status in self.batch.poll():
+            req = self.running.pop(sid)
+            req.status = status
+            if status == _lib.FPD_SIM_DONE:
+                req.beads = self.batch.beads(sid)[0]
+            req.finished = self.now()
+            self.batch.release(sid)
+            self.done.append(req)
+
+    def serve(self, requests, idle_sleep: float = 1e-3):
+        """Serve `requests` (sorted by arrival time, seconds from start) to completion;
+        returns them with admission and finish times filled in."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        total = len(pending)
+        self.t0 = self.clock()
+        while len(self.done) < total:
+            t = self.now()
+            while pending and pending[0].arrival <= t:
+                self.waiting.append(pending.popleft())
+            self._admit()
+            if self.running:
+                self.batch.run(self.chunk)
+                self._collect()
+            elif pending:
+                time.sleep(min(idle_sleep, max(0.0, pending[0].arrival - self.now())))
+        return self.done
+
+
+def summarize(reqs, warmup: int = 0) -> dict:
+    """p50 / p99 time-to-result and throughput over the requests after the first `warmup`
+    arrivals."""
+    reqs = sorted(reqs, key=lambda r: r.arrival)[warmup:]
+    lat = np.array([r.latency for r in reqs])
+    t_first = min(r.arrival for r in reqs)
+    t_last = max(r.finished for r in reqs)
+    ok = sum(1 for r in reqs if r.status == _lib.FPD_SIM_DONE)
+    return {
+        "requests": len(reqs), "completed": ok,
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "mean_s": float(lat.mean()), "sims_per_s": ok / (t_last - t_first),
+        "span_s": t_last - t_first,
+    }
+
+
+def fifo_replay(arrivals, service_times) -> np.ndarray:
+    """Finish-minus-arrival times of a single FIFO server with the given service times."""
+    t = 0.0
+    out = []
+    for a, s in zip(arrivals, service_times):
+        t = max(t, a) + s
+        out.append(t - a)
+    return np.array(out)
