@@ -10,7 +10,9 @@ namespace fpd {
 
 constexpr int kMaxBeads = FPD_MAX_BEADS;
 constexpr int kBeadThreads = 256;   // finish kernel (one thread per bead)
-constexpr int kBeadBlock = 1024;    // bead kernel (one block per bead)
+// Bead kernels (single and batched) use one block size: the per-bead FP64 reduction tree
+// follows it, so a simulation's bead velocities are bitwise the same alone and in a batch.
+constexpr int kBeadBlock = 256;
 
 // Device-resident fiber state, float64 (bead integration and reductions stay in FP64
 // whatever the population storage).

@@ -217,8 +217,16 @@ struct TileLds {
 // One tile (block_x nodes on rows_per_block rows) of one simulation.
 // Must be reached by every thread of the block (it synchronises when the tile meets the
 // fiber).  The tile numbered 0 also resets the window slot the bead kernel fills next.
+// The fiber's support window for this step (empty without a fiber).
+__device__ inline Window tile_window(const StepArgs& a) {
+    if (a.fib.n <= 0) return Window{0, 0, 0, 0, false};
+    return decode_window(a.fib.bs->win[a.parity], a.L.nx, a.L.ny, a.fib.rect_wmax,
+                         a.fib.rect_hmax);
+}
+
 template <int ST, int SPT>
-__device__ inline void lattice_tile(const StepArgs& a, int tile, TileLds& lds) {
+__device__ inline void lattice_tile(const StepArgs& a, const Window& win, int tile,
+                                    TileLds& lds) {
     using Cd = Codec<ST>;
     using T = typename Cd::T;
     using S = typename Cd::store_t;
@@ -244,8 +252,6 @@ __device__ inline void lattice_tile(const StepArgs& a, int tile, TileLds& lds) {
     bool fiber_tile = false;
     if (a.fib.n > 0) {
         BeadState* bs = a.fib.bs;
-        const Window win = decode_window(bs->win[a.parity], nx, ny, a.fib.rect_wmax,
-                                         a.fib.rect_hmax);
         wx0 = win.x0;
         wy0 = win.y0;
         ww = win.w;
@@ -313,7 +319,7 @@ template <int ST, int SPT>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ TileLds lds;
     const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    lattice_tile<ST, SPT>(a, tile, lds);
+    lattice_tile<ST, SPT>(a, tile_window(a), tile, lds);
 }
 
 // Index of the simulation that owns work item `item`: the largest s with off[s] <= item.
@@ -337,16 +343,29 @@ __device__ inline StepArgs load_args(const StepArgs* table, int i) {
     return a;
 }
 
-// Persistent lattice kernel over a batch of simulations of different sizes: a fixed grid
-// walks the (simulation, tile) items in a static stride (no queue, no waiting).
+// Persistent lattice kernel over a batch of simulations of different sizes.  Block b owns
+// the contiguous run of (simulation, tile) items [b*per, (b+1)*per): no queue, no waiting,
+// and the per-simulation state (arguments, window) is loaded only when the run crosses into
+// the next simulation.
 template <int ST, int SPT>
 __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     __shared__ TileLds lds;
     const int n = b.counts[0], total = b.counts[1];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int s = find_sim(b.tile_off, n, item);
-        const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-        lattice_tile<ST, SPT>(a, item - b.tile_off[s], lds);
+    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int begin = (int)blockIdx.x * per;
+    const int end = min(total, begin + per);
+    int s_off = 0, s_end = 0;
+    StepArgs a;
+    Window win{0, 0, 0, 0, false};
+    for (int item = begin; item < end; ++item) {
+        if (item >= s_end) {
+            const int s = find_sim(b.tile_off, n, item);
+            s_off = b.tile_off[s];
+            s_end = b.tile_off[s + 1];
+            a = load_args(b.args, 2 * s + b.gpar);
+            win = tile_window(a);
+        }
+        lattice_tile<ST, SPT>(a, win, item - s_off, lds);
         __syncthreads();  // the LDS bead list is rebuilt by the next item
     }
 }
@@ -475,16 +494,26 @@ __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_vel
     bead_block<ST>(a, blockIdx.x, do_velocity, win_out, scratch, s_R);
 }
 
-// Persistent bead kernel over a batch: (simulation, bead) items in a static stride.
+// Persistent bead kernel over a batch: block b owns a contiguous run of (simulation, bead)
+// items.
 template <int ST>
 __global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
     __shared__ double scratch[kBeadBlock / 64];
     __shared__ double s_R[2];
     const int n = b.counts[0], total = b.counts[2];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int s = find_sim(b.bead_off, n, item);
-        const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-        bead_block<ST>(a, item - b.bead_off[s], 1, 1 - a.parity, scratch, s_R);
+    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int begin = (int)blockIdx.x * per;
+    const int end = min(total, begin + per);
+    int s_off = 0, s_end = 0;
+    StepArgs a;
+    for (int item = begin; item < end; ++item) {
+        if (item >= s_end) {
+            const int s = find_sim(b.bead_off, n, item);
+            s_off = b.bead_off[s];
+            s_end = b.bead_off[s + 1];
+            a = load_args(b.args, 2 * s + b.gpar);
+        }
+        bead_block<ST>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
         __syncthreads();
     }
 }

@@ -968,7 +968,7 @@ int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return bail(fail(FPD_EDEVICE, "device query failed"));
     b->grid_lat = cus * 8;   // 256-thread blocks: up to 8 per CU
-    b->grid_bead = cus * 2;  // 1024-thread blocks: 2 per CU
+    b->grid_bead = cus * 8;  // 256-thread blocks: 8 per CU
     int rc = batch_rebuild(b);
     if (rc) return bail(rc);
     *out = b;

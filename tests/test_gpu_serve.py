@@ -13,7 +13,6 @@ pytestmark = pytest.mark.gpu
 def test_served_results_equal_alone(storage):
     print(f"[case] serve {storage}", flush=True)
     ws = [w.with_(storage=storage) for w in workloads.sweep_sims(10, seed=5, steps=300)]
-    ws = [w.with_(nx=min(w.nx, 256), cx=min(w.nx, 256) / 2) for w in ws]  # keep it quick
     arrivals = np.linspace(0.0, 0.05, len(ws))
     reqs = [serve.Request(i, _lib.params_from_mapping(w.params(), storage=storage), w.beads(),
                           300 if i % 3 else 150, float(t))
