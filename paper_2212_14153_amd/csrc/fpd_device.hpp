@@ -127,9 +127,20 @@ __device__ inline bool cols_overlap(int c0, int cw, int i0, int w, int nx) {
     return imod(c0 - i0, nx) < w || imod(i0 - c0, nx) < cw;
 }
 
-// Minimum-image x distance, written as in the oracle's definition.
+// Minimum-image x distance dx - nx * floor(dx / nx + 1/2).  For |dx| < 3 nx / 2 the shift is
+// 0 or one period and dx -+ nx is exact (Sterbenz: the operands are within a factor of two),
+// so the compare-and-subtract below returns the same bits as the formula without a
+// division; farther images fall back to the formula.
 __device__ inline double min_image(double dx, int nx) {
-    return dx - (double)nx * floor(dx / (double)nx + 0.5);
+    const double n = (double)nx;
+    if (dx >= 0.5 * n) {
+        if (dx < 1.5 * n) return dx - n;
+    } else if (dx < -0.5 * n) {
+        if (dx >= -1.5 * n) return dx + n;
+    } else {
+        return dx;
+    }
+    return dx - n * floor(dx / n + 0.5);
 }
 
 // phi of Eq. (2): 1/2 (tanh((a - r)/xi) + 1).

@@ -63,15 +63,19 @@ struct StepArgs {
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
     int rows_per_block;       // block_y * rows_per_thread
     int xcd_remap;
+    int forces_ready;         // 1: F^n and F/A were computed by a forces kernel this step
 };
 
 // A batch step: per simulation two StepArgs (the step parities of a chunk), prefix sums of
-// lattice tiles and of beads, and counts {simulations, tiles, beads}; all in device memory
-// so that a captured graph stays valid while simulations join and leave.
+// lattice tiles and of beads, item -> simulation tables and counts {simulations, tiles,
+// beads}; all in device memory, so a captured graph stays valid while the tables are
+// rewritten with the same counts (the grids are sized from the counts at launch).
 struct BatchArgs {
     const StepArgs* args;     // [2 * n]
     const int* tile_off;      // [n + 1]
     const int* bead_off;      // [n + 1]
+    const int* tile_sim;      // [tiles]: simulation of each lattice item
+    const int* bead_sim;      // [beads]: simulation of each bead item
     const int* counts;        // [3]
     int gpar;                 // parity of this step within the chunk
 };
@@ -83,7 +87,7 @@ hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_
                        hipStream_t st);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);
 hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int rows_per_thread,
-                             int grid_lattice, int grid_bead, hipStream_t st);
+                             const int counts[3], hipStream_t st);
 hipError_t health_gather(BeadState* const* states, unsigned* out, int n, hipStream_t st);
 hipError_t launch_unstream(int storage, const Lattice& L, double u_wall, const double* f64,
                            void* dst, hipStream_t st);

@@ -156,12 +156,12 @@ __device__ inline void own_bead(const Fiber& fib, const Bonds& B, int N, int b,
 // beads run in the same order as in a full loop.
 __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, int cw, int ry0,
                                    int rh, double (*sR)[2], double (*sC)[2], int* s_wave,
-                                   Bonds& B) {
+                                   Bonds& B, bool forces_ready) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthreads = blockDim.x * blockDim.y;
     const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
     const BeadState* bs = fib.bs;
-    fill_bonds(bs, fib.n, B);
+    if (!forces_ready) fill_bonds(bs, fib.n, B);
     int total = 0;
     for (int base = 0; base < fib.n; base += nthreads) {
         const int b = base + tid;
@@ -185,18 +185,23 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, in
             chunk += s_wave[w];
         }
         if (hit) {
-            // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
-            double F[2];
-            bead_force(B, fib.n, b, fib.ks_l02, fib.l0, fib.kb, F);
-            const double A = bs->A[b];
-            const double C0 = F[0] / A, C1 = F[1] / A;
             sR[off + before][0] = Rx;
             sR[off + before][1] = Ry;
-            sC[off + before][0] = C0;
-            sC[off + before][1] = C1;
-            const int ox = imod((int)floor(Rx), nx), oy = (int)floor(Ry);
-            if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
-                own_bead(fib, B, fib.n, b, F, C0, C1);
+            if (forces_ready) {
+                sC[off + before][0] = bs->C[b][0];
+                sC[off + before][1] = bs->C[b][1];
+            } else {
+                // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
+                double F[2];
+                bead_force(B, fib.n, b, fib.ks_l02, fib.l0, fib.kb, F);
+                const double A = bs->A[b];
+                const double C0 = F[0] / A, C1 = F[1] / A;
+                sC[off + before][0] = C0;
+                sC[off + before][1] = C1;
+                const int ox = imod((int)floor(Rx), nx), oy = (int)floor(Ry);
+                if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
+                    own_bead(fib, B, fib.n, b, F, C0, C1);
+            }
         }
         total += chunk;
         __syncthreads();
@@ -270,7 +275,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
                      cols_overlap(xtile, tw, wx0, ww, nx);
         if (fiber_tile)
             nb = gather_beads(a.fib, nx, ny, xtile, tw, ytile, a.rows_per_block, sR, sC,
-                              s_wave, lds.bonds);
+                              s_wave, lds.bonds, a.forces_ready != 0);
     }
 
 #pragma unroll
@@ -322,16 +327,6 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     lattice_tile<ST, SPT>(a, tile_window(a), tile, lds);
 }
 
-// Index of the simulation that owns work item `item`: the largest s with off[s] <= item.
-__device__ inline int find_sim(const int* off, int n, int item) {
-    int lo = 0, hi = n;  // off[lo] <= item < off[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= item) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // The argument table is read-only while a batch kernel runs: viewing it in the constant
 // address space lets the per-simulation arguments come in through scalar loads.
 typedef const StepArgs __attribute__((address_space(4))) ConstStepArgs;
@@ -343,31 +338,25 @@ __device__ inline StepArgs load_args(const StepArgs* table, int i) {
     return a;
 }
 
-// Persistent lattice kernel over a batch of simulations of different sizes.  Block b owns
-// the contiguous run of (simulation, tile) items [b*per, (b+1)*per): no queue, no waiting,
-// and the per-simulation state (arguments, window) is loaded only when the run crosses into
-// the next simulation.
+typedef const int __attribute__((address_space(4))) ConstInt;
+
+// Simulation index of a work item from the lookup table (uniform: a scalar load).
+__device__ inline int item_sim(const int* table, int item) {
+    return ((const ConstInt*)table)[item];
+}
+
+// Lattice kernel over a batch of simulations of different sizes: one block per (simulation,
+// tile) item of the work table, the grid sized to the table, so the blocks resident at any
+// moment work on neighbouring tiles of one simulation as in a single-simulation launch.
 template <int ST, int SPT>
 __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     __shared__ TileLds lds;
-    const int n = b.counts[0], total = b.counts[1];
-    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int begin = (int)blockIdx.x * per;
-    const int end = min(total, begin + per);
-    int s_off = 0, s_end = 0;
-    StepArgs a;
-    Window win{0, 0, 0, 0, false};
-    for (int item = begin; item < end; ++item) {
-        if (item >= s_end) {
-            const int s = find_sim(b.tile_off, n, item);
-            s_off = b.tile_off[s];
-            s_end = b.tile_off[s + 1];
-            a = load_args(b.args, 2 * s + b.gpar);
-            win = tile_window(a);
-        }
-        lattice_tile<ST, SPT>(a, win, item - s_off, lds);
-        __syncthreads();  // the LDS bead list is rebuilt by the next item
-    }
+    const int item = blockIdx.x;
+    if (item >= b.counts[1]) return;
+    const int s = item_sim(b.tile_sim, item);
+    const int s_off = ((const ConstInt*)b.tile_off)[s];
+    const StepArgs a = load_args(b.args, 2 * s + b.gpar);
+    lattice_tile<ST, SPT>(a, tile_window(a), item - s_off, lds);
 }
 
 // ----------------------------------------------------------------- bead kernel -----
@@ -494,28 +483,17 @@ __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_vel
     bead_block<ST>(a, blockIdx.x, do_velocity, win_out, scratch, s_R);
 }
 
-// Persistent bead kernel over a batch: block b owns a contiguous run of (simulation, bead)
-// items.
+// Bead kernel over a batch: one block per (simulation, bead) item.
 template <int ST>
 __global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
     __shared__ double scratch[kBeadBlock / 64];
     __shared__ double s_R[2];
-    const int n = b.counts[0], total = b.counts[2];
-    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int begin = (int)blockIdx.x * per;
-    const int end = min(total, begin + per);
-    int s_off = 0, s_end = 0;
-    StepArgs a;
-    for (int item = begin; item < end; ++item) {
-        if (item >= s_end) {
-            const int s = find_sim(b.bead_off, n, item);
-            s_off = b.bead_off[s];
-            s_end = b.bead_off[s + 1];
-            a = load_args(b.args, 2 * s + b.gpar);
-        }
-        bead_block<ST>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
-        __syncthreads();
-    }
+    const int item = blockIdx.x;
+    if (item >= b.counts[2]) return;
+    const int s = item_sim(b.bead_sim, item);
+    const int s_off = ((const ConstInt*)b.bead_off)[s];
+    const StepArgs a = load_args(b.args, 2 * s + b.gpar);
+    bead_block<ST>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
 }
 
 // Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same
@@ -712,28 +690,54 @@ hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_
     return hipGetLastError();
 }
 
-template <int ST>
-static hipError_t launch_batch_t(const BatchArgs& b, dim3 block, int spt, int grid_lat,
-                                 int grid_bead, hipStream_t st) {
-    switch (spt) {
-        case 1: hipLaunchKernelGGL((batch_step_kernel<ST, 1>), dim3(grid_lat), block, 0, st, b); break;
-        case 2: hipLaunchKernelGGL((batch_step_kernel<ST, 2>), dim3(grid_lat), block, 0, st, b); break;
-        case 4: hipLaunchKernelGGL((batch_step_kernel<ST, 4>), dim3(grid_lat), block, 0, st, b); break;
-        default: return hipErrorInvalidValue;
+// Forces F^n, F/A and bond strains of every simulation of a batch, one block per
+// simulation (the same arithmetic the lattice tiles use alone).
+__global__ void __launch_bounds__(kBeadThreads) batch_forces_kernel(BatchArgs b) {
+    __shared__ Bonds B;
+    const int s = blockIdx.x;
+    if (s >= b.counts[0]) return;
+    const StepArgs a = load_args(b.args, 2 * s + b.gpar);
+    const Fiber& fib = a.fib;
+    if (fib.n <= 0) return;
+    BeadState* bs = fib.bs;
+    fill_bonds(bs, fib.n, B);
+    for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
+        double F[2];
+        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, F);
+        own_bead(fib, B, fib.n, t, F, F[0] / bs->A[t], F[1] / bs->A[t]);
     }
+}
+
+template <int ST>
+static hipError_t launch_batch_t(const BatchArgs& b, dim3 block, int spt, const int counts[3],
+                                 hipStream_t st) {
+    if (counts[0] <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_forces_kernel, dim3(counts[0]), dim3(kBeadThreads), 0, st, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_bead_kernel<ST>), dim3(grid_bead), dim3(kBeadBlock), 0, st, b);
+    if (counts[1] > 0) {
+        const dim3 grid(counts[1]);
+        switch (spt) {
+            case 1: hipLaunchKernelGGL((batch_step_kernel<ST, 1>), grid, block, 0, st, b); break;
+            case 2: hipLaunchKernelGGL((batch_step_kernel<ST, 2>), grid, block, 0, st, b); break;
+            case 4: hipLaunchKernelGGL((batch_step_kernel<ST, 4>), grid, block, 0, st, b); break;
+            default: return hipErrorInvalidValue;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (counts[2] > 0)
+        hipLaunchKernelGGL((batch_bead_kernel<ST>), dim3(counts[2]), dim3(kBeadBlock), 0, st, b);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int spt,
-                             int grid_lat, int grid_bead, hipStream_t st) {
+                             const int counts[3], hipStream_t st) {
     switch (storage) {
-        case FPD_F64: return launch_batch_t<FPD_F64>(b, block, spt, grid_lat, grid_bead, st);
-        case FPD_F32: return launch_batch_t<FPD_F32>(b, block, spt, grid_lat, grid_bead, st);
-        case FPD_F16DEV: return launch_batch_t<FPD_F16DEV>(b, block, spt, grid_lat, grid_bead, st);
-        case FPD_BF16DEV: return launch_batch_t<FPD_BF16DEV>(b, block, spt, grid_lat, grid_bead, st);
+        case FPD_F64: return launch_batch_t<FPD_F64>(b, block, spt, counts, st);
+        case FPD_F32: return launch_batch_t<FPD_F32>(b, block, spt, counts, st);
+        case FPD_F16DEV: return launch_batch_t<FPD_F16DEV>(b, block, spt, counts, st);
+        case FPD_BF16DEV: return launch_batch_t<FPD_BF16DEV>(b, block, spt, counts, st);
     }
     return hipErrorInvalidValue;
 }

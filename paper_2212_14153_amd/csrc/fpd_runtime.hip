@@ -814,11 +814,16 @@ struct fpd_batch {
     int* h_counts = nullptr;
     BeadState** h_states = nullptr;
     unsigned* h_health = nullptr;
+    int* d_tile_sim = nullptr;   // item -> simulation row lookup tables (device, pinned host)
+    int* d_bead_sim = nullptr;
+    int* h_tile_sim = nullptr;
+    int* h_bead_sim = nullptr;
+    int cap_tiles = 0, cap_beads = 0;
     std::vector<int> table;  // entry index of table row r
     bool dirty = true;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
-    int grid_lat = 0, grid_bead = 0;
+    int graph_counts[3] = {0, 0, 0};  // counts the graph's grids were sized for
 };
 
 namespace {
@@ -862,6 +867,8 @@ int batch_rebuild(fpd_batch* b) {
         fpd_sim* s = e.sim;
         b->h_args[2 * r] = make_args(s, s->cur);
         b->h_args[2 * r + 1] = make_args(s, 1 - s->cur);
+        b->h_args[2 * r].forces_ready = 1;      // the batch's forces kernel runs first
+        b->h_args[2 * r + 1].forces_ready = 1;
         tiles += b->h_args[2 * r].n_tiles;
         beads += b->h_args[2 * r].fib.n;
         b->h_tile_off[r + 1] = tiles;
@@ -873,6 +880,39 @@ int batch_rebuild(fpd_batch* b) {
     b->h_counts[0] = r;
     b->h_counts[1] = tiles;
     b->h_counts[2] = beads;
+    if (b->graph && (b->graph_counts[0] != r || b->graph_counts[1] != tiles ||
+                     b->graph_counts[2] != beads))
+        batch_drop_graph(b);  // its grids no longer match the work tables
+    // item -> simulation lookup tables (grown geometrically; a new pointer drops the graph)
+    auto grow = [&](int need, int& cap, int*& d, int*& h) -> int {
+        if (need <= cap) return FPD_OK;
+        int ncap = cap > 0 ? cap : 1024;
+        while (ncap < need) ncap *= 2;
+        if (d) (void)hipFree(d);
+        if (h) (void)hipHostFree(h);
+        d = nullptr;
+        h = nullptr;
+        cap = 0;
+        if (hipMalloc((void**)&d, sizeof(int) * ncap) != hipSuccess ||
+            hipHostMalloc((void**)&h, sizeof(int) * ncap, 0) != hipSuccess)
+            return fail(FPD_ENOMEM, "batch item table allocation failed");
+        cap = ncap;
+        batch_drop_graph(b);
+        return FPD_OK;
+    };
+    int rc = grow(tiles, b->cap_tiles, b->d_tile_sim, b->h_tile_sim);
+    if (rc == FPD_OK) rc = grow(beads, b->cap_beads, b->d_bead_sim, b->h_bead_sim);
+    if (rc) return rc;
+    for (int q = 0; q < r; ++q) {
+        for (int t = b->h_tile_off[q]; t < b->h_tile_off[q + 1]; ++t) b->h_tile_sim[t] = q;
+        for (int t = b->h_bead_off[q]; t < b->h_bead_off[q + 1]; ++t) b->h_bead_sim[t] = q;
+    }
+    if (tiles > 0)
+        HIP_TRY(hipMemcpyAsync(b->d_tile_sim, b->h_tile_sim, sizeof(int) * tiles,
+                               hipMemcpyHostToDevice, b->stream));
+    if (beads > 0)
+        HIP_TRY(hipMemcpyAsync(b->d_bead_sim, b->h_bead_sim, sizeof(int) * beads,
+                               hipMemcpyHostToDevice, b->stream));
     if (r > 0) {
         HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(StepArgs) * 2 * r,
                                hipMemcpyHostToDevice, b->stream));
@@ -890,10 +930,11 @@ int batch_rebuild(fpd_batch* b) {
 }
 
 int batch_enqueue(fpd_batch* b, int gpar) {
-    BatchArgs a{b->d_args, b->d_tile_off, b->d_bead_off, b->d_counts, gpar};
+    BatchArgs a{b->d_args, b->d_tile_off, b->d_bead_off, b->d_tile_sim, b->d_bead_sim,
+                b->d_counts, gpar};
     const dim3 block(b->launch.block_x, b->launch.block_y);
-    HIP_TRY(launch_batch_step(b->storage, a, block, b->launch.rows_per_thread, b->grid_lat,
-                              b->grid_bead, b->stream));
+    HIP_TRY(launch_batch_step(b->storage, a, block, b->launch.rows_per_thread, b->h_counts,
+                              b->stream));
     return FPD_OK;
 }
 
@@ -912,6 +953,7 @@ int batch_build_graph(fpd_batch* b, int chunk) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(FPD_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
     b->graph_chunk = chunk;
+    for (int k = 0; k < 3; ++k) b->graph_counts[k] = b->h_counts[k];
     return FPD_OK;
 }
 
@@ -963,12 +1005,6 @@ int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage
         (void)hipGetLastError();
         return bail(fail(FPD_ENOMEM, "batch table allocation failed"));
     }
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return bail(fail(FPD_EDEVICE, "device query failed"));
-    b->grid_lat = cus * 8;   // 256-thread blocks: up to 8 per CU
-    b->grid_bead = cus * 8;  // 256-thread blocks: 8 per CU
     int rc = batch_rebuild(b);
     if (rc) return bail(rc);
     *out = b;
@@ -987,6 +1023,10 @@ void fpd_batch_destroy(fpd_batch* b) {
     (void)hipFree(b->d_counts);
     (void)hipFree(b->d_states);
     (void)hipFree(b->d_health);
+    (void)hipFree(b->d_tile_sim);
+    (void)hipFree(b->d_bead_sim);
+    (void)hipHostFree(b->h_tile_sim);
+    (void)hipHostFree(b->h_bead_sim);
     (void)hipHostFree(b->h_args);
     (void)hipHostFree(b->h_tile_off);
     (void)hipHostFree(b->h_bead_off);
