@@ -12,7 +12,7 @@ time) and a CPU baseline (the FP64 oracle on a bounded sample of the same worklo
 
 Other modes (each prints one JSON line):
   --mode batch   256 parameter-sweep simulations (uneven lattices 128x64..1024x512, 5-30
-                 beads) advanced together by the persistent batch kernels, against the plain
+                 beads) advanced together by the batch kernels, against the plain
                  path (the same simulations one at a time, per-step launches, no graph);
   --mode serve   Poisson arrivals (50 requests/s) of sweep simulations served with
                  continuous batching in FP16/BF16 deviation storage: p50/p99 time-to-result
@@ -21,7 +21,6 @@ Other modes (each prints one JSON line):
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import platform
@@ -34,7 +33,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E peak
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
-KERNEL_SRC = os.path.join(ROOT, "paper_2212_14153_amd", "csrc", "fpd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel.json")
 
 
@@ -52,8 +50,8 @@ def workload(name, storage):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_2212_14153_amd.profsum import kernel_source_hash
+    return kernel_source_hash()
 
 
 def measured_traffic(storage, nodes):
