@@ -5,8 +5,9 @@
 // square centre (x + 1/2, y + 1/2) (arXiv:2212.14153, Sec. II.C); walls at y = 0 (moving at
 // -U) and y = ny (moving at +U) (Sec. IV.A); x periodic.
 //
-// Storage: nine SoA planes g_k = f_k - w_k (deviations from the rest equilibrium), row
-// stride padded to 64 elements.  A buffer holds post-collision values; a step pulls them
+// Storage: deviations g_k = f_k - w_k from the rest equilibrium, one contiguous run of nx
+// values (padded to 64) per direction and row, the nine directions of a row side by side
+// (index y * stride + k * plane + x).  A buffer holds post-collision values; a step pulls them
 // along -e_k (half-way bounce-back at the walls), collides, and writes the next buffer.
 #pragma once
 

@@ -32,9 +32,12 @@ struct BeadState {
     unsigned long long max_strain_bits;  // bits of the largest |L - l0| / l0 (atomic max)
 };
 
+// Value (k, y, x) of a population buffer sits at y * stride + k * plane + x.  The nine
+// direction rows of one lattice row are adjacent (plane = nx padded to 64 elements, stride
+// = 9 * plane): the streams of a tile stay within a few hundred KB of each other.
 struct Lattice {
-    int nx, ny, stride;       // stride: row pitch in elements (multiple of 64)
-    long long plane;          // elements per direction plane (ny * stride)
+    int nx, ny, stride;       // stride: row pitch in elements
+    long long plane;          // offset between directions k and k + 1 in elements
 };
 
 // What the kernels need to evaluate phi, eta and the force density near the fiber.

@@ -127,8 +127,8 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
 int validate(const fpd_params* p) {
     if (!p) return fail(FPD_EINVAL, "params is NULL");
     if (p->nx < 1 || p->ny < 1) return fail(FPD_EINVAL, "nx, ny must be >= 1");
-    if ((long long)p->ny * padded_stride(p->nx) > 0x7fffffffLL)
-        return fail(FPD_EINVAL, "ny * padded nx must stay below 2^31 nodes per plane");
+    if (9LL * p->ny * padded_stride(p->nx) > 0x7fffffffLL)
+        return fail(FPD_EINVAL, "9 * ny * padded nx must stay below 2^31 values per buffer");
     if (!(p->nu_f > 0.0) || !(3.0 * p->nu_f + 0.5 > 0.5))
         return fail(FPD_EINVAL, "tau_f = 3 nu_f + 1/2 must exceed 1/2 (nu_f = %g)", p->nu_f);
     if (!(fabs(p->u_wall) < 0.1)) return fail(FPD_EINVAL, "|u_wall| must be < 0.1");
@@ -278,10 +278,12 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     s->p = *p;
     s->L.nx = p->nx;
     s->L.ny = p->ny;
-    s->L.stride = padded_stride(p->nx);
-    s->L.plane = (long long)p->ny * s->L.stride;
+    // the nine direction rows of a lattice row lie side by side: value (k, y, x) sits at
+    // y * stride + k * plane + x with plane = padded nx and stride = 9 * plane
+    s->L.plane = padded_stride(p->nx);
+    s->L.stride = 9 * padded_stride(p->nx);
     s->elem = storage_elem(p->storage);
-    s->buf_bytes = (size_t)9 * (size_t)s->L.plane * s->elem;
+    s->buf_bytes = (size_t)p->ny * (size_t)s->L.stride * s->elem;
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
     // measured on MI355X (8192 x 2048): 256 x 1 for 2- and 4-byte storage, 128 x 2 for
     // float64, one row per thread, default block order (no XCD remap)
@@ -718,7 +720,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 
 // ---------------------------------------------------------------- checkpoint -------
 
-static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '2'};
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '3'};
 
 int fpd_save(fpd_sim* s, const char* path) {
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");

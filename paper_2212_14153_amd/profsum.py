@@ -9,8 +9,8 @@
 `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of a kernel into HBM bytes per
 launch, each scaled by what the same counter reads for the plain copy kernel of known size
 that the same run dispatches (a copy of B bytes reads B and writes B bytes).  The JSON keeps
-one entry per storage format and the hash of the kernel source the counters were taken on,
-so a later kernel change invalidates them.
+one entry per storage format and the hash of the library sources the counters were taken
+on, so a later change of the kernels or the layout invalidates them.
 """
 from __future__ import annotations
 
@@ -22,13 +22,18 @@ import os
 import re
 import statistics
 
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fpd_kernels.hip")
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 COPY_KERNEL = "copy_kernel"
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of every kernel and runtime source (the memory layout is set by the runtime)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def short_name(name: str) -> str:
