@@ -216,9 +216,9 @@ int fpd_load(fpd_sim *s, const char *path);
 
 /* ------------------------------------------------------------------ batch ---- */
 /* A batch holds independent simulations of different lattice sizes (one storage format)
- * and advances all active ones together: each step is one persistent lattice kernel over
- * every (simulation, tile) pair and one persistent bead kernel over every (simulation,
- * bead) pair, replayed from a captured graph.  The parameter-sweep workload of the paper
+ * and advances all active ones together: each step is one forces kernel (a block per
+ * simulation), one lattice kernel over every (simulation, tile) pair and one bead kernel
+ * over every (simulation, bead) pair, replayed from a captured graph.  The parameter-sweep workload of the paper
  * (Sec. IV: stiffness, Re_ps 1-10, confinement) is the intended use.  Per-simulation
  * arithmetic is the single-simulation path's, so a result is bitwise the same alone and
  * in any mix. */

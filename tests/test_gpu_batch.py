@@ -1,5 +1,5 @@
-"""Batched simulations (persistent kernels over (simulation, tile) and (simulation, bead)
-items) against the same simulations run alone through the single-simulation path."""
+"""Batched simulations (kernels over (simulation, tile) and (simulation, bead) work items)
+against the same simulations run alone through the single-simulation path."""
 import numpy as np
 import pytest
 
