@@ -137,8 +137,8 @@ size_t fpd_population_bytes(const fpd_params *p);
 int fpd_create(const fpd_params *p, void *hip_stream, fpd_sim **out);
 
 /* As fpd_create, but the two population buffers are caller-owned device memory of
- * bytes_each >= fpd_population_bytes(p) bytes each (e.g. torch tensors); they must
- * outlive the simulation. */
+ * bytes_each >= fpd_population_bytes(p) bytes each (e.g. torch tensors), 16-byte aligned
+ * (FPD_EINVAL otherwise); they must outlive the simulation. */
 int fpd_create_with_buffers(const fpd_params *p, void *hip_stream, void *f_a, void *f_b,
                             size_t bytes_each, fpd_sim **out);
 

@@ -54,6 +54,13 @@ template <> struct Codec<FPD_F16DEV> {
     }
     __device__ static inline double to_f64(store_t v) { return (double)(float)v * (double)kInv; }
     __device__ static inline store_t from_f64(double v) { return (_Float16)(float)(v * 16384.0); }
+    // the same conversions on the raw 16 bits (low half of b)
+    __device__ static inline T from_bits(uint32_t b) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)b) * kInv;
+    }
+    __device__ static inline uint32_t to_bits(T v) {
+        return __builtin_bit_cast(uint16_t, (_Float16)(v * kScale));
+    }
 };
 
 // bfloat16 of g, round to nearest even (deviations are finite here).
@@ -73,6 +80,8 @@ template <> struct Codec<FPD_BF16DEV> {
     }
     __device__ static inline double to_f64(store_t v) { return (double)bf16_to_f32(v); }
     __device__ static inline store_t from_f64(double v) { return f32_to_bf16((float)v); }
+    __device__ static inline T from_bits(uint32_t b) { return bf16_to_f32((uint16_t)b); }
+    __device__ static inline uint32_t to_bits(T v) { return f32_to_bf16(v); }
 };
 
 // ------------------------------------------------------------------- helpers --------
@@ -216,6 +225,126 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
         g[4] = Cd::load(p2 + r0 + x);
         g[7] = Cd::load(p5 + r0 + x) - u6;
         g[8] = Cd::load(p6 + r0 + x) + u6;
+    }
+}
+
+// Two-byte storage: a lane updates the nodes x0 and x0 + 1 (x0 even) of one row and moves
+// populations as aligned 32-bit words, so every memory request carries four bytes per
+// lane.  A value one node left of x0, or two nodes right of it, is a half of the
+// neighbouring lane's word (a wave's 64 lanes hold 128 consecutive nodes of one row); at a
+// wave's edge and at the periodic wrap it is a 2-byte load.  All lanes of the wave must
+// call these (the cross-lane moves need every lane); lanes with x0 >= nx load nothing.
+// Rows start at multiples of 64 elements in 16-byte aligned buffers, so x0 even keeps the
+// word loads aligned.
+
+// The loads of one direction row for the pair (x0, x0 + 1) pulled along an x shift
+// SX = e_kx: node x0 takes the row's value at x0 - SX, node x0 + 1 the one at x0 + 1 - SX
+// (x wraps).  w is the word at x0; e / c hold the 2-byte values a lane needs beyond what
+// its neighbours' words give (wave edges, wrap).  All loads of a node pair are issued
+// before any cross-lane move, so a wave waits for memory once.
+struct PairRaw {
+    uint32_t w, e, c;
+};
+
+template <int SX>
+__device__ inline PairRaw pair_load(const uint16_t* __restrict__ row, int x0, int nx,
+                                    bool first, bool last) {
+    const bool in = x0 < nx;
+    PairRaw r{0u, 0u, 0u};
+    if (in) r.w = *(const uint32_t*)(row + x0);
+    if (SX == 1) {
+        if (in && (first || x0 == 0)) r.e = row[x0 == 0 ? nx - 1 : x0 - 1];
+    } else if (SX == -1) {
+        if (in && x0 + 1 < nx && (last || x0 + 2 >= nx)) r.e = row[imod(x0 + 2, nx)];
+        if (in && x0 + 1 >= nx) r.c = row[0];
+    }
+    return r;
+}
+
+template <class Cd, int SX>
+__device__ inline void pair_finish(const PairRaw& r, int x0, int nx, bool first, bool last,
+                                   typename Cd::T& va, typename Cd::T& vb) {
+    const bool in = x0 < nx;
+    if (SX == 0) {
+        va = Cd::from_bits(r.w & 0xffffu);
+        vb = Cd::from_bits(r.w >> 16);
+    } else if (SX == 1) {
+        uint32_t l = (uint32_t)__shfl_up((int)(r.w >> 16), 1);  // x0 - 1: left lane's high half
+        if (in && (first || x0 == 0)) l = r.e;
+        va = Cd::from_bits(l);
+        vb = Cd::from_bits(r.w & 0xffffu);
+    } else {
+        uint32_t rr = (uint32_t)__shfl_down((int)(r.w & 0xffffu), 1);  // x0 + 2: right lane's low half
+        if (in && x0 + 1 < nx && (last || x0 + 2 >= nx)) rr = r.e;
+        const uint32_t c = (in && x0 + 1 >= nx) ? r.c : (r.w >> 16);  // x0 + 1
+        va = Cd::from_bits(c);
+        vb = Cd::from_bits(rr);
+    }
+}
+
+// pull() for the pair of nodes x0, x0 + 1 of row y; ga / gb receive their populations.
+template <class Cd>
+__device__ inline void pull_pair(const uint16_t* __restrict__ src, int nx, int ny, int stride,
+                                 long long plane, int x0, int y, bool first, bool last,
+                                 typename Cd::T u6, typename Cd::T ga[9],
+                                 typename Cd::T gb[9]) {
+    const long long r0 = (long long)y * stride;
+    const uint16_t* row = src + r0;
+    const bool bottom = y == 0, top = y == ny - 1;
+    // rows and shifts of g_2, g_5, g_6 (from below, or reflected at the bottom wall) and
+    // g_4, g_7, g_8 (from above, or reflected at the top wall)
+    const uint16_t* rm = bottom ? row : row - stride;
+    const uint16_t* rp = top ? row : row + stride;
+    const PairRaw q0 = pair_load<0>(row, x0, nx, first, last);
+    const PairRaw q1 = pair_load<1>(row + plane, x0, nx, first, last);
+    const PairRaw q3 = pair_load<-1>(row + 3 * plane, x0, nx, first, last);
+    PairRaw q2, q5, q6, q4, q7, q8;
+    if (!bottom) {
+        q2 = pair_load<0>(rm + 2 * plane, x0, nx, first, last);
+        q5 = pair_load<1>(rm + 5 * plane, x0, nx, first, last);
+        q6 = pair_load<-1>(rm + 6 * plane, x0, nx, first, last);
+    } else {
+        q2 = pair_load<0>(row + 4 * plane, x0, nx, first, last);
+        q5 = pair_load<0>(row + 7 * plane, x0, nx, first, last);
+        q6 = pair_load<0>(row + 8 * plane, x0, nx, first, last);
+    }
+    if (!top) {
+        q4 = pair_load<0>(rp + 4 * plane, x0, nx, first, last);
+        q7 = pair_load<-1>(rp + 7 * plane, x0, nx, first, last);
+        q8 = pair_load<1>(rp + 8 * plane, x0, nx, first, last);
+    } else {
+        q4 = pair_load<0>(row + 2 * plane, x0, nx, first, last);
+        q7 = pair_load<0>(row + 5 * plane, x0, nx, first, last);
+        q8 = pair_load<0>(row + 6 * plane, x0, nx, first, last);
+    }
+    pair_finish<Cd, 0>(q0, x0, nx, first, last, ga[0], gb[0]);
+    pair_finish<Cd, 1>(q1, x0, nx, first, last, ga[1], gb[1]);
+    pair_finish<Cd, -1>(q3, x0, nx, first, last, ga[3], gb[3]);
+    if (!bottom) {
+        pair_finish<Cd, 0>(q2, x0, nx, first, last, ga[2], gb[2]);
+        pair_finish<Cd, 1>(q5, x0, nx, first, last, ga[5], gb[5]);
+        pair_finish<Cd, -1>(q6, x0, nx, first, last, ga[6], gb[6]);
+    } else {
+        pair_finish<Cd, 0>(q2, x0, nx, first, last, ga[2], gb[2]);
+        pair_finish<Cd, 0>(q5, x0, nx, first, last, ga[5], gb[5]);
+        pair_finish<Cd, 0>(q6, x0, nx, first, last, ga[6], gb[6]);
+        ga[5] -= u6;
+        gb[5] -= u6;
+        ga[6] += u6;
+        gb[6] += u6;
+    }
+    if (!top) {
+        pair_finish<Cd, 0>(q4, x0, nx, first, last, ga[4], gb[4]);
+        pair_finish<Cd, -1>(q7, x0, nx, first, last, ga[7], gb[7]);
+        pair_finish<Cd, 1>(q8, x0, nx, first, last, ga[8], gb[8]);
+    } else {
+        pair_finish<Cd, 0>(q4, x0, nx, first, last, ga[4], gb[4]);
+        pair_finish<Cd, 0>(q7, x0, nx, first, last, ga[7], gb[7]);
+        pair_finish<Cd, 0>(q8, x0, nx, first, last, ga[8], gb[8]);
+        ga[7] -= u6;
+        gb[7] -= u6;
+        ga[8] += u6;
+        gb[8] += u6;
     }
 }
 

@@ -35,6 +35,12 @@ struct BeadState {
 // Value (k, y, x) of a population buffer sits at y * stride + k * plane + x.  The nine
 // direction rows of one lattice row are adjacent (plane = nx padded to 64 elements, stride
 // = 9 * plane): the streams of a tile stay within a few hundred KB of each other.
+// Nodes one lane of the lattice kernel updates along x: two for 2-byte storage (the
+// populations move as 32-bit words), one otherwise.
+constexpr int nodes_per_lane(int storage) {
+    return (storage == FPD_F16DEV || storage == FPD_BF16DEV) ? 2 : 1;
+}
+
 struct Lattice {
     int nx, ny, stride;       // stride: row pitch in elements
     long long plane;          // offset between directions k and k + 1 in elements

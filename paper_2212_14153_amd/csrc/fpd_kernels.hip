@@ -229,6 +229,38 @@ __device__ inline Window tile_window(const StepArgs& a) {
                          a.fib.rect_hmax);
 }
 
+// Step (1) at one node (x, y) of a fiber tile: phi_i^n (Eq. 2), eta^n (Eq. 1) and the
+// relaxation rates, f^n (Eq. 4), recorded in the force window.
+template <typename T>
+__device__ inline void fiber_node(const StepArgs& a, const double (*sR)[2],
+                                  const double (*sC)[2], int nb, int x, int y, int wx0,
+                                  int wy0, int ww, int wh, T& Fx, T& Fy, T& s_nu, T& s_q) {
+    const int nx = a.L.nx;
+    const double xc = (double)x + 0.5, yc = (double)y + 0.5;
+    T sphi = T(0);
+    for (int i = 0; i < nb; ++i) {
+        const double dx = min_image(xc - sR[i][0], nx);
+        const double dy = yc - sR[i][1];
+        const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi, a.fib.inv_xi);
+        sphi += ph;
+        Fx += ph * (T)sC[i][0];
+        Fy += ph * (T)sC[i][1];
+    }
+    if (a.fib.clamp && sphi > T(1)) sphi = T(1);
+    if (sphi > T(0)) {  // else the fluid rates, exactly as on the other tiles
+        const T nu_f = (T)a.fib.nu_f;
+        const T eta = nu_f + ((T)a.fib.nu_s - nu_f) * sphi;
+        s_nu = T(1) / (T(3) * eta + T(0.5));
+        s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
+    }
+    const int wi = imod(x - wx0, nx), wj = y - wy0;
+    if (wi < ww && wj >= 0 && wj < wh) {
+        T* rf = (T*)a.fib.rect_f + 2 * ((long long)wj * a.fib.rect_wmax + wi);
+        rf[0] = Fx;
+        rf[1] = Fy;
+    }
+}
+
 template <int ST, int SPT>
 __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int tile,
                                     TileLds& lds) {
@@ -285,34 +317,8 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
         T g[9];
         pull<Cd>(src, nx, ny, stride, plane, x, y, u6, g);
         T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
-        if (fiber_tile) {
-            // Step (1) at this node: phi_i^n (Eq. 2), eta^n (Eq. 1), f^n (Eq. 4).
-            const double xc = (double)x + 0.5, yc = (double)y + 0.5;
-            T sphi = T(0);
-            for (int i = 0; i < nb; ++i) {
-                const double dx = min_image(xc - sR[i][0], nx);
-                const double dy = yc - sR[i][1];
-                const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi,
-                                              a.fib.inv_xi);
-                sphi += ph;
-                Fx += ph * (T)sC[i][0];
-                Fy += ph * (T)sC[i][1];
-            }
-            if (a.fib.clamp && sphi > T(1)) sphi = T(1);
-            if (sphi > T(0)) {  // else the fluid rates, exactly as on the other tiles
-                const T nu_f = (T)a.fib.nu_f;
-                const T eta = nu_f + ((T)a.fib.nu_s - nu_f) * sphi;
-                s_nu = T(1) / (T(3) * eta + T(0.5));
-                s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed
-                                            : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
-            }
-            const int wi = imod(x - wx0, nx), wj = y - wy0;
-            if (wi < ww && wj >= 0 && wj < wh) {
-                T* rf = (T*)a.fib.rect_f + 2 * ((long long)wj * a.fib.rect_wmax + wi);
-                rf[0] = Fx;
-                rf[1] = Fy;
-            }
-        }
+        if (fiber_tile)
+            fiber_node<T>(a, sR, sC, nb, x, y, wx0, wy0, ww, wh, Fx, Fy, s_nu, s_q);
         mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
         S* o = dst + (long long)y * stride + x;
 #pragma unroll
@@ -320,11 +326,98 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     }
 }
 
+// lattice_tile for 2-byte storage: a tile is 2 * block_x nodes wide and each lane updates
+// two neighbouring nodes with the same per-node arithmetic as the one-node path.
+template <int ST, int SPT>
+__device__ inline void lattice_tile_pair(const StepArgs& a, const Window& win, int tile,
+                                         TileLds& lds) {
+    using Cd = Codec<ST>;
+    using T = typename Cd::T;
+    static_assert(sizeof(typename Cd::store_t) == 2, "pair path is for 2-byte storage");
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int tw = 2 * (int)blockDim.x;
+    const int xtile = tx * tw;
+    const int x0 = xtile + 2 * (int)threadIdx.x;
+    const int lane = (int)threadIdx.x & 63;
+    const bool first = lane == 0, last = lane == 63;
+    const int ytile = ty * a.rows_per_block;
+    const int ybase = ytile + threadIdx.y * SPT;
+    const int nx = a.L.nx, ny = a.L.ny, stride = a.L.stride;
+    const long long plane = a.L.plane;
+    const uint16_t* __restrict__ src = (const uint16_t*)a.src;
+    uint16_t* __restrict__ dst = (uint16_t*)a.dst;
+    const T u6 = (T)a.u6;
+    const T s_e = (T)a.s_e, s_eps = (T)a.s_eps;
+
+    int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
+    bool fiber_tile = false;
+    if (a.fib.n > 0) {
+        BeadState* bs = a.fib.bs;
+        wx0 = win.x0;
+        wy0 = win.y0;
+        ww = win.w;
+        wh = win.h;
+        if (tile == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+            int* nxt = bs->win[1 - a.parity];
+            nxt[0] = 0x7fffffff;
+            nxt[1] = -0x7fffffff;
+            nxt[2] = 0x7fffffff;
+            nxt[3] = -0x7fffffff;
+            if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
+        }
+        fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
+                     ytile + a.rows_per_block - 1 >= wy0 &&
+                     cols_overlap(xtile, tw, wx0, ww, nx);
+        if (fiber_tile)
+            nb = gather_beads(a.fib, nx, ny, xtile, tw, ytile, a.rows_per_block, lds.R, lds.C,
+                              lds.wave, lds.bonds, a.forces_ready != 0);
+    }
+
+#pragma unroll
+    for (int r = 0; r < SPT; ++r) {
+        const int y = ybase + r;
+        if (y >= ny) continue;  // uniform over a wave (its lanes share one row)
+        T ga[9], gb[9];
+        pull_pair<Cd>(src, nx, ny, stride, plane, x0, y, first, last, u6, ga, gb);
+        if (x0 >= nx) continue;
+        const bool has_b = x0 + 1 < nx;
+        T Fxa = T(0), Fya = T(0), nua = (T)a.s_nu_f, qa = (T)a.s_q_f;
+        T Fxb = T(0), Fyb = T(0), nub = (T)a.s_nu_f, qb = (T)a.s_q_f;
+        if (fiber_tile) {
+            fiber_node<T>(a, lds.R, lds.C, nb, x0, y, wx0, wy0, ww, wh, Fxa, Fya, nua, qa);
+            if (has_b)
+                fiber_node<T>(a, lds.R, lds.C, nb, x0 + 1, y, wx0, wy0, ww, wh, Fxb, Fyb, nub,
+                              qb);
+        }
+        mrt_collide<T>(ga, Fxa, Fya, nua, qa, s_e, s_eps);
+        mrt_collide<T>(gb, Fxb, Fyb, nub, qb, s_e, s_eps);
+        uint16_t* o = dst + (long long)y * stride + x0;
+        if (has_b) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                __builtin_nontemporal_store(Cd::to_bits(ga[k]) | (Cd::to_bits(gb[k]) << 16),
+                                            (uint32_t*)(o + k * plane));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                __builtin_nontemporal_store((uint16_t)Cd::to_bits(ga[k]), o + k * plane);
+        }
+    }
+}
+
+template <int ST, int SPT>
+__device__ inline void tile_any(const StepArgs& a, const Window& win, int tile, TileLds& lds) {
+    if constexpr (nodes_per_lane(ST) == 2)
+        lattice_tile_pair<ST, SPT>(a, win, tile, lds);
+    else
+        lattice_tile<ST, SPT>(a, win, tile, lds);
+}
+
 template <int ST, int SPT>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ TileLds lds;
     const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    lattice_tile<ST, SPT>(a, tile_window(a), tile, lds);
+    tile_any<ST, SPT>(a, tile_window(a), tile, lds);
 }
 
 // The argument table is read-only while a batch kernel runs: viewing it in the constant
@@ -356,7 +449,7 @@ __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     const int s = item_sim(b.tile_sim, item);
     const int s_off = ((const ConstInt*)b.tile_off)[s];
     const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    lattice_tile<ST, SPT>(a, tile_window(a), item - s_off, lds);
+    tile_any<ST, SPT>(a, tile_window(a), item - s_off, lds);
 }
 
 // ----------------------------------------------------------------- bead kernel -----

@@ -54,6 +54,15 @@ size_t storage_elem(int st) {
 
 int padded_stride(int nx) { return (nx + 63) / 64 * 64; }
 
+// Launch shapes measured best on MI355X at 8192 x 2048 (default block order, no XCD remap):
+// 128 x 2 for float64, 256 x 1 for float32, 64 x 4 with two rows per thread for the
+// two-byte formats (whose lanes update two nodes each).
+fpd_launch default_launch(int storage, int graph_chunk) {
+    if (storage == FPD_F64) return fpd_launch{128, 2, 1, 2, graph_chunk};
+    if (nodes_per_lane(storage) == 2) return fpd_launch{64, 4, 2, 2, graph_chunk};
+    return fpd_launch{256, 1, 1, 2, graph_chunk};
+}
+
 double default_cutoff(int storage) { return storage == FPD_F64 ? 20.0 : 9.0; }
 
 }  // namespace
@@ -117,7 +126,8 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.kb = s->p.k_b;
     const fpd_launch& c = s->launch;
     a.rows_per_block = c.block_y * c.rows_per_thread;
-    a.tiles_x = (s->L.nx + c.block_x - 1) / c.block_x;
+    const int tw = c.block_x * nodes_per_lane(s->p.storage);
+    a.tiles_x = (s->L.nx + tw - 1) / tw;
     const int tiles_y = (s->L.ny + a.rows_per_block - 1) / a.rows_per_block;
     a.n_tiles = a.tiles_x * tiles_y;
     a.xcd_remap = c.xcd_remap == 1 ? 1 : 0;
@@ -285,10 +295,7 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     s->elem = storage_elem(p->storage);
     s->buf_bytes = (size_t)p->ny * (size_t)s->L.stride * s->elem;
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
-    // measured on MI355X (8192 x 2048): 256 x 1 for 2- and 4-byte storage, 128 x 2 for
-    // float64, one row per thread, default block order (no XCD remap)
-    s->launch = p->storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 64}
-                                      : fpd_launch{256, 1, 1, 2, 64};
+    s->launch = default_launch(p->storage, 64);
     auto bail = [&](int code) {
         fpd_destroy(s);
         return code;
@@ -408,6 +415,8 @@ int fpd_create(const fpd_params* p, void* hip_stream, fpd_sim** out) {
 int fpd_create_with_buffers(const fpd_params* p, void* hip_stream, void* f_a, void* f_b,
                             size_t bytes_each, fpd_sim** out) {
     if (!f_a || !f_b) return fail(FPD_EINVAL, "buffers must not be NULL");
+    if (((uintptr_t)f_a | (uintptr_t)f_b) & 15)
+        return fail(FPD_EINVAL, "buffers must be 16-byte aligned");
     return create_impl(p, hip_stream, f_a, f_b, bytes_each, out);
 }
 
@@ -978,7 +987,7 @@ int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage
     b->budget = hbm_budget_bytes;
     b->max_slots = max_slots;
     b->storage = storage;
-    b->launch = storage == FPD_F64 ? fpd_launch{128, 2, 1, 2, 32} : fpd_launch{256, 1, 1, 2, 32};
+    b->launch = default_launch(storage, 32);
     auto bail = [&](int code) {
         fpd_batch_destroy(b);
         return code;

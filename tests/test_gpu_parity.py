@@ -93,6 +93,34 @@ def test_lattice_steps_without_fiber(nx, ny, storage):
     assert rel_err(f, st.f) <= tol
 
 
+# Two-byte storage moves populations as 32-bit words, two nodes per lane, with the
+# neighbours' values passed between lanes: odd widths, widths that end inside a wave, and
+# rows spanning several waves (130, 300) cover every edge case of that exchange.  The
+# bound is the storage rounding (|g| < 2e-2 here; 11 / 8 significant bits, two roundings
+# per step: the written state and each stored result) with a factor 2 of slack; a
+# population taken from a wrong node would be off by the 5e-3 perturbation.
+@pytest.mark.parametrize("nx,ny", [(64, 32), (67, 13), (130, 7), (300, 5), (5, 3), (1, 4),
+                                   (9, 1), (2, 3)])
+@pytest.mark.parametrize("storage,bits", [("f16dev", 11), ("bf16dev", 8)])
+def test_two_byte_storage_steps_without_fiber(nx, ny, storage, bits):
+    w = workloads.c1_small_fp64().with_(nx=nx, ny=ny, n_beads=0, u_wall=0.03, nu_f=0.02)
+    print_case("lattice-2byte", w, storage)
+    p = orc_params(w)
+    f0 = oracle.init(p, 1) + workloads.perturbation((9, ny, nx), 5e-3, seed=nx * 7 + ny)
+    gmax = float(np.abs(f0 - oracle.init(p, 1)).max()) + 0.03
+    for steps in (1, 3):
+        st = oracle.make_state(p, 1)
+        st.f[:] = f0
+        oracle.run(st, steps)
+        with gpu_sim(w, storage) as sim:
+            sim.write_populations(f0)
+            sim.step(steps)
+            sim.sync()
+            f = sim.populations()
+        tol = 2.0 * (steps + 1) * gmax * 2.0 ** -bits
+        assert np.max(np.abs(f - st.f)) <= tol, (steps, np.max(np.abs(f - st.f)), tol)
+
+
 # --------------------------------------------------------------- coupled fiber step ---
 
 def run_both(w, storage, steps, record=None):
@@ -187,7 +215,7 @@ LAUNCHES = [
 ]
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
 def test_launch_shapes_and_graph_replay_are_bitwise_identical(storage):
     w = small_fiber(150, 37, 6, 11, storage)
     print_case("launch-shapes", w, storage)
