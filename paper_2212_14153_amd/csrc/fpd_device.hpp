@@ -228,124 +228,149 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
     }
 }
 
-// Two-byte storage: a lane updates the nodes x0 and x0 + 1 (x0 even) of one row and moves
-// populations as aligned 32-bit words, so every memory request carries four bytes per
-// lane.  A value one node left of x0, or two nodes right of it, is a half of the
-// neighbouring lane's word (a wave's 64 lanes hold 128 consecutive nodes of one row); at a
-// wave's edge and at the periodic wrap it is a 2-byte load.  All lanes of the wave must
-// call these (the cross-lane moves need every lane); lanes with x0 >= nx load nothing.
-// Rows start at multiples of 64 elements in 16-byte aligned buffers, so x0 even keeps the
-// word loads aligned.
+// Two-byte storage: a lane updates G = nodes_per_lane consecutive nodes x0 .. x0 + G - 1
+// (x0 a multiple of G) of one row and moves populations as aligned G/2-dword vectors, so
+// every memory request carries 2 G bytes per lane.  A value left of x0, or right of the
+// group, is an end of the neighbouring lane's vector (a wave's 64 lanes hold 64 G
+// consecutive nodes of one row); at a wave's edge and at the periodic wrap it is a 2-byte
+// load.  All lanes of the wave must call these (the cross-lane moves need every lane);
+// lanes with x0 >= nx load nothing.  Rows start at multiples of 64 elements in 16-byte
+// aligned buffers, so the vector loads are aligned.
 
-// The loads of one direction row for the pair (x0, x0 + 1) pulled along an x shift
-// SX = e_kx: node x0 takes the row's value at x0 - SX, node x0 + 1 the one at x0 + 1 - SX
-// (x wraps).  w is the word at x0; e / c hold the 2-byte values a lane needs beyond what
-// its neighbours' words give (wave edges, wrap).  All loads of a node pair are issued
+// The loads of one direction row for the group, pulled along an x shift SX = e_kx: node
+// x0 + i takes the row's value at x0 + i - SX (x wraps).  w holds the vector at x0; e the
+// value beyond the group edge that a wave-edge or wrapping lane loads itself; c the value
+// at x = 0 for a node nx - 1 inside the group (SX = -1).  All loads of a group are issued
 // before any cross-lane move, so a wave waits for memory once.
-struct PairRaw {
-    uint32_t w, e, c;
+template <int G>
+struct GroupRaw {
+    uint32_t w[G / 2];
+    uint32_t e, c;
+    __device__ inline uint32_t elem(int i) const { return (w[i >> 1] >> (16 * (i & 1))) & 0xffffu; }
 };
 
-template <int SX>
-__device__ inline PairRaw pair_load(const uint16_t* __restrict__ row, int x0, int nx,
-                                    bool first, bool last) {
+template <int G, int SX>
+__device__ inline GroupRaw<G> group_load(const uint16_t* __restrict__ row, int x0, int nx,
+                                         bool first, bool last) {
     const bool in = x0 < nx;
-    PairRaw r{0u, 0u, 0u};
-    if (in) r.w = *(const uint32_t*)(row + x0);
+    GroupRaw<G> r;
+#pragma unroll
+    for (int i = 0; i < G / 2; ++i) r.w[i] = 0u;
+    r.e = 0u;
+    r.c = 0u;
+    if (in) {
+        if constexpr (G == 2) {
+            r.w[0] = *(const uint32_t*)(row + x0);
+        } else {
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            const u32x2 v = *(const u32x2*)(row + x0);
+            r.w[0] = v.x;
+            r.w[1] = v.y;
+        }
+    }
     if (SX == 1) {
         if (in && (first || x0 == 0)) r.e = row[x0 == 0 ? nx - 1 : x0 - 1];
     } else if (SX == -1) {
-        if (in && x0 + 1 < nx && (last || x0 + 2 >= nx)) r.e = row[imod(x0 + 2, nx)];
-        if (in && x0 + 1 >= nx) r.c = row[0];
+        if (in && x0 + G - 1 < nx && (last || x0 + G >= nx)) r.e = row[imod(x0 + G, nx)];
+        if (in && x0 + G - 1 >= nx) r.c = row[0];
     }
     return r;
 }
 
-template <class Cd, int SX>
-__device__ inline void pair_finish(const PairRaw& r, int x0, int nx, bool first, bool last,
-                                   typename Cd::T& va, typename Cd::T& vb) {
+template <class Cd, int G, int SX>
+__device__ inline void group_finish(const GroupRaw<G>& r, int x0, int nx, bool first,
+                                    bool last, typename Cd::T v[G]) {
     const bool in = x0 < nx;
     if (SX == 0) {
-        va = Cd::from_bits(r.w & 0xffffu);
-        vb = Cd::from_bits(r.w >> 16);
+#pragma unroll
+        for (int i = 0; i < G; ++i) v[i] = Cd::from_bits(r.elem(i));
     } else if (SX == 1) {
-        uint32_t l = (uint32_t)__shfl_up((int)(r.w >> 16), 1);  // x0 - 1: left lane's high half
+        uint32_t l = (uint32_t)__shfl_up((int)r.elem(G - 1), 1);  // x0 - 1: left lane's last
         if (in && (first || x0 == 0)) l = r.e;
-        va = Cd::from_bits(l);
-        vb = Cd::from_bits(r.w & 0xffffu);
+        v[0] = Cd::from_bits(l);
+#pragma unroll
+        for (int i = 1; i < G; ++i) v[i] = Cd::from_bits(r.elem(i - 1));
     } else {
-        uint32_t rr = (uint32_t)__shfl_down((int)(r.w & 0xffffu), 1);  // x0 + 2: right lane's low half
-        if (in && x0 + 1 < nx && (last || x0 + 2 >= nx)) rr = r.e;
-        const uint32_t c = (in && x0 + 1 >= nx) ? r.c : (r.w >> 16);  // x0 + 1
-        va = Cd::from_bits(c);
-        vb = Cd::from_bits(rr);
+        uint32_t rr = (uint32_t)__shfl_down((int)r.elem(0), 1);  // x0 + G: right lane's first
+        if (in && x0 + G - 1 < nx && (last || x0 + G >= nx)) rr = r.e;
+#pragma unroll
+        for (int i = 0; i < G - 1; ++i)
+            v[i] = Cd::from_bits(x0 + i + 1 < nx ? r.elem(i + 1) : r.c);
+        v[G - 1] = Cd::from_bits(rr);
     }
 }
 
-// pull() for the pair of nodes x0, x0 + 1 of row y; ga / gb receive their populations.
-template <class Cd>
-__device__ inline void pull_pair(const uint16_t* __restrict__ src, int nx, int ny, int stride,
-                                 long long plane, int x0, int y, bool first, bool last,
-                                 typename Cd::T u6, typename Cd::T ga[9],
-                                 typename Cd::T gb[9]) {
+// pull() for the group of nodes x0 .. x0 + G - 1 of row y; g[i] receives node x0 + i.
+template <class Cd, int G>
+__device__ inline void pull_group(const uint16_t* __restrict__ src, int nx, int ny, int stride,
+                                  long long plane, int x0, int y, bool first, bool last,
+                                  typename Cd::T u6, typename Cd::T g[G][9]) {
+    using T = typename Cd::T;
     const long long r0 = (long long)y * stride;
     const uint16_t* row = src + r0;
     const bool bottom = y == 0, top = y == ny - 1;
-    // rows and shifts of g_2, g_5, g_6 (from below, or reflected at the bottom wall) and
-    // g_4, g_7, g_8 (from above, or reflected at the top wall)
     const uint16_t* rm = bottom ? row : row - stride;
     const uint16_t* rp = top ? row : row + stride;
-    const PairRaw q0 = pair_load<0>(row, x0, nx, first, last);
-    const PairRaw q1 = pair_load<1>(row + plane, x0, nx, first, last);
-    const PairRaw q3 = pair_load<-1>(row + 3 * plane, x0, nx, first, last);
-    PairRaw q2, q5, q6, q4, q7, q8;
+    // g_2, g_5, g_6 come from the row below, or reflected at the bottom wall; g_4, g_7,
+    // g_8 from the row above, or reflected at the top wall
+    const GroupRaw<G> q0 = group_load<G, 0>(row, x0, nx, first, last);
+    const GroupRaw<G> q1 = group_load<G, 1>(row + plane, x0, nx, first, last);
+    const GroupRaw<G> q3 = group_load<G, -1>(row + 3 * plane, x0, nx, first, last);
+    GroupRaw<G> q2, q5, q6, q4, q7, q8;
     if (!bottom) {
-        q2 = pair_load<0>(rm + 2 * plane, x0, nx, first, last);
-        q5 = pair_load<1>(rm + 5 * plane, x0, nx, first, last);
-        q6 = pair_load<-1>(rm + 6 * plane, x0, nx, first, last);
+        q2 = group_load<G, 0>(rm + 2 * plane, x0, nx, first, last);
+        q5 = group_load<G, 1>(rm + 5 * plane, x0, nx, first, last);
+        q6 = group_load<G, -1>(rm + 6 * plane, x0, nx, first, last);
     } else {
-        q2 = pair_load<0>(row + 4 * plane, x0, nx, first, last);
-        q5 = pair_load<0>(row + 7 * plane, x0, nx, first, last);
-        q6 = pair_load<0>(row + 8 * plane, x0, nx, first, last);
+        q2 = group_load<G, 0>(row + 4 * plane, x0, nx, first, last);
+        q5 = group_load<G, 0>(row + 7 * plane, x0, nx, first, last);
+        q6 = group_load<G, 0>(row + 8 * plane, x0, nx, first, last);
     }
     if (!top) {
-        q4 = pair_load<0>(rp + 4 * plane, x0, nx, first, last);
-        q7 = pair_load<-1>(rp + 7 * plane, x0, nx, first, last);
-        q8 = pair_load<1>(rp + 8 * plane, x0, nx, first, last);
+        q4 = group_load<G, 0>(rp + 4 * plane, x0, nx, first, last);
+        q7 = group_load<G, -1>(rp + 7 * plane, x0, nx, first, last);
+        q8 = group_load<G, 1>(rp + 8 * plane, x0, nx, first, last);
     } else {
-        q4 = pair_load<0>(row + 2 * plane, x0, nx, first, last);
-        q7 = pair_load<0>(row + 5 * plane, x0, nx, first, last);
-        q8 = pair_load<0>(row + 6 * plane, x0, nx, first, last);
+        q4 = group_load<G, 0>(row + 2 * plane, x0, nx, first, last);
+        q7 = group_load<G, 0>(row + 5 * plane, x0, nx, first, last);
+        q8 = group_load<G, 0>(row + 6 * plane, x0, nx, first, last);
     }
-    pair_finish<Cd, 0>(q0, x0, nx, first, last, ga[0], gb[0]);
-    pair_finish<Cd, 1>(q1, x0, nx, first, last, ga[1], gb[1]);
-    pair_finish<Cd, -1>(q3, x0, nx, first, last, ga[3], gb[3]);
+    T v[G];
+#define FPD_PUT(K, Q, SX)                                               \
+    group_finish<Cd, G, SX>(Q, x0, nx, first, last, v);                 \
+    _Pragma("unroll") for (int i = 0; i < G; ++i) g[i][K] = v[i];
+    FPD_PUT(0, q0, 0)
+    FPD_PUT(1, q1, 1)
+    FPD_PUT(3, q3, -1)
     if (!bottom) {
-        pair_finish<Cd, 0>(q2, x0, nx, first, last, ga[2], gb[2]);
-        pair_finish<Cd, 1>(q5, x0, nx, first, last, ga[5], gb[5]);
-        pair_finish<Cd, -1>(q6, x0, nx, first, last, ga[6], gb[6]);
+        FPD_PUT(2, q2, 0)
+        FPD_PUT(5, q5, 1)
+        FPD_PUT(6, q6, -1)
     } else {
-        pair_finish<Cd, 0>(q2, x0, nx, first, last, ga[2], gb[2]);
-        pair_finish<Cd, 0>(q5, x0, nx, first, last, ga[5], gb[5]);
-        pair_finish<Cd, 0>(q6, x0, nx, first, last, ga[6], gb[6]);
-        ga[5] -= u6;
-        gb[5] -= u6;
-        ga[6] += u6;
-        gb[6] += u6;
+        FPD_PUT(2, q2, 0)
+        FPD_PUT(5, q5, 0)
+        FPD_PUT(6, q6, 0)
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            g[i][5] -= u6;
+            g[i][6] += u6;
+        }
     }
     if (!top) {
-        pair_finish<Cd, 0>(q4, x0, nx, first, last, ga[4], gb[4]);
-        pair_finish<Cd, -1>(q7, x0, nx, first, last, ga[7], gb[7]);
-        pair_finish<Cd, 1>(q8, x0, nx, first, last, ga[8], gb[8]);
+        FPD_PUT(4, q4, 0)
+        FPD_PUT(7, q7, -1)
+        FPD_PUT(8, q8, 1)
     } else {
-        pair_finish<Cd, 0>(q4, x0, nx, first, last, ga[4], gb[4]);
-        pair_finish<Cd, 0>(q7, x0, nx, first, last, ga[7], gb[7]);
-        pair_finish<Cd, 0>(q8, x0, nx, first, last, ga[8], gb[8]);
-        ga[7] -= u6;
-        gb[7] -= u6;
-        ga[8] += u6;
-        gb[8] += u6;
+        FPD_PUT(4, q4, 0)
+        FPD_PUT(7, q7, 0)
+        FPD_PUT(8, q8, 0)
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            g[i][7] -= u6;
+            g[i][8] += u6;
+        }
     }
+#undef FPD_PUT
 }
 
 // ---------------------------------------------------------- MRT collision ---------

@@ -326,18 +326,20 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     }
 }
 
-// lattice_tile for 2-byte storage: a tile is 2 * block_x nodes wide and each lane updates
-// two neighbouring nodes with the same per-node arithmetic as the one-node path.
+// lattice_tile for 2-byte storage: a tile is G * block_x nodes wide and each lane updates
+// G neighbouring nodes with the same per-node arithmetic as the one-node path.
 template <int ST, int SPT>
-__device__ inline void lattice_tile_pair(const StepArgs& a, const Window& win, int tile,
-                                         TileLds& lds) {
+__device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, int tile,
+                                          TileLds& lds) {
     using Cd = Codec<ST>;
     using T = typename Cd::T;
-    static_assert(sizeof(typename Cd::store_t) == 2, "pair path is for 2-byte storage");
+    constexpr int G = nodes_per_lane(ST);
+    static_assert(sizeof(typename Cd::store_t) == 2 && (G == 2 || G == 4),
+                  "group path is for 2-byte storage");
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int tw = 2 * (int)blockDim.x;
+    const int tw = G * (int)blockDim.x;
     const int xtile = tx * tw;
-    const int x0 = xtile + 2 * (int)threadIdx.x;
+    const int x0 = xtile + G * (int)threadIdx.x;
     const int lane = (int)threadIdx.x & 63;
     const bool first = lane == 0, last = lane == 63;
     const int ytile = ty * a.rows_per_block;
@@ -377,38 +379,52 @@ __device__ inline void lattice_tile_pair(const StepArgs& a, const Window& win, i
     for (int r = 0; r < SPT; ++r) {
         const int y = ybase + r;
         if (y >= ny) continue;  // uniform over a wave (its lanes share one row)
-        T ga[9], gb[9];
-        pull_pair<Cd>(src, nx, ny, stride, plane, x0, y, first, last, u6, ga, gb);
+        T g[G][9];
+        pull_group<Cd, G>(src, nx, ny, stride, plane, x0, y, first, last, u6, g);
         if (x0 >= nx) continue;
-        const bool has_b = x0 + 1 < nx;
-        T Fxa = T(0), Fya = T(0), nua = (T)a.s_nu_f, qa = (T)a.s_q_f;
-        T Fxb = T(0), Fyb = T(0), nub = (T)a.s_nu_f, qb = (T)a.s_q_f;
-        if (fiber_tile) {
-            fiber_node<T>(a, lds.R, lds.C, nb, x0, y, wx0, wy0, ww, wh, Fxa, Fya, nua, qa);
-            if (has_b)
-                fiber_node<T>(a, lds.R, lds.C, nb, x0 + 1, y, wx0, wy0, ww, wh, Fxb, Fyb, nub,
-                              qb);
+        uint32_t bits[9][G / 2];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
+            if (fiber_tile && x0 + i < nx)
+                fiber_node<T>(a, lds.R, lds.C, nb, x0 + i, y, wx0, wy0, ww, wh, Fx, Fy, s_nu,
+                              s_q);
+            mrt_collide<T>(g[i], Fx, Fy, s_nu, s_q, s_e, s_eps);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const uint32_t b = Cd::to_bits(g[i][k]);
+                if (i & 1) bits[k][i >> 1] |= b << 16;
+                else bits[k][i >> 1] = b;
+            }
         }
-        mrt_collide<T>(ga, Fxa, Fya, nua, qa, s_e, s_eps);
-        mrt_collide<T>(gb, Fxb, Fyb, nub, qb, s_e, s_eps);
         uint16_t* o = dst + (long long)y * stride + x0;
-        if (has_b) {
+        if (x0 + G - 1 < nx) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-                __builtin_nontemporal_store(Cd::to_bits(ga[k]) | (Cd::to_bits(gb[k]) << 16),
-                                            (uint32_t*)(o + k * plane));
+            for (int k = 0; k < 9; ++k) {
+                if constexpr (G == 2) {
+                    __builtin_nontemporal_store(bits[k][0], (uint32_t*)(o + k * plane));
+                } else {
+                    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                    u32x2 v;
+                    v.x = bits[k][0];
+                    v.y = bits[k][1];
+                    __builtin_nontemporal_store(v, (u32x2*)(o + k * plane));
+                }
+            }
         } else {
+            for (int i = 0; i < G && x0 + i < nx; ++i)
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-                __builtin_nontemporal_store((uint16_t)Cd::to_bits(ga[k]), o + k * plane);
+                for (int k = 0; k < 9; ++k)
+                    __builtin_nontemporal_store(
+                        (uint16_t)(bits[k][i >> 1] >> (16 * (i & 1))), o + i + k * plane);
         }
     }
 }
 
 template <int ST, int SPT>
 __device__ inline void tile_any(const StepArgs& a, const Window& win, int tile, TileLds& lds) {
-    if constexpr (nodes_per_lane(ST) == 2)
-        lattice_tile_pair<ST, SPT>(a, win, tile, lds);
+    if constexpr (nodes_per_lane(ST) > 1)
+        lattice_tile_group<ST, SPT>(a, win, tile, lds);
     else
         lattice_tile<ST, SPT>(a, win, tile, lds);
 }

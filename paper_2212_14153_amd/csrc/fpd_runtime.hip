@@ -59,7 +59,7 @@ int padded_stride(int nx) { return (nx + 63) / 64 * 64; }
 // two-byte formats (whose lanes update two nodes each).
 fpd_launch default_launch(int storage, int graph_chunk) {
     if (storage == FPD_F64) return fpd_launch{128, 2, 1, 2, graph_chunk};
-    if (nodes_per_lane(storage) == 2) return fpd_launch{64, 4, 2, 2, graph_chunk};
+    if (nodes_per_lane(storage) > 1) return fpd_launch{64, 4, 2, 2, graph_chunk};
     return fpd_launch{256, 1, 1, 2, graph_chunk};
 }
 
