@@ -45,6 +45,9 @@ class _Params(ctypes.Structure):
         ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double),
         ("s_q_fixed", ctypes.c_double),
         ("clamp_phi", ctypes.c_int),
+        ("periodic_y", ctypes.c_int),
+        ("fx_ext", ctypes.c_double), ("fy_ext", ctypes.c_double),
+        ("gx_body", ctypes.c_double), ("gy_body", ctypes.c_double),
     ]
 
 
@@ -66,11 +69,17 @@ class OracleParams:
     s_eps: float = 1.54
     s_q_fixed: float = 0.0
     clamp_phi: int = 0
+    periodic_y: int = 0       # 1: no walls (the single-particle box of Sec. III.B)
+    fx_ext: float = 0.0       # external force on every bead
+    fy_ext: float = 0.0
+    gx_body: float = 0.0      # uniform body force density on every node
+    gy_body: float = 0.0
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.u_wall, self.nu_f, self.eta_ratio, self.xi,
                        self.n_beads, self.radius, self.l0, self.k_s, self.k_b, self.s_e,
-                       self.s_eps, self.s_q_fixed, self.clamp_phi)
+                       self.s_eps, self.s_q_fixed, self.clamp_phi, self.periodic_y,
+                       self.fx_ext, self.fy_ext, self.gx_body, self.gy_body)
 
     @classmethod
     def from_mapping(cls, m) -> "OracleParams":
@@ -105,6 +114,8 @@ def lib():
         L.orc_run.argtypes = [P, _D, _D, ctypes.c_long, _D, _D, _D]
         L.orc_init.argtypes = [P, ctypes.c_int, _D]
         L.orc_macro.argtypes = [P, _D, _D, _D, _D, _D, _D]
+        L.orc_iso_gradient.argtypes = [P, _D, _D, _D]
+        L.orc_particle_stats.argtypes = [P, _D, _D, ctypes.c_int, _D]
         _lib = L
     return _lib
 
@@ -249,3 +260,26 @@ def macro(p: OracleParams, f, R):
     eta = np.zeros_like(rho)
     lib().orc_macro(ctypes.byref(p.c()), _p(f), _p(Rb), _p(rho), _p(ux), _p(uy), _p(eta))
     return rho, ux, uy, eta
+
+
+def iso_gradient(p: OracleParams, q):
+    """Isotropic D2Q9 gradient (gx, gy) of a node field q[ny, nx]."""
+    q = _f64(q, (p.ny, p.nx))
+    gx = np.zeros_like(q)
+    gy = np.zeros_like(q)
+    lib().orc_iso_gradient(ctypes.byref(p.c()), _p(q), _p(gx), _p(gy))
+    return gx, gy
+
+
+STATS_FIELDS = ("A", "V0x", "V0y", "eps_v", "Fvisc_x", "Fvisc_y", "Fpres_x", "Fpres_y")
+
+
+def particle_stats(p: OracleParams, f, R, bead: int = 0) -> dict:
+    """Single-particle diagnostics of Sec. III.B for one bead on the current state:
+    A, the phi-weighted velocity V0, eps_v (Eq. 15) and the viscous and pressure forces
+    of Eq. (17) in diffuse-interface form."""
+    f = _f64(f, (9, p.ny, p.nx))
+    Rb = _f64(R, (p.n_beads, 2))
+    out = np.zeros(8)
+    lib().orc_particle_stats(ctypes.byref(p.c()), _p(f), _p(Rb), int(bead), _p(out))
+    return dict(zip(STATS_FIELDS, out.tolist()))

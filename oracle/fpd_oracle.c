@@ -15,7 +15,8 @@
  *   - node (i, j) sits at the centre (i+1/2, j+1/2) of lattice square (i, j)
  *     (Sec. II.C, last paragraph before the integration steps);
  *   - the wall below y = 0 moves with -U x, the wall above y = ny with +U x, x is
- *     periodic (Sec. IV.A, Fig. 1b);
+ *     periodic (Sec. IV.A, Fig. 1b); or, for the single-particle benchmark of
+ *     Sec. III.B, no walls: x and y both periodic;
  *   - populations f are stored k-major: f[(k*ny + j)*nx + i], k = 0..8;
  *   - bead positions R[2*b + {0,1}], b = 0..N-1 (the paper's bead i is b = i-1).
  *
@@ -36,6 +37,17 @@
  *     U_b = -k_b sum_j t_{j+1}.t_j (linear in the cosine); they are evaluated here as
  *     printed, with tangents outside 1..N-1 taken as zero.
  *   - moving walls: half-way bounce-back with wall density rho0.
+ *   - the driven particle of Sec. III.B: a constant external force F0 on every bead,
+ *     added to F_i and spread by Eq. (4); in a periodic box a uniform body force g on
+ *     every node (the caller takes g = -N F0 / (nx ny)) removes the net momentum input,
+ *     so that the fluid far from the particle stays at rest on average.
+ *   - drag of Eq. (17): the printed normalisation by int phi does not give a force;
+ *     the diffuse-interface form of the surface integral is used, n dA -> -grad phi dr:
+ *     F = int (p grad phi - sigma . grad phi) dr with sigma = eta (grad v + grad v^T),
+ *     p = rho / 3, gradients by the isotropic D2Q9 stencil 3 sum_k w_k e_k q(x + e_k).
+ *     The viscous and pressure parts are returned separately.
+ *   - Eq. (15): V0 is the phi-weighted mean velocity of the particle, i.e. Eq. (5)
+ *     evaluated on the current state.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -56,6 +68,9 @@ typedef struct orc_params {
     double s_e, s_eps;    /* MRT rates of the energy and energy-square moments           */
     double s_q_fixed;     /* > 0: fixed heat-flux rate; <= 0: per-site magic value       */
     int    clamp_phi;     /* 1: clamp sum_i phi_i to 1 in Eq. (1) (off by default)       */
+    int    periodic_y;    /* 1: no walls, y periodic too (Sec. III.B benchmark box)      */
+    double fx_ext, fy_ext;   /* external force F0 on every bead                          */
+    double gx_body, gy_body; /* uniform body force density on every node                 */
 } orc_params;
 
 /* ---------------------------------------------------------- D2Q9 lattice ---------- */
@@ -112,7 +127,8 @@ static void proj_over_len(const double v[2], const double t[2], double L, double
 }
 
 /* F_i = F_i^s + F_i^b, Eq. (10): stretching force Eq. (11a,b) and bending force
- * Eq. (12a-e), each bead i = 1..N evaluated from the printed per-bead formulas. */
+ * Eq. (12a-e), each bead i = 1..N evaluated from the printed per-bead formulas; plus the
+ * external force F0 of the driven-particle benchmark (Sec. III.B). */
 void orc_bead_forces(const orc_params *p, const double *R, double *F)
 {
     const int N = p->n_beads;
@@ -149,20 +165,21 @@ void orc_bead_forces(const orc_params *p, const double *R, double *F)
             Fb[0] -= p->k_b * q[0];
             Fb[1] -= p->k_b * q[1];
         }
-        F[2 * (i - 1)] = Fs[0] + Fb[0];
-        F[2 * (i - 1) + 1] = Fs[1] + Fb[1];
+        F[2 * (i - 1)] = Fs[0] + Fb[0] + p->fx_ext;
+        F[2 * (i - 1) + 1] = Fs[1] + Fb[1] + p->fy_ext;
     }
 }
 
 /* ---------------------------------------------- Eq. (2): interface profile -------- */
 
-/* phi_i at node (i, j) for a bead centred at (Rx, Ry); the x distance is the
- * minimum image on the periodic lattice. */
+/* phi_i at node (i, j) for a bead centred at (Rx, Ry); distances along periodic
+ * directions are minimum images. */
 double orc_phi(const orc_params *p, double Rx, double Ry, int i, int j)
 {
     double dx = ((double)i + 0.5) - Rx;
     double dy = ((double)j + 0.5) - Ry;
     dx -= (double)p->nx * floor(dx / (double)p->nx + 0.5);
+    if (p->periodic_y) dy -= (double)p->ny * floor(dy / (double)p->ny + 0.5);
     double r = sqrt(dx * dx + dy * dy);
     double t = (p->radius - r) / p->xi;
     if (t <= -TANH_SATURATION) return 0.0;     /* tanh(t) is exactly -1 here */
@@ -174,6 +191,11 @@ double orc_phi(const orc_params *p, double Rx, double Ry, int i, int j)
  * and the loops skip them without changing any result. */
 static void phi_rows(const orc_params *p, double Ry, int *jlo, int *jhi)
 {
+    if (p->periodic_y) {     /* the support may wrap: take every row */
+        *jlo = 0;
+        *jhi = p->ny - 1;
+        return;
+    }
     double reach = p->radius + TANH_SATURATION * p->xi + 1.0;
     int lo = (int)floor(Ry - reach), hi = (int)ceil(Ry + reach);
     *jlo = lo < 0 ? 0 : lo;
@@ -183,7 +205,8 @@ static void phi_rows(const orc_params *p, double Ry, int *jlo, int *jhi)
 /* Step (1) of Sec. II.C at time n, evaluated from the bead positions R^n:
  *   phi_i^n at every node (Eq. (2)), stored for the rows where it can be non-zero;
  *   A_i = int phi_i^n, the lattice sum in the denominators of Eqs. (4) and (5);
- *   F_i^n (Eqs. (10)-(12)); the force density f^n (Eq. (4)); eta^n (Eq. (1)). */
+ *   F_i^n (Eqs. (10)-(12)); the force density f^n (Eq. (4), plus the uniform body
+ *   force g); eta^n (Eq. (1)). */
 typedef struct stage1 {
     int     N;
     int    *jlo, *jhi;      /* phi_i rows: phi[i] holds rows jlo[i]..jhi[i], all columns */
@@ -246,6 +269,8 @@ static void stage1_compute(const orc_params *p, const double *R, stage1 *s1)
         double sp = sphi[s];
         if (p->clamp_phi && sp > 1.0) sp = 1.0;
         s1->eta[s] = eta_f + (eta_s - eta_f) * sp;         /* Eq. (1) */
+        s1->fx[s] += p->gx_body;                           /* uniform body force */
+        s1->fy[s] += p->gy_body;
     }
     free(sphi);
 }
@@ -366,8 +391,8 @@ static double q_rate(const orc_params *p, double s_nu)
 
 /* -------------------------------------------- streaming with moving walls --------- */
 
-/* Push every post-collision population to its neighbour; x wraps; a population that
- * would leave through a wall is reflected half-way back into the opposite direction at
+/* Push every post-collision population to its neighbour; x wraps (y too without
+ * walls); a population that would leave through a wall is reflected half-way back into the opposite direction at
  * the same node and picks up 6 w rho0 (e . u_wall) (moving-wall bounce-back). */
 void orc_stream(const orc_params *p, const double *fpost, double *fnew)
 {
@@ -377,6 +402,7 @@ void orc_stream(const orc_params *p, const double *fpost, double *fnew)
             for (int i = 0; i < nx; ++i) {
                 double v = fpost[idx(p, k, i, j)];
                 int jd = j + EY[k];
+                if (p->periodic_y) jd = (jd + ny) % ny;
                 if (jd >= 0 && jd < ny) {
                     int id = ((i + EX[k]) % nx + nx) % nx;
                     fnew[idx(p, k, id, jd)] = v;
@@ -542,4 +568,100 @@ void orc_macro(const orc_params *p, const double *f, const double *R, double *rh
         }
     memcpy(eta, s1.eta, S * sizeof(double));
     stage1_free(&s1);
+}
+
+/* ------------------------------------- single-particle diagnostics (Sec. III.B) -- */
+
+/* Isotropic D2Q9 gradient of a node field q: grad q (x) = 3 sum_k w_k e_k q(x + e_k)
+ * (the isotropic discretisation the paper uses for gradients of phase-field variables,
+ * Sec. II.C).  Neighbours wrap along periodic directions; with walls, rows 0 and ny-1
+ * have no complete stencil and get NaN. */
+void orc_iso_gradient(const orc_params *p, const double *q, double *gx, double *gy)
+{
+    const int nx = p->nx, ny = p->ny;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t s = (size_t)j * (size_t)nx + (size_t)i;
+            if (!p->periodic_y && (j == 0 || j == ny - 1)) {
+                gx[s] = NAN;
+                gy[s] = NAN;
+                continue;
+            }
+            double ax = 0.0, ay = 0.0;
+            for (int k = 1; k < 9; ++k) {
+                int in = ((i + EX[k]) % nx + nx) % nx;
+                int jn = ((j + EY[k]) % ny + ny) % ny;
+                double v = q[(size_t)jn * (size_t)nx + (size_t)in];
+                ax += W[k] * EX[k] * v;
+                ay += W[k] * EY[k] * v;
+            }
+            gx[s] = 3.0 * ax;
+            gy[s] = 3.0 * ay;
+        }
+}
+
+/* Diagnostics of bead b on the current state (pre-collision f at step n, positions R^n):
+ *   out[0]    A = sum_x phi_b
+ *   out[1,2]  V0 = sum_x phi_b v / A, v = (j + f^n/2)/rho (Eq. (5) on this state)
+ *   out[3]    eps_v = sum_x phi_b |v - V0|^2 / A (Eq. (15))
+ *   out[4,5]  viscous force of the fluid on the particle, -sum_x sigma . grad phi_b,
+ *             sigma = eta (grad v + grad v^T) with eta of Eq. (1)
+ *   out[6,7]  pressure force, sum_x p grad phi_b with p = rho/3
+ * (Eq. (17) in its diffuse-interface form: n dA -> -grad phi dr.) */
+void orc_particle_stats(const orc_params *p, const double *f, const double *R, int b,
+                        double *out)
+{
+    const int nx = p->nx, ny = p->ny;
+    const size_t S = (size_t)nx * (size_t)ny;
+    double *rho = (double *)malloc(S * sizeof(double));
+    double *vx = (double *)malloc(S * sizeof(double));
+    double *vy = (double *)malloc(S * sizeof(double));
+    double *eta = (double *)malloc(S * sizeof(double));
+    double *ph = (double *)malloc(S * sizeof(double));
+    double *g[6];
+    for (int m = 0; m < 6; ++m) g[m] = (double *)malloc(S * sizeof(double));
+    orc_macro(p, f, R, rho, vx, vy, eta);
+    double A = 0.0;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t s = (size_t)j * (size_t)nx + (size_t)i;
+            ph[s] = orc_phi(p, R[2 * b], R[2 * b + 1], i, j);
+            A += ph[s];
+        }
+    double mx = 0.0, my = 0.0;
+    for (size_t s = 0; s < S; ++s) {
+        mx += ph[s] * vx[s];
+        my += ph[s] * vy[s];
+    }
+    const double V0x = mx / A, V0y = my / A;
+    double e = 0.0;
+    for (size_t s = 0; s < S; ++s) {
+        double dx = vx[s] - V0x, dy = vy[s] - V0y;
+        e += ph[s] * (dx * dx + dy * dy);
+    }
+    orc_iso_gradient(p, ph, g[0], g[1]);   /* d_x phi, d_y phi */
+    orc_iso_gradient(p, vx, g[2], g[3]);   /* d_x vx, d_y vx   */
+    orc_iso_gradient(p, vy, g[4], g[5]);   /* d_x vy, d_y vy   */
+    double fvx = 0.0, fvy = 0.0, fpx = 0.0, fpy = 0.0;
+    for (size_t s = 0; s < S; ++s) {
+        double dpx = g[0][s], dpy = g[1][s];
+        if (dpx == 0.0 && dpy == 0.0) continue;   /* outside the interface */
+        double sxx = eta[s] * 2.0 * g[2][s];
+        double syy = eta[s] * 2.0 * g[5][s];
+        double sxy = eta[s] * (g[3][s] + g[4][s]);
+        fvx -= sxx * dpx + sxy * dpy;
+        fvy -= sxy * dpx + syy * dpy;
+        fpx += rho[s] / 3.0 * dpx;
+        fpy += rho[s] / 3.0 * dpy;
+    }
+    out[0] = A;
+    out[1] = V0x;
+    out[2] = V0y;
+    out[3] = e / A;
+    out[4] = fvx;
+    out[5] = fvy;
+    out[6] = fpx;
+    out[7] = fpy;
+    for (int m = 0; m < 6; ++m) free(g[m]);
+    free(rho); free(vx); free(vy); free(eta); free(ph);
 }
