@@ -44,7 +44,8 @@
  *   - drag of Eq. (17): the printed normalisation by int phi does not give a force;
  *     the diffuse-interface form of the surface integral is used, n dA -> -grad phi dr:
  *     F = int (p grad phi - sigma . grad phi) dr with sigma = eta (grad v + grad v^T),
- *     p = rho / 3, gradients by the isotropic D2Q9 stencil 3 sum_k w_k e_k q(x + e_k).
+ *     p = rho / 3 taken relative to rho0 / 3, gradients by the isotropic D2Q9 stencil
+ *     3 sum_k w_k e_k q(x + e_k).
  *     The viscous and pressure parts are returned separately.
  *   - Eq. (15): V0 is the phi-weighted mean velocity of the particle, i.e. Eq. (5)
  *     evaluated on the current state.
@@ -606,8 +607,11 @@ void orc_iso_gradient(const orc_params *p, const double *q, double *gx, double *
  *   out[3]    eps_v = sum_x phi_b |v - V0|^2 / A (Eq. (15))
  *   out[4,5]  viscous force of the fluid on the particle, -sum_x sigma . grad phi_b,
  *             sigma = eta (grad v + grad v^T) with eta of Eq. (1)
- *   out[6,7]  pressure force, sum_x p grad phi_b with p = rho/3
- * (Eq. (17) in its diffuse-interface form: n dA -> -grad phi dr.) */
+ *   out[6,7]  pressure force, sum_x (p - p0) grad phi_b with p = rho/3, p0 = 1/3 (the
+ *             constant p0 adds nothing: sum_x grad phi_b telescopes to zero, and leaving
+ *             it out avoids summing O(1) terms that cancel)
+ * (Eq. (17) in its diffuse-interface form: n dA -> -grad phi dr.)  With walls the forces
+ * are NaN when phi_b reaches the two outer rows at a wall (incomplete stencil). */
 void orc_particle_stats(const orc_params *p, const double *f, const double *R, int b,
                         double *out)
 {
@@ -642,8 +646,19 @@ void orc_particle_stats(const orc_params *p, const double *f, const double *R, i
     orc_iso_gradient(p, ph, g[0], g[1]);   /* d_x phi, d_y phi */
     orc_iso_gradient(p, vx, g[2], g[3]);   /* d_x vx, d_y vx   */
     orc_iso_gradient(p, vy, g[4], g[5]);   /* d_x vy, d_y vy   */
+    /* with walls the stencil is incomplete on rows 0 and ny-1: they hold no interface
+     * as long as phi_b vanishes on the two outer rows at each wall; otherwise the
+     * forces are undefined (NaN) */
+    int wall_touch = 0;
+    if (!p->periodic_y)
+        for (int i = 0; i < nx; ++i)
+            for (int r = 0; r < 2 && r < ny; ++r)
+                if (ph[(size_t)r * nx + i] != 0.0 || ph[(size_t)(ny - 1 - r) * nx + i] != 0.0)
+                    wall_touch = 1;
     double fvx = 0.0, fvy = 0.0, fpx = 0.0, fpy = 0.0;
     for (size_t s = 0; s < S; ++s) {
+        int j = (int)(s / (size_t)nx);
+        if (!p->periodic_y && (j == 0 || j == ny - 1) && !wall_touch) continue;
         double dpx = g[0][s], dpy = g[1][s];
         if (dpx == 0.0 && dpy == 0.0) continue;   /* outside the interface */
         double sxx = eta[s] * 2.0 * g[2][s];
@@ -651,8 +666,8 @@ void orc_particle_stats(const orc_params *p, const double *f, const double *R, i
         double sxy = eta[s] * (g[3][s] + g[4][s]);
         fvx -= sxx * dpx + sxy * dpy;
         fvy -= sxy * dpx + syy * dpy;
-        fpx += rho[s] / 3.0 * dpx;
-        fpy += rho[s] / 3.0 * dpy;
+        fpx += (rho[s] - 1.0) / 3.0 * dpx;
+        fpy += (rho[s] - 1.0) / 3.0 * dpy;
     }
     out[0] = A;
     out[1] = V0x;

@@ -207,3 +207,19 @@ def test_drag_converges_to_the_steady_momentum_balance():
     # the particle is nearly rigid at r_eta = 50 (Sec. III.B): the rms residual flow
     # inside it is a few per cent of its speed (0.3 % of V0^2 in eps_v here)
     assert 0 < s2["eps_v"] < 1e-2 * s2["V0x"] ** 2
+
+
+def test_wall_rows_are_skipped_unless_the_particle_reaches_them():
+    n = 40
+    p = ORC.OracleParams(nx=n, ny=60, n_beads=1, radius=3.0, xi=1.0, nu_f=0.1, eta_ratio=1.0)
+    x, y = grid(n)
+    f = equilibrium(np.ones((60, n)), 1e-3 * np.sin(2 * math.pi * x[:1].repeat(60, 0) / n),
+                    np.zeros((60, n)))
+    s = ORC.particle_stats(p, f, np.array([[20.3, 30.1]]))     # support ends at row 54
+    assert all(np.isfinite(v) for v in s.values())
+    pw = ORC.OracleParams(**{**p.__dict__, "periodic_y": 1})
+    sw = ORC.particle_stats(pw, f, np.array([[20.3, 30.1]]))   # same sums in a periodic box
+    for k in s:
+        assert s[k] == pytest.approx(sw[k], rel=1e-13, abs=1e-30)
+    near = ORC.particle_stats(p, f, np.array([[20.3, 10.0]]))  # support reaches row 0
+    assert math.isnan(near["Fvisc_x"])
