@@ -10,7 +10,8 @@
  *       eta^n (Eq. 1);
  *   (2) one MRT-LBM collide-and-stream update of the fluid with the local viscosity
  *       eta^n and the force density f^n, walls at y = 0 and y = H moving at -U and +U
- *       (Sec. IV.A, Fig. 1b), x periodic;
+ *       (Sec. IV.A, Fig. 1b), x periodic; or, for the driven-particle benchmark of
+ *       Sec. III.B, no walls (x and y periodic, FPD_PERIODIC);
  *   (3) the bead velocities V_i^{n+1} (Eq. 5) and the forward-Euler update
  *       R_i^{n+1} = R_i^n + dt V_i^{n+1}.
  *
@@ -26,8 +27,9 @@
  *     e_0 = (0,0), e_1..e_4 = (1,0),(0,1),(-1,0),(0,-1),
  *     e_5..e_8 = (1,1),(-1,1),(-1,-1),(1,-1);
  *   per-node fields [ny][nx]; bead arrays [n_beads][2].
- * Device-side layout (not visible through this ABI): nine SoA planes, rows padded to a
- * multiple of 64 elements, two buffers (pull streaming), stored as f - w_k.
+ * Device-side layout (not visible through this ABI): two buffers (pull streaming) of
+ * f - w_k; value (k, j, i) at j * 9P + k * P + i with P = nx rounded up to 64 (the nine
+ * direction rows of a lattice row side by side).
  *
  * Errors: every int-returning call returns FPD_OK (0) or a negative FPD_E* code and
  * never throws; fpd_last_error() gives a message for the calling thread.  Calls on one
@@ -62,6 +64,10 @@ extern "C" {
 #define FPD_INIT_REST            0   /* rho = 1, u = 0 everywhere                         */
 #define FPD_INIT_LINEAR_COUETTE  1   /* equilibrium at u_x = U (2 y / H - 1)              */
 
+/* boundary in y */
+#define FPD_WALLS     0   /* moving walls at y = 0 and y = ny (Sec. IV.A)                  */
+#define FPD_PERIODIC  1   /* no walls: y periodic too (the box of Sec. III.B)               */
+
 /* flags */
 #define FPD_FLAG_CLAMP_PHI     0x1u  /* clamp sum_i phi_i to 1 in Eq. (1)                 */
 #define FPD_FLAG_NO_GRAPH      0x2u  /* launch every kernel directly (no graph replay)    */
@@ -71,7 +77,7 @@ extern "C" {
 #define FPD_HEALTH_NAN      0x1u   /* NaN or Inf in a bead position or velocity           */
 #define FPD_HEALTH_STRAIN   0x2u   /* a bond is stretched or compressed by more than 50%  */
 #define FPD_HEALTH_MACH     0x4u   /* a bead moves faster than 0.3 c_s                    */
-#define FPD_HEALTH_WALL     0x8u   /* a bead came within a + xi of a wall                 */
+#define FPD_HEALTH_WALL     0x8u   /* a bead came within a + xi of a wall (FPD_WALLS)     */
 #define FPD_HEALTH_SUPPORT  0x10u  /* the fiber outgrew the reserved support window       */
 
 #define FPD_MAX_BEADS 256
@@ -96,12 +102,17 @@ typedef struct fpd_params {
     int32_t  storage;       /* FPD_F64 | FPD_F32 | FPD_F16DEV | FPD_BF16DEV                 */
     int32_t  init_flow;     /* FPD_INIT_REST | FPD_INIT_LINEAR_COUETTE                      */
     uint32_t flags;         /* FPD_FLAG_*                                                   */
+    int32_t  boundary;      /* FPD_WALLS | FPD_PERIODIC (then u_wall = 0, FPD_INIT_REST)    */
+    double   f_ext[2];      /* external force added to F_i of every bead (the driving force
+                               F0 of Sec. III.B), spread by Eq. (4) like F_i               */
+    double   g_body[2];     /* uniform body force density on every node; in a periodic box
+                               g = -N f_ext / (nx ny) keeps the total momentum constant     */
 } fpd_params;
 
 /* Launch shape of the fused lattice kernel; any field <= 0 keeps the current value. */
 typedef struct fpd_launch {
     int32_t block_x;          /* threads per block along x: 64, 128 or 256                 */
-    int32_t block_y;          /* thread rows per block: 1, 2, 4 (block_x*block_y <= 1024)  */
+    int32_t block_y;          /* thread rows per block: 1, 2, 4 (block_x*block_y <= 256)   */
     int32_t rows_per_thread;  /* lattice rows per thread: 1, 2 or 4                         */
     int32_t xcd_remap;        /* 1: consecutive tiles on one XCD; 2: off                    */
     int32_t graph_chunk;      /* steps per captured graph (even, >= 2)                      */
@@ -186,6 +197,20 @@ int fpd_write_populations(fpd_sim *s, const double *f);
 
 /* Host [n_beads][2] each, NULL to skip: R^n, V^n (velocity of the last step), F^n. */
 int fpd_read_beads(fpd_sim *s, double *R, double *V, double *F);
+
+/* Diagnostics of the driven-particle benchmark (Sec. III.B) for bead `bead` on the
+ * current state (pre-collision populations at step n, positions R^n, force density f^n
+ * of that state), computed on the device with fixed-order FP64 sums; synchronises.
+ * out[8] (host): A = sum_x phi_b; V0 = sum_x phi_b v / A with v = (j + f^n/2)/rho
+ * (Eq. 5 on this state); eps_v = sum_x phi_b |v - V0|^2 / A (Eq. 15); the viscous
+ * force -sum_x sigma . grad phi_b with sigma = eta (grad v + grad v^T), eta of Eq. (1),
+ * and the pressure force sum_x ((rho - 1)/3) grad phi_b (the reference pressure 1/3
+ * contributes nothing) (Eq. 17 in diffuse-interface form:
+ * n dA -> -grad phi dr).  Gradients use the isotropic D2Q9 stencil
+ * grad q (x) = 3 sum_k w_k e_k q(x + e_k).  Sums run over the bead's support box grown by
+ * one node.  FPD_EINVAL if there is no such bead or, with walls, if that box reaches the
+ * first or last row (the stencil would leave the channel). */
+int fpd_particle_stats(fpd_sim *s, int32_t bead, double *out);
 
 /* ---------------------------------------------------------------- tuning ----- */
 

@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("FPD_LIBRARY") or os.path.join(HERE, "libfpdlbm.so")
 FPD_OK, FPD_EINVAL, FPD_ENOMEM, FPD_EUNSTABLE, FPD_EDEVICE, FPD_ESTATE = 0, -1, -2, -3, -4, -5
 FPD_F64, FPD_F32, FPD_F16DEV, FPD_BF16DEV = 0, 1, 2, 3
 FPD_INIT_REST, FPD_INIT_LINEAR_COUETTE = 0, 1
+FPD_WALLS, FPD_PERIODIC = 0, 1
 FPD_FLAG_CLAMP_PHI, FPD_FLAG_NO_GRAPH, FPD_FLAG_TIME_KERNELS = 0x1, 0x2, 0x4
 FPD_HEALTH_NAN, FPD_HEALTH_STRAIN, FPD_HEALTH_MACH, FPD_HEALTH_WALL, FPD_HEALTH_SUPPORT = (
     0x1, 0x2, 0x4, 0x8, 0x10)
@@ -40,6 +41,8 @@ class fpd_params(ctypes.Structure):
         ("s_q_fixed", ctypes.c_double), ("cutoff", ctypes.c_double),
         ("storage", ctypes.c_int32), ("init_flow", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("boundary", ctypes.c_int32),
+        ("f_ext", ctypes.c_double * 2), ("g_body", ctypes.c_double * 2),
     ]
 
 
@@ -80,6 +83,7 @@ SIGNATURES = [
     ("fpd_read_populations", ctypes.c_int, [_SIM, _D]),
     ("fpd_write_populations", ctypes.c_int, [_SIM, _D]),
     ("fpd_read_beads", ctypes.c_int, [_SIM, _D, _D, _D]),
+    ("fpd_particle_stats", ctypes.c_int, [_SIM, ctypes.c_int32, _D]),
     ("fpd_set_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_get_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_set_flags", ctypes.c_int, [_SIM, ctypes.c_uint32]),
@@ -186,7 +190,8 @@ def params_from_mapping(m, storage=None, **over) -> fpd_params:
     d.update(over)
     for name, _ in fpd_params._fields_:
         if name in d and name != "storage":
-            setattr(p, name, d[name])
+            v = d[name]
+            setattr(p, name, tuple(v) if name in ("f_ext", "g_body") else v)
     st = storage if storage is not None else d.get("storage", "f32")
     p.storage = STORAGE[st] if isinstance(st, str) else int(st)
     return p
@@ -276,6 +281,15 @@ class Simulation:
         out = [np.empty((self.ny, self.nx)) for _ in range(4)]
         check(lib().fpd_read_fields(self.h, *[_ptr(o) for o in out]))
         return tuple(out)
+
+    STATS_FIELDS = ("A", "V0x", "V0y", "eps_v", "Fvisc_x", "Fvisc_y", "Fpres_x", "Fpres_y")
+
+    def particle_stats(self, bead: int = 0) -> dict:
+        """Driven-particle diagnostics of one bead on the current state (fpd_particle_stats):
+        A, the phi-weighted velocity V0, eps_v (Eq. 15), viscous and pressure forces."""
+        out = np.empty(8)
+        check(lib().fpd_particle_stats(self.h, int(bead), _ptr(out)))
+        return dict(zip(self.STATS_FIELDS, out.tolist()))
 
     def beads(self):
         R = np.empty((max(self.n, 0), 2))

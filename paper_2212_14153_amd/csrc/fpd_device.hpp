@@ -108,8 +108,10 @@ __device__ inline bool bead_sane(double Rx, double Ry) {
     return fabs(Rx) < 1.0e9 && fabs(Ry) < 1.0e9;  // false for NaN too
 }
 
-__device__ inline void bead_box(double Rx, double Ry, double rc, int nx, int ny, int& i0,
-                                int& w, int& j0, int& j1) {
+// With walls, rows j0..j1 are clipped to the channel; in a periodic box (per) they are
+// j0 .. j1 with j0 in [0, ny) and j1 - j0 < ny, to be taken modulo ny.
+__device__ inline void bead_box(double Rx, double Ry, double rc, int nx, int ny, bool per,
+                                int& i0, int& w, int& j0, int& j1) {
     if (!bead_sane(Rx, Ry)) {
         i0 = 0;
         w = 0;
@@ -128,6 +130,12 @@ __device__ inline void bead_box(double Rx, double Ry, double rc, int nx, int ny,
     }
     const int a = (int)floor(Ry - 0.5 - rc);
     const int b = (int)ceil(Ry - 0.5 + rc);
+    if (per) {
+        const int h = b - a + 1 < ny ? b - a + 1 : ny;
+        j0 = h == ny ? 0 : imod(a, ny);
+        j1 = j0 + h - 1;
+        return;
+    }
     j0 = a < 0 ? 0 : a;
     j1 = b > ny - 1 ? ny - 1 : b;
 }
@@ -151,6 +159,11 @@ __device__ inline double min_image(double dx, int nx) {
         return dx;
     }
     return dx - n * floor(dx / n + 0.5);
+}
+
+// y distance: the minimum image in a periodic box, plain between walls.
+__device__ inline double y_image(double dy, int ny, bool per) {
+    return per ? min_image(dy, ny) : dy;
 }
 
 // phi of Eq. (2): 1/2 (tanh((a - r)/xi) + 1).
@@ -182,13 +195,14 @@ template <> struct PhiEval<float> {
 };
 
 // -------------------------------------------------------------- pull streaming -----
-// g[k] <- post-collision g*_k at x - e_k; x wraps; a population that would come from
-// behind a wall is the node's own reflected g*_{opp(k)} plus 6 w_k rho0 (e_k . u_wall),
-// i.e. +-U/6 on the diagonals (u_wall = -U below, +U above).
+// g[k] <- post-collision g*_k at x - e_k; x wraps (y too in a periodic box, per); a
+// population that would come from behind a wall is the node's own reflected g*_{opp(k)}
+// plus 6 w_k rho0 (e_k . u_wall), i.e. +-U/6 on the diagonals (u_wall = -U below, +U
+// above).
 
 template <class Cd>
 __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx, int ny,
-                            int stride, long long plane, int x, int y,
+                            int stride, long long plane, int x, int y, bool per,
                             typename Cd::T u6, typename Cd::T g[9]) {
     using S = typename Cd::store_t;
     const int xm = (x == 0) ? nx - 1 : x - 1;
@@ -206,8 +220,8 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
     g[0] = Cd::load(p0 + r0 + x);
     g[1] = Cd::load(p1 + r0 + xm);
     g[3] = Cd::load(p3 + r0 + xp);
-    if (y > 0) {
-        const int rm = r0 - stride;
+    if (y > 0 || per) {
+        const int rm = y > 0 ? r0 - stride : (ny - 1) * stride;
         g[2] = Cd::load(p2 + rm + x);
         g[5] = Cd::load(p5 + rm + xm);
         g[6] = Cd::load(p6 + rm + xp);
@@ -216,8 +230,8 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
         g[5] = Cd::load(p7 + r0 + x) - u6;
         g[6] = Cd::load(p8 + r0 + x) + u6;
     }
-    if (y < ny - 1) {
-        const int rp = r0 + stride;
+    if (y < ny - 1 || per) {
+        const int rp = y < ny - 1 ? r0 + stride : 0;
         g[4] = Cd::load(p4 + rp + x);
         g[7] = Cd::load(p7 + rp + xp);
         g[8] = Cd::load(p8 + rp + xm);
@@ -303,14 +317,14 @@ __device__ inline void group_finish(const GroupRaw<G>& r, int x0, int nx, bool f
 // pull() for the group of nodes x0 .. x0 + G - 1 of row y; g[i] receives node x0 + i.
 template <class Cd, int G>
 __device__ inline void pull_group(const uint16_t* __restrict__ src, int nx, int ny, int stride,
-                                  long long plane, int x0, int y, bool first, bool last,
-                                  typename Cd::T u6, typename Cd::T g[G][9]) {
+                                  long long plane, int x0, int y, bool per, bool first,
+                                  bool last, typename Cd::T u6, typename Cd::T g[G][9]) {
     using T = typename Cd::T;
     const long long r0 = (long long)y * stride;
     const uint16_t* row = src + r0;
-    const bool bottom = y == 0, top = y == ny - 1;
-    const uint16_t* rm = bottom ? row : row - stride;
-    const uint16_t* rp = top ? row : row + stride;
+    const bool bottom = y == 0 && !per, top = y == ny - 1 && !per;
+    const uint16_t* rm = y > 0 ? row - stride : (per ? row + (long long)(ny - 1) * stride : row);
+    const uint16_t* rp = y < ny - 1 ? row + stride : (per ? src : row);
     // g_2, g_5, g_6 come from the row below, or reflected at the bottom wall; g_4, g_7,
     // g_8 from the row above, or reflected at the top wall
     const GroupRaw<G> q0 = group_load<G, 0>(row, x0, nx, first, last);

@@ -44,6 +44,7 @@ constexpr int nodes_per_lane(int storage) {
 
 struct Lattice {
     int nx, ny, stride;       // stride: row pitch in elements
+    int periodic;             // 1: no walls, y wraps like x (FPD_PERIODIC)
     long long plane;          // offset between directions k and k + 1 in elements
 };
 
@@ -59,6 +60,7 @@ struct Fiber {
     void* rect_f;             // force density f^n on the support window, [h][w][2] of T
     int rect_wmax, rect_hmax; // reserved window
     double l0, ks_l02, kb;    // spring rest length, k_s / l0^2, k_b
+    double fext[2];           // external force on every bead
 };
 
 struct StepArgs {
@@ -69,6 +71,7 @@ struct StepArgs {
     double u6;                // U / 6 (moving-wall momentum on the diagonals)
     double s_nu_f, s_q_f;     // fluid shear and heat-flux rates away from the fiber
     double s_e, s_eps;
+    double gx, gy;            // uniform body force density on every node
     Fiber fib;
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
     int rows_per_block;       // block_y * rows_per_thread
@@ -90,14 +93,26 @@ struct BatchArgs {
     int gpar;                 // parity of this step within the chunk
 };
 
+// A box of nodes: columns cx0 + [0, cw) and rows cy0 + [0, ch), modulo the lattice along
+// periodic directions.  A box that spans a whole period along a direction (wrap_x: cw ==
+// nx; wrap_y: ch == ny in a periodic box) wraps onto itself there: neighbour lookups
+// inside it are then taken modulo its size.  Otherwise its one-node border only feeds
+// the gradient stencil of the nodes inside.
+struct NodeBox {
+    int cx0, cw, cy0, ch;
+    bool wrap_x, wrap_y;
+};
+
 // Kernel launchers (fpd_kernels.hip).
 hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
                        hipStream_t st);
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
                        hipStream_t st);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);
+// any_periodic: some simulation of the batch has no walls (the kernel then reads the
+// boundary of each simulation from its arguments)
 hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int rows_per_thread,
-                             const int counts[3], hipStream_t st);
+                             const int counts[3], bool any_periodic, hipStream_t st);
 hipError_t health_gather(BeadState* const* states, unsigned* out, int n, hipStream_t st);
 hipError_t launch_unstream(int storage, const Lattice& L, double u_wall, const double* f64,
                            void* dst, hipStream_t st);
@@ -108,5 +123,8 @@ hipError_t launch_init_eq(const Lattice& L, double u_wall, int init_flow, double
 hipError_t launch_fields(int storage, const StepArgs& a, double* rho, double* ux,
                          double* uy, double* eta, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+// fields[4 * cw * ch] (device scratch), out[8] (device)
+hipError_t launch_particle_stats(int storage, const StepArgs& a, int bead, const NodeBox& B,
+                                 double* fields, double* out, hipStream_t st);
 
 }  // namespace fpd

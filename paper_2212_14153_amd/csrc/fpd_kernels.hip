@@ -79,9 +79,9 @@ __device__ inline void add_proj(const Bonds& B, int u, int v, double sg_kb, doub
 }
 
 __device__ inline void bead_force(const Bonds& B, int N, int t, double ks_l02, double l0,
-                                  double kb, double F[2]) {
-    F[0] = 0.0;
-    F[1] = 0.0;
+                                  double kb, const double fext[2], double F[2]) {
+    F[0] = fext[0];  // external driving force (Sec. III.B), zero for the fiber runs
+    F[1] = fext[1];
     if (t >= 1) {  // bond (t-1, t): pulls t back towards t-1 when stretched
         const double s = ks_l02 * (B.L[t - 1] - l0);
         F[0] -= s * B.t[t - 1][0];
@@ -108,7 +108,8 @@ struct Window {
     bool clamped;
 };
 
-__device__ inline Window decode_window(const int* raw, int nx, int ny, int wmax, int hmax) {
+__device__ inline Window decode_window(const int* raw, int nx, int ny, bool per, int wmax,
+                                       int hmax) {
     Window r{0, 0, 0, 0, false};
     const int lo = raw[0], hi = raw[1], j0 = raw[2], j1 = raw[3];
     if (lo > hi || j0 > j1) return r;
@@ -119,9 +120,19 @@ __device__ inline Window decode_window(const int* raw, int nx, int ny, int wmax,
     } else {
         r.x0 = imod(lo, nx);
     }
-    r.y0 = j0 < 0 ? 0 : j0;
-    const int y1 = j1 > ny - 1 ? ny - 1 : j1;
-    r.h = y1 >= r.y0 ? y1 - r.y0 + 1 : 0;
+    if (per) {  // rows wrap like columns
+        r.h = j1 - j0 + 1;
+        if (r.h >= ny) {
+            r.h = ny;
+            r.y0 = 0;
+        } else {
+            r.y0 = imod(j0, ny);
+        }
+    } else {
+        r.y0 = j0 < 0 ? 0 : j0;
+        const int y1 = j1 > ny - 1 ? ny - 1 : j1;
+        r.h = y1 >= r.y0 ? y1 - r.y0 + 1 : 0;
+    }
     if (r.w > wmax || r.h > hmax) {
         r.clamped = true;
         r.w = min(r.w, wmax);
@@ -154,9 +165,9 @@ __device__ inline void own_bead(const Fiber& fib, const Bonds& B, int N, int b,
 // Ordered compaction of the beads whose support box meets the tile's columns
 // [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
 // beads run in the same order as in a full loop.
-__device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, int cw, int ry0,
-                                   int rh, double (*sR)[2], double (*sC)[2], int* s_wave,
-                                   Bonds& B, bool forces_ready) {
+__device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, int cx0, int cw,
+                                   int ry0, int rh, double (*sR)[2], double (*sC)[2],
+                                   int* s_wave, Bonds& B, bool forces_ready) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthreads = blockDim.x * blockDim.y;
     const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
@@ -171,9 +182,10 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, in
             Rx = bs->R[b][0];
             Ry = bs->R[b][1];
             int i0, w, j0, j1;
-            bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
-            hit = (j0 <= j1) && (j0 <= ry0 + rh - 1) && (j1 >= ry0) &&
-                  cols_overlap(cx0, cw, i0, w, nx);
+            bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
+            const bool rows_hit = per ? (j0 <= j1 && cols_overlap(ry0, rh, j0, j1 - j0 + 1, ny))
+                                      : ((j0 <= j1) && (j0 <= ry0 + rh - 1) && (j1 >= ry0));
+            hit = rows_hit && cols_overlap(cx0, cw, i0, w, nx);
         }
         const unsigned long long m = __ballot(hit);
         const int before = __popcll(m & ((1ull << lane) - 1ull));
@@ -193,12 +205,13 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, int cx0, in
             } else {
                 // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
                 double F[2];
-                bead_force(B, fib.n, b, fib.ks_l02, fib.l0, fib.kb, F);
+                bead_force(B, fib.n, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
                 const double A = bs->A[b];
                 const double C0 = F[0] / A, C1 = F[1] / A;
                 sC[off + before][0] = C0;
                 sC[off + before][1] = C1;
-                const int ox = imod((int)floor(Rx), nx), oy = (int)floor(Ry);
+                const int ox = imod((int)floor(Rx), nx);
+                const int oy = per ? imod((int)floor(Ry), ny) : (int)floor(Ry);
                 if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
                     own_bead(fib, B, fib.n, b, F, C0, C1);
             }
@@ -225,27 +238,31 @@ struct TileLds {
 // The fiber's support window for this step (empty without a fiber).
 __device__ inline Window tile_window(const StepArgs& a) {
     if (a.fib.n <= 0) return Window{0, 0, 0, 0, false};
-    return decode_window(a.fib.bs->win[a.parity], a.L.nx, a.L.ny, a.fib.rect_wmax,
+    return decode_window(a.fib.bs->win[a.parity], a.L.nx, a.L.ny, a.L.periodic != 0,
+                         a.fib.rect_wmax,
                          a.fib.rect_hmax);
 }
 
 // Step (1) at one node (x, y) of a fiber tile: phi_i^n (Eq. 2), eta^n (Eq. 1) and the
-// relaxation rates, f^n (Eq. 4), recorded in the force window.
+// relaxation rates, f^n (Eq. 4, plus the uniform body force), recorded in the force
+// window.  Fx, Fy are overwritten; s_nu, s_q keep the fluid values where sum phi = 0.
 template <typename T>
-__device__ inline void fiber_node(const StepArgs& a, const double (*sR)[2],
+__device__ inline void fiber_node(const StepArgs& a, bool per, const double (*sR)[2],
                                   const double (*sC)[2], int nb, int x, int y, int wx0,
                                   int wy0, int ww, int wh, T& Fx, T& Fy, T& s_nu, T& s_q) {
-    const int nx = a.L.nx;
+    const int nx = a.L.nx, ny = a.L.ny;
     const double xc = (double)x + 0.5, yc = (double)y + 0.5;
-    T sphi = T(0);
+    T sphi = T(0), fx = T(0), fy = T(0);
     for (int i = 0; i < nb; ++i) {
         const double dx = min_image(xc - sR[i][0], nx);
-        const double dy = yc - sR[i][1];
+        const double dy = y_image(yc - sR[i][1], ny, per);
         const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi, a.fib.inv_xi);
         sphi += ph;
-        Fx += ph * (T)sC[i][0];
-        Fy += ph * (T)sC[i][1];
+        fx += ph * (T)sC[i][0];
+        fy += ph * (T)sC[i][1];
     }
+    Fx = fx + (T)a.gx;
+    Fy = fy + (T)a.gy;
     if (a.fib.clamp && sphi > T(1)) sphi = T(1);
     if (sphi > T(0)) {  // else the fluid rates, exactly as on the other tiles
         const T nu_f = (T)a.fib.nu_f;
@@ -253,7 +270,7 @@ __device__ inline void fiber_node(const StepArgs& a, const double (*sR)[2],
         s_nu = T(1) / (T(3) * eta + T(0.5));
         s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
     }
-    const int wi = imod(x - wx0, nx), wj = y - wy0;
+    const int wi = imod(x - wx0, nx), wj = per ? imod(y - wy0, ny) : y - wy0;
     if (wi < ww && wj >= 0 && wj < wh) {
         T* rf = (T*)a.fib.rect_f + 2 * ((long long)wj * a.fib.rect_wmax + wi);
         rf[0] = Fx;
@@ -261,10 +278,19 @@ __device__ inline void fiber_node(const StepArgs& a, const double (*sR)[2],
     }
 }
 
-template <int ST, int SPT>
+// Boundary in y as a compile-time choice: kWalls and kPeriodic fix it (the code for the
+// other one drops out), kAnyBoundary reads it from the arguments (batches that mix both).
+constexpr int kWalls = 0, kPeriodic = 1, kAnyBoundary = 2;
+
+__device__ inline bool periodic_of(int bc, const StepArgs& a) {
+    return bc == kAnyBoundary ? a.L.periodic != 0 : bc == kPeriodic;
+}
+
+template <int ST, int SPT, int BC>
 __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int tile,
                                     TileLds& lds) {
     using Cd = Codec<ST>;
+    const bool per = periodic_of(BC, a);
     using T = typename Cd::T;
     using S = typename Cd::store_t;
     double (*sR)[2] = lds.R;
@@ -302,24 +328,31 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
             nxt[3] = -0x7fffffff;
             if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
         }
-        fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
-                     ytile + a.rows_per_block - 1 >= wy0 &&
-                     cols_overlap(xtile, tw, wx0, ww, nx);
+        const bool rows_hit =
+            per ? cols_overlap(ytile, a.rows_per_block, wy0, wh, ny)
+                         : (ytile <= wy0 + wh - 1 && ytile + a.rows_per_block - 1 >= wy0);
+        fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx);
         if (fiber_tile)
-            nb = gather_beads(a.fib, nx, ny, xtile, tw, ytile, a.rows_per_block, sR, sC,
-                              s_wave, lds.bonds, a.forces_ready != 0);
+            nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
+                              a.rows_per_block, sR, sC, s_wave, lds.bonds,
+                              a.forces_ready != 0);
     }
 
+    const bool plain = !fiber_tile && a.gx == 0.0 && a.gy == 0.0;  // block-uniform
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
         const int y = ybase + r;
         if (x >= nx || y >= ny) continue;
-        T g[9];
-        pull<Cd>(src, nx, ny, stride, plane, x, y, u6, g);
-        T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
+        // the fiber terms first: the populations are not live during the bead loop
+        T Fx = (T)a.gx, Fy = (T)a.gy, s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
         if (fiber_tile)
-            fiber_node<T>(a, sR, sC, nb, x, y, wx0, wy0, ww, wh, Fx, Fy, s_nu, s_q);
-        mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
+            fiber_node<T>(a, per, sR, sC, nb, x, y, wx0, wy0, ww, wh, Fx, Fy, s_nu, s_q);
+        T g[9];
+        pull<Cd>(src, nx, ny, stride, plane, x, y, per, u6, g);
+        if (plain)  // no force anywhere on this tile: the unforced collision
+            mrt_collide<T>(g, T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+        else
+            mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
         S* o = dst + (long long)y * stride + x;
 #pragma unroll
         for (int k = 0; k < 9; ++k) Cd::store(o + k * plane, g[k]);
@@ -328,10 +361,11 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
 
 // lattice_tile for 2-byte storage: a tile is G * block_x nodes wide and each lane updates
 // G neighbouring nodes with the same per-node arithmetic as the one-node path.
-template <int ST, int SPT>
+template <int ST, int SPT, int BC>
 __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, int tile,
                                           TileLds& lds) {
     using Cd = Codec<ST>;
+    const bool per = periodic_of(BC, a);
     using T = typename Cd::T;
     constexpr int G = nodes_per_lane(ST);
     static_assert(sizeof(typename Cd::store_t) == 2 && (G == 2 || G == 4),
@@ -367,29 +401,44 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
             nxt[3] = -0x7fffffff;
             if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
         }
-        fiber_tile = ww > 0 && wh > 0 && ytile <= wy0 + wh - 1 &&
-                     ytile + a.rows_per_block - 1 >= wy0 &&
-                     cols_overlap(xtile, tw, wx0, ww, nx);
+        const bool rows_hit =
+            per ? cols_overlap(ytile, a.rows_per_block, wy0, wh, ny)
+                         : (ytile <= wy0 + wh - 1 && ytile + a.rows_per_block - 1 >= wy0);
+        fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx);
         if (fiber_tile)
-            nb = gather_beads(a.fib, nx, ny, xtile, tw, ytile, a.rows_per_block, lds.R, lds.C,
-                              lds.wave, lds.bonds, a.forces_ready != 0);
+            nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
+                              a.rows_per_block, lds.R, lds.C, lds.wave, lds.bonds,
+                              a.forces_ready != 0);
     }
 
+    const bool plain = !fiber_tile && a.gx == 0.0 && a.gy == 0.0;  // block-uniform
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
         const int y = ybase + r;
         if (y >= ny) continue;  // uniform over a wave (its lanes share one row)
+        // the fiber terms first: the populations are not live during the bead loops
+        T Fx[G], Fy[G], s_nu[G], s_q[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            Fx[i] = (T)a.gx;
+            Fy[i] = (T)a.gy;
+            s_nu[i] = (T)a.s_nu_f;
+            s_q[i] = (T)a.s_q_f;
+            if (fiber_tile && x0 + i < nx)
+                fiber_node<T>(a, per, lds.R, lds.C, nb, x0 + i, y, wx0, wy0, ww, wh, Fx[i], Fy[i],
+                              s_nu[i], s_q[i]);
+        }
         T g[G][9];
-        pull_group<Cd, G>(src, nx, ny, stride, plane, x0, y, first, last, u6, g);
+        pull_group<Cd, G>(src, nx, ny, stride, plane, x0, y, per, first, last, u6,
+                          g);
         if (x0 >= nx) continue;
         uint32_t bits[9][G / 2];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-            T Fx = T(0), Fy = T(0), s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
-            if (fiber_tile && x0 + i < nx)
-                fiber_node<T>(a, lds.R, lds.C, nb, x0 + i, y, wx0, wy0, ww, wh, Fx, Fy, s_nu,
-                              s_q);
-            mrt_collide<T>(g[i], Fx, Fy, s_nu, s_q, s_e, s_eps);
+            if (plain)  // no force anywhere on this tile: the unforced collision
+                mrt_collide<T>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+            else
+                mrt_collide<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const uint32_t b = Cd::to_bits(g[i][k]);
@@ -421,19 +470,19 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
     }
 }
 
-template <int ST, int SPT>
+template <int ST, int SPT, int BC>
 __device__ inline void tile_any(const StepArgs& a, const Window& win, int tile, TileLds& lds) {
     if constexpr (nodes_per_lane(ST) > 1)
-        lattice_tile_group<ST, SPT>(a, win, tile, lds);
+        lattice_tile_group<ST, SPT, BC>(a, win, tile, lds);
     else
-        lattice_tile<ST, SPT>(a, win, tile, lds);
+        lattice_tile<ST, SPT, BC>(a, win, tile, lds);
 }
 
-template <int ST, int SPT>
+template <int ST, int SPT, int BC>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ TileLds lds;
     const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    tile_any<ST, SPT>(a, tile_window(a), tile, lds);
+    tile_any<ST, SPT, BC>(a, tile_window(a), tile, lds);
 }
 
 // The argument table is read-only while a batch kernel runs: viewing it in the constant
@@ -457,7 +506,7 @@ __device__ inline int item_sim(const int* table, int item) {
 // Lattice kernel over a batch of simulations of different sizes: one block per (simulation,
 // tile) item of the work table, the grid sized to the table, so the blocks resident at any
 // moment work on neighbouring tiles of one simulation as in a single-simulation launch.
-template <int ST, int SPT>
+template <int ST, int SPT, int BC>
 __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     __shared__ TileLds lds;
     const int item = blockIdx.x;
@@ -465,7 +514,7 @@ __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     const int s = item_sim(b.tile_sim, item);
     const int s_off = ((const ConstInt*)b.tile_off)[s];
     const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    tile_any<ST, SPT>(a, tile_window(a), item - s_off, lds);
+    tile_any<ST, SPT, BC>(a, tile_window(a), item - s_off, lds);
 }
 
 // ----------------------------------------------------------------- bead kernel -----
@@ -490,48 +539,82 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     BeadState* bs = fib.bs;
     const int tid = threadIdx.x;
     const int nx = a.L.nx, ny = a.L.ny;
+    const bool per = a.L.periodic != 0;
     double Rx = bs->R[b][0], Ry = bs->R[b][1];
 
     if (do_velocity) {
         int i0, w, j0, j1;
-        bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+        bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
         const int rows = j1 - j0 + 1;
         const int total = (rows > 0 && w > 0) ? rows * w : 0;
-        const Window win = decode_window(bs->win[a.parity], nx, ny, fib.rect_wmax,
+        const Window win = decode_window(bs->win[a.parity], nx, ny, per, fib.rect_wmax,
                                          fib.rect_hmax);
         const int wx0 = win.x0, wy0 = win.y0, ww = win.w, wh = win.h;
         const T* rf = (const T*)fib.rect_f;
         const S* cur = (const S*)a.dst;
         double sx = 0.0, sy = 0.0;
-        for (int t = tid; t < total; t += blockDim.x) {
-            const int jj = j0 + t / w;
-            int ii = i0 + t % w;
-            if (ii >= nx) ii -= nx;
-            const double dx = min_image((double)ii + 0.5 - Rx, nx);
-            const double dy = (double)jj + 0.5 - Ry;
-            const double ph = bead_phi<T>(fib, dx, dy);
-            if (ph == 0.0) continue;
-            T g[9];
-            pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii, jj, (T)a.u6, g);
-            double drho = 0.0;
+        // kVelBatch nodes per thread and pass: their loads are issued together, so a pass
+        // waits for memory once; the sums still run over t = tid, tid + blockDim.x, ...
+        constexpr int kVelBatch = 4;
+        const int nt = (int)blockDim.x;
+        for (int t0 = tid; t0 < total; t0 += kVelBatch * nt) {
+            double ph[kVelBatch];
+            int ii[kVelBatch], jj[kVelBatch];
+            T g[kVelBatch][9];
+            T fw[kVelBatch][2];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) drho += (double)g[k];
-            const double jx = ((double)g[1] - (double)g[3]) + ((double)g[5] - (double)g[6]) -
-                              ((double)g[7] - (double)g[8]);
-            const double jy = ((double)g[2] - (double)g[4]) + ((double)g[5] + (double)g[6]) -
-                              ((double)g[7] + (double)g[8]);
-            // f^n at this node from the window the lattice kernel filled (the window covers
-            // every support box unless it was clamped, which raises FPD_HEALTH_SUPPORT)
-            const int wi = imod(ii - wx0, nx), wj = jj - wy0;
-            double fxn = 0.0, fyn = 0.0;
-            if (wi < ww && wj >= 0 && wj < wh) {
-                const T* fp = rf + 2 * ((long long)wj * fib.rect_wmax + wi);
-                fxn = (double)fp[0];
-                fyn = (double)fp[1];
+            for (int u = 0; u < kVelBatch; ++u) {
+                const int t = t0 + u * nt;
+                ph[u] = 0.0;
+                ii[u] = i0;
+                jj[u] = j0;
+                if (t < total) {
+                    int yy = j0 + t / w;
+                    if (yy >= ny) yy -= ny;  // periodic box: rows wrap
+                    jj[u] = yy;
+                    int x = i0 + t % w;
+                    if (x >= nx) x -= nx;
+                    ii[u] = x;
+                    const double dx = min_image((double)x + 0.5 - Rx, nx);
+                    const double dy = y_image((double)yy + 0.5 - Ry, ny, per);
+                    ph[u] = bead_phi<T>(fib, dx, dy);
+                }
             }
-            const double rho = 1.0 + drho;
-            sx += ph * ((jx + 0.5 * fxn) / rho);
-            sy += ph * ((jy + 0.5 * fyn) / rho);
+#pragma unroll
+            for (int u = 0; u < kVelBatch; ++u) {
+                fw[u][0] = (T)a.gx;  // outside the window f^n is the body force alone
+                fw[u][1] = (T)a.gy;
+                if (ph[u] != 0.0) {
+                    pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii[u], jj[u], per, (T)a.u6,
+                             g[u]);
+                    // f^n at this node from the window the lattice kernel filled (the window
+                    // covers every support box unless it was clamped, which raises
+                    // FPD_HEALTH_SUPPORT)
+                    const int wi = imod(ii[u] - wx0, nx);
+                    const int wj = per ? imod(jj[u] - wy0, ny) : jj[u] - wy0;
+                    if (wi < ww && wj >= 0 && wj < wh) {
+                        const T* fp = rf + 2 * ((long long)wj * fib.rect_wmax + wi);
+                        fw[u][0] = fp[0];
+                        fw[u][1] = fp[1];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kVelBatch; ++u) {
+                if (ph[u] == 0.0) continue;
+                double drho = 0.0;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) drho += (double)g[u][k];
+                const double jx = ((double)g[u][1] - (double)g[u][3]) +
+                                  ((double)g[u][5] - (double)g[u][6]) -
+                                  ((double)g[u][7] - (double)g[u][8]);
+                const double jy = ((double)g[u][2] - (double)g[u][4]) +
+                                  ((double)g[u][5] + (double)g[u][6]) -
+                                  ((double)g[u][7] + (double)g[u][8]);
+                const double rho = 1.0 + drho;
+                sx += ph[u] * ((jx + 0.5 * (double)fw[u][0]) / rho);
+                sy += ph[u] * ((jy + 0.5 * (double)fw[u][1]) / rho);
+            }
         }
         sx = block_sum(sx, scratch);
         sy = block_sum(sy, scratch);
@@ -551,16 +634,17 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     }
 
     int i0, w, j0, j1;
-    bead_box(Rx, Ry, fib.rc, nx, ny, i0, w, j0, j1);
+    bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
     const int rows = j1 - j0 + 1;
     const int total = (rows > 0 && w > 0) ? rows * w : 0;
     double s = 0.0;
     for (int t = tid; t < total; t += blockDim.x) {
-        const int jj = j0 + t / w;
+        int jj = j0 + t / w;
+        if (jj >= ny) jj -= ny;
         int ii = i0 + t % w;
         if (ii >= nx) ii -= nx;
         const double dx = min_image((double)ii + 0.5 - Rx, nx);
-        const double dy = (double)jj + 0.5 - Ry;
+        const double dy = y_image((double)jj + 0.5 - Ry, ny, per);
         s += bead_phi<T>(fib, dx, dy);
     }
     s = block_sum(s, scratch);
@@ -579,7 +663,8 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
         if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) || !isfinite(s))
             h |= FPD_HEALTH_NAN;
         if (Vx * Vx + Vy * Vy > 0.09 / 3.0) h |= FPD_HEALTH_MACH;
-        if (Ry - fib.a - fib.xi < 0.0 || Ry + fib.a + fib.xi > (double)ny) h |= FPD_HEALTH_WALL;
+        if (!per && (Ry - fib.a - fib.xi < 0.0 || Ry + fib.a + fib.xi > (double)ny))
+            h |= FPD_HEALTH_WALL;
         if (h) atomicOr(&bs->health, h);
     }
 }
@@ -614,7 +699,7 @@ __global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
     fill_bonds(bs, fib.n, B);
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
-        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, F);
+        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
         bs->F[t][0] = F[0];
         bs->F[t][1] = F[1];
         bs->C[t][0] = F[0] / bs->A[t];
@@ -644,7 +729,8 @@ __global__ void unstream_kernel(Lattice L, double u_wall, const double* __restri
     if (x >= L.nx || y >= L.ny) return;
     const long long S = (long long)L.nx * L.ny;
     for (int k = 0; k < 9; ++k) {
-        const int yd = y + ey_of(k);
+        int yd = y + ey_of(k);
+        if (L.periodic) yd = imod(yd, L.ny);
         double v;
         if (yd >= 0 && yd < L.ny) {
             const int xd = imod(x + ex_of(k), L.nx);
@@ -674,23 +760,24 @@ __global__ void stream_out_kernel(Lattice L, double u_wall, const typename Codec
         return Cd::to_f64(src[k * P + (long long)yy * L.stride + xx]);
     };
     const double u6 = u_wall / 6.0;
+    const int ym = y > 0 ? y - 1 : L.ny - 1, yp = y < L.ny - 1 ? y + 1 : 0;
     double g[9];
     g[0] = at(0, x, y);
     g[1] = at(1, xm, y);
     g[3] = at(3, xp, y);
-    if (y > 0) {
-        g[2] = at(2, x, y - 1);
-        g[5] = at(5, xm, y - 1);
-        g[6] = at(6, xp, y - 1);
+    if (y > 0 || L.periodic) {
+        g[2] = at(2, x, ym);
+        g[5] = at(5, xm, ym);
+        g[6] = at(6, xp, ym);
     } else {
         g[2] = at(4, x, y);
         g[5] = at(7, x, y) - u6;
         g[6] = at(8, x, y) + u6;
     }
-    if (y < L.ny - 1) {
-        g[4] = at(4, x, y + 1);
-        g[7] = at(7, xp, y + 1);
-        g[8] = at(8, xm, y + 1);
+    if (y < L.ny - 1 || L.periodic) {
+        g[4] = at(4, x, yp);
+        g[7] = at(7, xp, yp);
+        g[8] = at(8, xm, yp);
     } else {
         g[4] = at(2, x, y);
         g[7] = at(5, x, y) - u6;
@@ -715,18 +802,17 @@ __global__ void init_eq_kernel(Lattice L, double u_wall, int init_flow, double* 
     }
 }
 
-// rho, u = (j + f^n/2)/rho and eta^n at every node from the current state.
+// rho, u = (j + f^n/2)/rho and eta^n at node (x, y) from the current state (F/A of every
+// bead in bs->C, computed by forces_kernel beforehand).
 template <int ST>
-__global__ void fields_kernel(StepArgs a, double* rho_o, double* ux_o, double* uy_o,
-                              double* eta_o) {
+__device__ inline void node_fields(const StepArgs& a, int x, int y, double& rho, double& ux,
+                                   double& uy, double& eta) {
     using Cd = Codec<ST>;
     using T = typename Cd::T;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
     const int nx = a.L.nx, ny = a.L.ny;
-    if (x >= nx || y >= ny) return;
+    const bool per = a.L.periodic != 0;
     T g[9];
-    pull<Cd>((const typename Cd::store_t*)a.src, nx, ny, a.L.stride, a.L.plane, x, y,
+    pull<Cd>((const typename Cd::store_t*)a.src, nx, ny, a.L.stride, a.L.plane, x, y, per,
              (T)a.u6, g);
     double drho = 0.0;
     for (int k = 0; k < 9; ++k) drho += (double)g[k];
@@ -738,7 +824,7 @@ __global__ void fields_kernel(StepArgs a, double* rho_o, double* ux_o, double* u
     const Fiber& fib = a.fib;
     for (int b = 0; b < fib.n; ++b) {
         const double dx = min_image((double)x + 0.5 - fib.bs->R[b][0], nx);
-        const double dy = (double)y + 0.5 - fib.bs->R[b][1];
+        const double dy = y_image((double)y + 0.5 - fib.bs->R[b][1], ny, per);
         const double r2 = dx * dx + dy * dy;
         if (r2 >= fib.rc2) continue;
         const double ph = phi_f64(sqrt(r2), fib.a, fib.xi);
@@ -746,13 +832,150 @@ __global__ void fields_kernel(StepArgs a, double* rho_o, double* ux_o, double* u
         fx += ph * fib.bs->C[b][0];
         fy += ph * fib.bs->C[b][1];
     }
+    fx += a.gx;
+    fy += a.gy;
     if (fib.clamp && sphi > 1.0) sphi = 1.0;
-    const double rho = 1.0 + drho;
+    rho = 1.0 + drho;
+    ux = (jx + 0.5 * fx) / rho;
+    uy = (jy + 0.5 * fy) / rho;
+    eta = fib.nu_f + (fib.nu_s - fib.nu_f) * sphi;
+}
+
+template <int ST>
+__global__ void fields_kernel(StepArgs a, double* rho_o, double* ux_o, double* uy_o,
+                              double* eta_o) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int nx = a.L.nx, ny = a.L.ny;
+    if (x >= nx || y >= ny) return;
+    double rho, ux, uy, eta;
+    node_fields<ST>(a, x, y, rho, ux, uy, eta);
     const long long s = (long long)y * nx + x;
     if (rho_o) rho_o[s] = rho;
-    if (ux_o) ux_o[s] = (jx + 0.5 * fx) / rho;
-    if (uy_o) uy_o[s] = (jy + 0.5 * fy) / rho;
-    if (eta_o) eta_o[s] = fib.nu_f + (fib.nu_s - fib.nu_f) * sphi;
+    if (ux_o) ux_o[s] = ux;
+    if (uy_o) uy_o[s] = uy;
+    if (eta_o) eta_o[s] = eta;
+}
+
+// ------------------------------------------ single-particle diagnostics (Sec. III.B) --
+__device__ inline int box_x(const NodeBox& B, int nx, int bx) { return imod(B.cx0 + bx, nx); }
+__device__ inline int box_y(const NodeBox& B, int ny, bool per, int by) {
+    return per ? imod(B.cy0 + by, ny) : B.cy0 + by;
+}
+
+// rho - 1, v, eta of every node of the box into fields[4][ch][cw].
+template <int ST>
+__global__ void box_fields_kernel(StepArgs a, NodeBox B, double* __restrict__ fields) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = B.cw * B.ch;
+    if (idx >= n) return;
+    const int bx = idx % B.cw, by = idx / B.cw;
+    const int x = box_x(B, a.L.nx, bx), y = box_y(B, a.L.ny, a.L.periodic != 0, by);
+    double rho, ux, uy, eta;
+    node_fields<ST>(a, x, y, rho, ux, uy, eta);
+    fields[idx] = rho - 1.0;  // density deviation: the pressure force uses p - p0
+    fields[n + idx] = ux;
+    fields[2 * n + idx] = uy;
+    fields[3 * n + idx] = eta;
+}
+
+// Eq. (15) and the diffuse-interface drag of Eq. (17) for bead b, summed over the box
+// without its one-node border (the border only feeds the gradient stencil; a wrapped
+// direction has no border).  One block; fixed-order sums.  out[8]: A, V0x, V0y, eps_v,
+// viscous force (x, y), pressure force (x, y).
+__device__ inline double phi_at_node(const StepArgs& a, double Rx, double Ry, int x, int y) {
+    const double dx = min_image((double)x + 0.5 - Rx, a.L.nx);
+    const double dy = y_image((double)y + 0.5 - Ry, a.L.ny, a.L.periodic != 0);
+    const double r2 = dx * dx + dy * dy;
+    if (r2 >= a.fib.rc2) return 0.0;
+    return phi_f64(sqrt(r2), a.fib.a, a.fib.xi);
+}
+
+__global__ void __launch_bounds__(kBeadBlock)
+particle_stats_kernel(StepArgs a, int b, NodeBox B, const double* __restrict__ fields,
+                      double* __restrict__ out) {
+    __shared__ double scratch[kBeadBlock / 64];
+    const int tid = threadIdx.x;
+    const int nx = a.L.nx, ny = a.L.ny;
+    const bool per = a.L.periodic != 0;
+    const double Rx = a.fib.bs->R[b][0], Ry = a.fib.bs->R[b][1];
+    const int n = B.cw * B.ch;
+    const double* drho = fields;
+    const double* vx = fields + n;
+    const double* vy = fields + 2 * n;
+    const double* eta = fields + 3 * n;
+    const int bx0 = B.wrap_x ? 0 : 1, bw = B.wrap_x ? B.cw : B.cw - 2;
+    const int by0 = B.wrap_y ? 0 : 1, bh = B.wrap_y ? B.ch : B.ch - 2;
+    const int total = bw * bh;
+    auto nbr = [&](int bx, int by, int ex, int ey) -> int {
+        const int xx = B.wrap_x ? imod(bx + ex, B.cw) : bx + ex;
+        const int yy = B.wrap_y ? imod(by + ey, B.ch) : by + ey;
+        return yy * B.cw + xx;
+    };
+    // pass 1: A and the phi-weighted velocity
+    double A = 0.0, mx = 0.0, my = 0.0;
+    for (int t = tid; t < total; t += blockDim.x) {
+        const int bx = bx0 + t % bw, by = by0 + t / bw;
+        const double ph = phi_at_node(a, Rx, Ry, box_x(B, nx, bx), box_y(B, ny, per, by));
+        const int i = by * B.cw + bx;
+        A += ph;
+        mx += ph * vx[i];
+        my += ph * vy[i];
+    }
+    A = block_sum(A, scratch);
+    mx = block_sum(mx, scratch);
+    my = block_sum(my, scratch);
+    const double V0x = mx / A, V0y = my / A;
+    // pass 2: residual flow and forces; gradients by the isotropic D2Q9 stencil
+    const int EXs[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int EYs[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    double e = 0.0, fvx = 0.0, fvy = 0.0, fpx = 0.0, fpy = 0.0;
+    for (int t = tid; t < total; t += blockDim.x) {
+        const int bx = bx0 + t % bw, by = by0 + t / bw;
+        const int x = box_x(B, nx, bx), y = box_y(B, ny, per, by);
+        const int i = by * B.cw + bx;
+        const double ph = phi_at_node(a, Rx, Ry, x, y);
+        const double dvx = vx[i] - V0x, dvy = vy[i] - V0y;
+        e += ph * (dvx * dvx + dvy * dvy);
+        double gpx = 0.0, gpy = 0.0, gxx = 0.0, gyx = 0.0, gxy = 0.0, gyy = 0.0;
+        for (int k = 1; k < 9; ++k) {
+            const double wk = k < 5 ? 1.0 / 9.0 : 1.0 / 36.0;
+            const int ex = EXs[k], ey = EYs[k];
+            const double pn = phi_at_node(a, Rx, Ry, imod(x + ex, nx),
+                                          per ? imod(y + ey, ny) : y + ey);
+            const int j = nbr(bx, by, ex, ey);
+            gpx += wk * ex * pn;
+            gpy += wk * ey * pn;
+            gxx += wk * ex * vx[j];   // d_x v_x
+            gyx += wk * ey * vx[j];   // d_y v_x
+            gxy += wk * ex * vy[j];   // d_x v_y
+            gyy += wk * ey * vy[j];   // d_y v_y
+        }
+        gpx *= 3.0; gpy *= 3.0; gxx *= 3.0; gyx *= 3.0; gxy *= 3.0; gyy *= 3.0;
+        if (gpx == 0.0 && gpy == 0.0) continue;
+        const double sxx = eta[i] * 2.0 * gxx;
+        const double syy = eta[i] * 2.0 * gyy;
+        const double sxy = eta[i] * (gyx + gxy);
+        fvx -= sxx * gpx + sxy * gpy;
+        fvy -= sxy * gpx + syy * gpy;
+        fpx += drho[i] / 3.0 * gpx;  // (p - p0) grad phi: p0 adds nothing to the sum
+        fpy += drho[i] / 3.0 * gpy;
+    }
+    e = block_sum(e, scratch);
+    fvx = block_sum(fvx, scratch);
+    fvy = block_sum(fvy, scratch);
+    fpx = block_sum(fpx, scratch);
+    fpy = block_sum(fpy, scratch);
+    if (tid == 0) {
+        out[0] = A;
+        out[1] = V0x;
+        out[2] = V0y;
+        out[3] = e / A;
+        out[4] = fvx;
+        out[5] = fvy;
+        out[6] = fpx;
+        out[7] = fpy;
+    }
 }
 
 __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
@@ -766,11 +989,20 @@ __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__
 template <int ST>
 static hipError_t launch_step_t(const StepArgs& a, dim3 block, int spt, hipStream_t st) {
     const dim3 grid(a.n_tiles);
-    switch (spt) {
-        case 1: hipLaunchKernelGGL((step_kernel<ST, 1>), grid, block, 0, st, a); break;
-        case 2: hipLaunchKernelGGL((step_kernel<ST, 2>), grid, block, 0, st, a); break;
-        case 4: hipLaunchKernelGGL((step_kernel<ST, 4>), grid, block, 0, st, a); break;
-        default: return hipErrorInvalidValue;
+    if (a.L.periodic) {
+        switch (spt) {
+            case 1: hipLaunchKernelGGL((step_kernel<ST, 1, kPeriodic>), grid, block, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((step_kernel<ST, 2, kPeriodic>), grid, block, 0, st, a); break;
+            case 4: hipLaunchKernelGGL((step_kernel<ST, 4, kPeriodic>), grid, block, 0, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (spt) {
+            case 1: hipLaunchKernelGGL((step_kernel<ST, 1, kWalls>), grid, block, 0, st, a); break;
+            case 2: hipLaunchKernelGGL((step_kernel<ST, 2, kWalls>), grid, block, 0, st, a); break;
+            case 4: hipLaunchKernelGGL((step_kernel<ST, 4, kWalls>), grid, block, 0, st, a); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
@@ -812,27 +1044,34 @@ __global__ void __launch_bounds__(kBeadThreads) batch_forces_kernel(BatchArgs b)
     fill_bonds(bs, fib.n, B);
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
-        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, F);
+        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
         own_bead(fib, B, fib.n, t, F, F[0] / bs->A[t], F[1] / bs->A[t]);
     }
 }
 
+template <int ST, int BC>
+static hipError_t launch_batch_lattice(const BatchArgs& b, dim3 grid, dim3 block, int spt,
+                                       hipStream_t st) {
+    switch (spt) {
+        case 1: hipLaunchKernelGGL((batch_step_kernel<ST, 1, BC>), grid, block, 0, st, b); break;
+        case 2: hipLaunchKernelGGL((batch_step_kernel<ST, 2, BC>), grid, block, 0, st, b); break;
+        case 4: hipLaunchKernelGGL((batch_step_kernel<ST, 4, BC>), grid, block, 0, st, b); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int ST>
 static hipError_t launch_batch_t(const BatchArgs& b, dim3 block, int spt, const int counts[3],
-                                 hipStream_t st) {
+                                 bool any_periodic, hipStream_t st) {
     if (counts[0] <= 0) return hipSuccess;
     hipLaunchKernelGGL(batch_forces_kernel, dim3(counts[0]), dim3(kBeadThreads), 0, st, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (counts[1] > 0) {
         const dim3 grid(counts[1]);
-        switch (spt) {
-            case 1: hipLaunchKernelGGL((batch_step_kernel<ST, 1>), grid, block, 0, st, b); break;
-            case 2: hipLaunchKernelGGL((batch_step_kernel<ST, 2>), grid, block, 0, st, b); break;
-            case 4: hipLaunchKernelGGL((batch_step_kernel<ST, 4>), grid, block, 0, st, b); break;
-            default: return hipErrorInvalidValue;
-        }
-        e = hipGetLastError();
+        e = any_periodic ? launch_batch_lattice<ST, kAnyBoundary>(b, grid, block, spt, st)
+                         : launch_batch_lattice<ST, kWalls>(b, grid, block, spt, st);
         if (e != hipSuccess) return e;
     }
     if (counts[2] > 0)
@@ -841,12 +1080,12 @@ static hipError_t launch_batch_t(const BatchArgs& b, dim3 block, int spt, const 
 }
 
 hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int spt,
-                             const int counts[3], hipStream_t st) {
+                             const int counts[3], bool any_periodic, hipStream_t st) {
     switch (storage) {
-        case FPD_F64: return launch_batch_t<FPD_F64>(b, block, spt, counts, st);
-        case FPD_F32: return launch_batch_t<FPD_F32>(b, block, spt, counts, st);
-        case FPD_F16DEV: return launch_batch_t<FPD_F16DEV>(b, block, spt, counts, st);
-        case FPD_BF16DEV: return launch_batch_t<FPD_BF16DEV>(b, block, spt, counts, st);
+        case FPD_F64: return launch_batch_t<FPD_F64>(b, block, spt, counts, any_periodic, st);
+        case FPD_F32: return launch_batch_t<FPD_F32>(b, block, spt, counts, any_periodic, st);
+        case FPD_F16DEV: return launch_batch_t<FPD_F16DEV>(b, block, spt, counts, any_periodic, st);
+        case FPD_BF16DEV: return launch_batch_t<FPD_BF16DEV>(b, block, spt, counts, any_periodic, st);
     }
     return hipErrorInvalidValue;
 }
@@ -901,6 +1140,24 @@ hipError_t launch_fields(int storage, const StepArgs& a, double* rho, double* ux
         case FPD_BF16DEV: hipLaunchKernelGGL((fields_kernel<FPD_BF16DEV>), grid, block, 0, st, a, rho, ux, uy, eta); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_particle_stats(int storage, const StepArgs& a, int bead, const NodeBox& B,
+                                 double* fields, double* out, hipStream_t st) {
+    const int n = B.cw * B.ch;
+    const dim3 grid((n + 127) / 128), block(128);
+    switch (storage) {
+        case FPD_F64: hipLaunchKernelGGL((box_fields_kernel<FPD_F64>), grid, block, 0, st, a, B, fields); break;
+        case FPD_F32: hipLaunchKernelGGL((box_fields_kernel<FPD_F32>), grid, block, 0, st, a, B, fields); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((box_fields_kernel<FPD_F16DEV>), grid, block, 0, st, a, B, fields); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((box_fields_kernel<FPD_BF16DEV>), grid, block, 0, st, a, B, fields); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(particle_stats_kernel, dim3(1), dim3(kBeadBlock), 0, st, a, bead, B,
+                       (const double*)fields, out);
     return hipGetLastError();
 }
 

@@ -100,6 +100,8 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     a.dst = s->buf[1 - src_idx];
     a.L = s->L;
     a.u6 = s->p.u_wall / 6.0;
+    a.gx = s->p.g_body[0];
+    a.gy = s->p.g_body[1];
     const double tau_f = 3.0 * s->p.nu_f + 0.5;
     a.s_nu_f = 1.0 / tau_f;
     a.s_q_f = s->p.s_q_fixed > 0.0 ? s->p.s_q_fixed
@@ -124,6 +126,8 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.l0 = s->p.l0;
     f.ks_l02 = s->p.k_s / (s->p.l0 * s->p.l0);
     f.kb = s->p.k_b;
+    f.fext[0] = s->p.f_ext[0];
+    f.fext[1] = s->p.f_ext[1];
     const fpd_launch& c = s->launch;
     a.rows_per_block = c.block_y * c.rows_per_thread;
     const int tw = c.block_x * nodes_per_lane(s->p.storage);
@@ -151,6 +155,13 @@ int validate(const fpd_params* p) {
         return fail(FPD_EINVAL, "unknown init_flow %d", p->init_flow);
     if (p->n_beads < 0 || p->n_beads > FPD_MAX_BEADS)
         return fail(FPD_EINVAL, "n_beads must be in [0, %d]", FPD_MAX_BEADS);
+    if (p->boundary != FPD_WALLS && p->boundary != FPD_PERIODIC)
+        return fail(FPD_EINVAL, "unknown boundary %d", p->boundary);
+    if (p->boundary == FPD_PERIODIC && (p->u_wall != 0.0 || p->init_flow != FPD_INIT_REST))
+        return fail(FPD_EINVAL, "a periodic box has no walls: u_wall = 0 and FPD_INIT_REST");
+    if (!isfinite(p->f_ext[0]) || !isfinite(p->f_ext[1]) || !isfinite(p->g_body[0]) ||
+        !isfinite(p->g_body[1]))
+        return fail(FPD_EINVAL, "f_ext and g_body must be finite");
     if (p->n_beads > 0) {
         if (!(p->radius > 0.0) || !(p->xi > 0.0) || !(p->l0 > 0.0))
             return fail(FPD_EINVAL, "radius, xi and l0 must be > 0");
@@ -292,6 +303,7 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     // y * stride + k * plane + x with plane = padded nx and stride = 9 * plane
     s->L.plane = padded_stride(p->nx);
     s->L.stride = 9 * padded_stride(p->nx);
+    s->L.periodic = p->boundary == FPD_PERIODIC ? 1 : 0;
     s->elem = storage_elem(p->storage);
     s->buf_bytes = (size_t)p->ny * (size_t)s->L.stride * s->elem;
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
@@ -441,7 +453,8 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
     for (int i = 0; i < N; ++i) {
         const double x = R[2 * i], y = R[2 * i + 1];
         if (!isfinite(x) || !isfinite(y)) return fail(FPD_EINVAL, "bead %d is not finite", i);
-        if (y - s->p.radius - s->p.xi < 0.0 || y + s->p.radius + s->p.xi > s->p.ny)
+        if (s->p.boundary == FPD_WALLS &&
+            (y - s->p.radius - s->p.xi < 0.0 || y + s->p.radius + s->p.xi > s->p.ny))
             return fail(FPD_EINVAL, "bead %d lies within a + xi of a wall", i);
     }
     for (int i = 0; i + 1 < N; ++i) {
@@ -600,6 +613,67 @@ int fpd_read_fields(fpd_sim* s, double* rho, double* ux, double* uy, double* eta
     return FPD_OK;
 }
 
+int fpd_particle_stats(fpd_sim* s, int32_t bead, double* out) {
+    if (!s || !out) return fail(FPD_EINVAL, "NULL argument");
+    if (!s->fiber || bead < 0 || bead >= s->p.n_beads)
+        return fail(FPD_EINVAL, "no bead %d in this simulation", bead);
+    int rc0 = sync_check(s);
+    if (rc0) return rc0;
+    double R[2];
+    HIP_TRY(hipMemcpy(R, &s->bs->R[bead][0], sizeof R, hipMemcpyDeviceToHost));
+    if (!isfinite(R[0]) || !isfinite(R[1]) || fabs(R[0]) > 1e9 || fabs(R[1]) > 1e9)
+        return fail(FPD_EUNSTABLE, "bead %d is not at a finite position", bead);
+    const int nx = s->p.nx, ny = s->p.ny;
+    auto wrap = [](long long v, int n) { long long r = v % n; return (int)(r < 0 ? r + n : r); };
+    // the support box grown by one node (where grad phi can be non-zero) plus a one-node
+    // border for the stencil
+    const long long xlo = (long long)floor(R[0] - 0.5 - s->rc) - 2;
+    const long long xhi = (long long)ceil(R[0] - 0.5 + s->rc) + 2;
+    const long long ylo = (long long)floor(R[1] - 0.5 - s->rc) - 2;
+    const long long yhi = (long long)ceil(R[1] - 0.5 + s->rc) + 2;
+    NodeBox B;
+    if (xhi - xlo + 1 >= nx) {
+        B.cx0 = 0;
+        B.cw = nx;
+        B.wrap_x = true;
+    } else {
+        B.cx0 = wrap(xlo, nx);
+        B.cw = (int)(xhi - xlo + 1);
+        B.wrap_x = false;
+    }
+    if (s->p.boundary == FPD_PERIODIC) {
+        if (yhi - ylo + 1 >= ny) {
+            B.cy0 = 0;
+            B.ch = ny;
+            B.wrap_y = true;
+        } else {
+            B.cy0 = wrap(ylo, ny);
+            B.ch = (int)(yhi - ylo + 1);
+            B.wrap_y = false;
+        }
+    } else {
+        if (ylo < 0 || yhi > ny - 1)
+            return fail(FPD_EINVAL, "bead %d is too close to a wall for the diagnostics", bead);
+        B.cy0 = (int)ylo;
+        B.ch = (int)(yhi - ylo + 1);
+        B.wrap_y = false;
+    }
+    double* d = nullptr;
+    const size_t n = (size_t)B.cw * (size_t)B.ch;
+    HIP_TRY(hipMalloc(&d, (4 * n + 8) * sizeof(double)));
+    const StepArgs a = make_args(s, s->cur);
+    hipError_t e = launch_forces(a, s->stream);  // C = F / A of the current bead state
+    if (e == hipSuccess)
+        e = launch_particle_stats(s->p.storage, a, bead, B, d, d + 4 * n, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d + 4 * n, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "particle_stats: %s", hipGetErrorString(e));
+    return FPD_OK;
+}
+
 int fpd_read_populations(fpd_sim* s, double* f) {
     if (!s || !f) return fail(FPD_EINVAL, "NULL argument");
     const size_t n = (size_t)9 * s->p.nx * s->p.ny;
@@ -729,7 +803,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 
 // ---------------------------------------------------------------- checkpoint -------
 
-static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '3'};
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '4'};
 
 int fpd_save(fpd_sim* s, const char* path) {
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
@@ -835,6 +909,8 @@ struct fpd_batch {
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     int graph_counts[3] = {0, 0, 0};  // counts the graph's grids were sized for
+    bool any_periodic = false;        // some active simulation has no walls
+    bool graph_periodic = false;      // the kernel variant the graph was captured with
 };
 
 namespace {
@@ -891,9 +967,12 @@ int batch_rebuild(fpd_batch* b) {
     b->h_counts[0] = r;
     b->h_counts[1] = tiles;
     b->h_counts[2] = beads;
+    b->any_periodic = false;
+    for (int q = 0; q < r; ++q)
+        if (b->h_args[2 * q].L.periodic) b->any_periodic = true;
     if (b->graph && (b->graph_counts[0] != r || b->graph_counts[1] != tiles ||
-                     b->graph_counts[2] != beads))
-        batch_drop_graph(b);  // its grids no longer match the work tables
+                     b->graph_counts[2] != beads || b->graph_periodic != b->any_periodic))
+        batch_drop_graph(b);  // its grids or kernel variant no longer match the tables
     // item -> simulation lookup tables (grown geometrically; a new pointer drops the graph)
     auto grow = [&](int need, int& cap, int*& d, int*& h) -> int {
         if (need <= cap) return FPD_OK;
@@ -945,7 +1024,7 @@ int batch_enqueue(fpd_batch* b, int gpar) {
                 b->d_counts, gpar};
     const dim3 block(b->launch.block_x, b->launch.block_y);
     HIP_TRY(launch_batch_step(b->storage, a, block, b->launch.rows_per_thread, b->h_counts,
-                              b->stream));
+                              b->any_periodic, b->stream));
     return FPD_OK;
 }
 
@@ -965,6 +1044,7 @@ int batch_build_graph(fpd_batch* b, int chunk) {
     if (e != hipSuccess) return fail(FPD_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
     b->graph_chunk = chunk;
     for (int k = 0; k < 3; ++k) b->graph_counts[k] = b->h_counts[k];
+    b->graph_periodic = b->any_periodic;
     return FPD_OK;
 }
 

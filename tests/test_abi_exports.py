@@ -46,7 +46,7 @@ def test_params_struct_layout_matches_header():
     text = open(HEADER).read()
     body = text[text.index("typedef struct fpd_params {"):text.index("} fpd_params;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    fields = re.findall(r"\b([a-z_0-9]+)\s*[,;]", body)
+    fields = re.findall(r"\b([a-z_0-9]+)(?:\[\d+\])?\s*[,;]", body)
     assert fields == [n for n, _ in _lib.fpd_params._fields_]
 
 

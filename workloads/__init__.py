@@ -56,10 +56,17 @@ class Workload:
     kappa: float = float("nan")
     re_ps: float = float("nan")
     confinement: float = float("nan")
+    boundary: int = 0                    # 0 moving walls, 1 periodic box (no walls)
+    f_ext: tuple = (0.0, 0.0)            # external force on every bead
+    g_body: tuple = (0.0, 0.0)           # uniform body force density on every node
 
     def params(self) -> dict:
-        """Lattice parameters as a plain mapping (both sides read what they need)."""
-        return {k: v for k, v in asdict(self).items()}
+        """Lattice parameters as a plain mapping (both sides read what they need; the
+        boundary and the two forces are also given under the oracle's names)."""
+        d = {k: v for k, v in asdict(self).items()}
+        d.update(periodic_y=int(self.boundary == 1), fx_ext=self.f_ext[0],
+                 fy_ext=self.f_ext[1], gx_body=self.g_body[0], gy_body=self.g_body[1])
+        return d
 
     def beads(self) -> np.ndarray:
         return straight_fiber(self.n_beads, self.l0, self.theta0, self.cx, self.cy)
@@ -162,6 +169,22 @@ def poisson_arrivals(count: int, rate: float = 50.0, seed: int = 50) -> np.ndarr
     """Arrival times (s) of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def driven_particle(n: int = 48, radius: float = 3.0, xi: float = 1.0, force: float = 1e-4,
+                    eta_ratio: float = 50.0, nu_f: float = 1.0 / 6.0, storage: str = "f64",
+                    steps: int = 4000, offset=(0.3, 0.1)) -> Workload:
+    """The single-particle benchmark of Sec. III.B: one bead (a disk of radius a) in an
+    n x n periodic box (no walls), pushed along x by a constant force F0; the uniform body
+    force -F0 / n^2 on every node keeps the total momentum at zero, so the fluid far from
+    the particle stays at rest on average.  The paper's box is H = 10 d; the bead starts
+    slightly off the node lattice (offset) so that no symmetry is special."""
+    return Workload(
+        name=f"particle_{n}x{n}_a{radius:g}_{storage}", nx=n, ny=n, u_wall=0.0, nu_f=nu_f,
+        eta_ratio=eta_ratio, xi=xi, n_beads=1, radius=radius, l0=2.0 * radius, k_s=0.0,
+        k_b=0.0, theta0=0.0, cx=n / 2 + offset[0], cy=n / 2 + offset[1], steps=steps,
+        storage=storage, init_flow=0, boundary=1, f_ext=(force, 0.0),
+        g_body=(-force / (n * n), 0.0))
 
 
 def perturbation(shape, amplitude: float, seed: int) -> np.ndarray:
