@@ -16,7 +16,10 @@ Other modes (each prints one JSON line):
                  path (the same simulations one at a time, per-step launches, no graph);
   --mode serve   Poisson arrivals (50 requests/s) of sweep simulations served with
                  continuous batching in FP16/BF16 deviation storage: p50/p99 time-to-result
-                 and simulations per second, against a single-simulation FIFO server.
+                 and simulations per second, against a single-simulation FIFO server;
+  --mode particle  the driven-particle benchmark of Sec. III.B (periodic box, H = 10 d,
+                 d = 20) swept over 64 driving forces in one batch (90k steps): C_d(Re_p), eps_v,
+                 the diffuse-interface drag, and throughput.
 """
 from __future__ import annotations
 
@@ -235,6 +238,103 @@ def main_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def main_particle(args):
+    """The driven-particle benchmark of Sec. III.B as a batched sweep over the driving
+    force: a disk of diameter d = 20 lattice units (dx = d / 20) in a periodic box of side
+    H = 10 d, interface xi = d / 8, r_eta = 50, pushed by F0 with the balancing body
+    force; after a fixed number of steps, C_d (Eq. 16, |F_d| = F0 at steady state), Re_p,
+    eps_v (Eq. 15) and the diffuse-interface drag of Eq. (17) for every force."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2212_14153_amd import _lib
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    storage = args.storage
+    d, n, xi, nu = 20.0, 200, 2.5, 1.0 / 6.0
+    forces = np.geomspace(args.f_min, args.f_max, args.particles)
+    ws = [workloads.driven_particle(n=n, radius=d / 2, xi=xi, force=float(F), nu_f=nu,
+                                    eta_ratio=50.0, storage=storage, steps=args.particle_steps)
+          for F in forces]
+    params = sweep_params(_lib, ws, storage)
+    nodes = sum(w.nx * w.ny for w in ws)
+    budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
+    log(f"particle sweep: {len(ws)} boxes of {n}x{n}, F0 {forces[0]:.2e}..{forces[-1]:.2e}, "
+        f"{args.particle_steps} steps, storage {storage}")
+    b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
+    ids = [b.add(p, w.beads(), args.particle_steps) for p, w in zip(params, ws)]
+    half = args.particle_steps * 2 // 3
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    left = half
+    while left > 0:
+        left -= b.run(left)
+    e1.record(stream)
+    e1.synchronize()
+    ms_first = e0.elapsed_time(e1)
+    mid = [b.particle_stats(i) for i in ids]
+    left = args.particle_steps - half
+    e2 = torch.cuda.Event(enable_timing=True)
+    e3 = torch.cuda.Event(enable_timing=True)
+    e2.record(stream)
+    while left > 0:
+        adv = b.run(left)
+        if adv == 0:
+            break
+        left -= adv
+    e3.record(stream)
+    e3.synchronize()
+    ms_total = ms_first + e2.elapsed_time(e3)
+    end = [b.particle_stats(i) for i in ids]
+    health = [b.info(i) for i in ids]
+    b.close()
+    curve = []
+    for F, s0, s1, (steps_done, status, hflags) in zip(forces, mid, end, health):
+        V0 = s1["V0x"]
+        drag = -(s1["Fvisc_x"] + s1["Fpres_x"])
+        curve.append({
+            "F0": float(F), "V0": V0, "Re_p": V0 * d / nu,
+            "C_d": float(F) / (0.5 * V0 * V0 * d),
+            "eps_v_over_V0sq": s1["eps_v"] / (V0 * V0),
+            "drag_eq17_over_F0": drag / float(F),
+            "V0_change_last_third": abs(V0 - s0["V0x"]) / abs(V0),
+            "status": int(status), "health": int(hflags)})
+    steps = args.particle_steps
+    mlups = nodes * steps / (ms_total * 1e-3) / 1e6
+    bytes_alg = 18 * BYTES_PER_VALUE[storage] * nodes
+    achieved = bytes_alg * steps / (ms_total * 1e-3) / 1e9
+    out = {
+        "metric": "driven-particle sweep MLUPS", "value": round(mlups, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(ms_total / steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": storage, "data": "synthetic",
+        "config": {"workload": f"{len(ws)} driven particles, d = 20, H = 10 d, periodic "
+                               f"{n}x{n}, xi = d/8, r_eta = 50", "nodes_total": nodes,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "whole batch step (all three kernels)",
+                     "bytes_per_launch_alg": bytes_alg},
+        "curve": curve,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        w = ws[len(ws) // 2].with_(storage="f64")
+        p = oracle.OracleParams.from_mapping(w.params())
+        st = oracle.make_state(p, 0, w.beads())
+        oracle.run(st, 1)
+        t0 = time.perf_counter()
+        oracle.run(st, args.cpu_steps * 10)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(n * n * args.cpu_steps * 10 / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": 1, "kind": "oracle",
+            "sample": f"one {n}x{n} box, {args.cpu_steps * 10} FP64 steps ({dt:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,7 +345,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "particle"])
+    ap.add_argument("--particles", type=int, default=64)
+    ap.add_argument("--particle-steps", type=int, default=90000)
+    ap.add_argument("--f-min", type=float, default=1e-4)
+    ap.add_argument("--f-max", type=float, default=1e-1)
     ap.add_argument("--sims", type=int, default=256)
     ap.add_argument("--sweep-steps", type=int, default=20000)
     ap.add_argument("--plain-sims", type=int, default=8)
@@ -268,6 +372,8 @@ def main():
         return main_batch(args)
     if args.mode == "serve":
         return main_serve(args)
+    if args.mode == "particle":
+        return main_particle(args)
 
     import torch
     from paper_2212_14153_amd import _lib

@@ -286,6 +286,7 @@ int fpd_batch_read_beads(fpd_batch *b, int64_t sim_id, double *R, double *V, dou
 int fpd_batch_read_populations(fpd_batch *b, int64_t sim_id, double *f);
 int fpd_batch_read_fields(fpd_batch *b, int64_t sim_id, double *rho, double *ux, double *uy,
                           double *eta);
+int fpd_batch_particle_stats(fpd_batch *b, int64_t sim_id, int32_t bead, double *out);
 int fpd_batch_sim_info(fpd_batch *b, int64_t sim_id, int64_t *steps, int32_t *status,
                        uint32_t *health);
 

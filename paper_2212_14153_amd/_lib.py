@@ -106,6 +106,7 @@ SIGNATURES = [
     ("fpd_batch_read_beads", ctypes.c_int, [_SIM, ctypes.c_int64, _D, _D, _D]),
     ("fpd_batch_read_populations", ctypes.c_int, [_SIM, ctypes.c_int64, _D]),
     ("fpd_batch_read_fields", ctypes.c_int, [_SIM, ctypes.c_int64, _D, _D, _D, _D]),
+    ("fpd_batch_particle_stats", ctypes.c_int, [_SIM, ctypes.c_int64, ctypes.c_int32, _D]),
     ("fpd_batch_sim_info", ctypes.c_int,
      [_SIM, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
       ctypes.POINTER(ctypes.c_uint32)]),
@@ -416,6 +417,11 @@ class Batch:
         if n:
             check(lib().fpd_batch_read_beads(self.h, sid, _ptr(R), _ptr(V), _ptr(F)))
         return R, V, F
+
+    def particle_stats(self, sid: int, bead: int = 0) -> dict:
+        out = np.empty(8)
+        check(lib().fpd_batch_particle_stats(self.h, int(sid), int(bead), _ptr(out)))
+        return dict(zip(Simulation.STATS_FIELDS, out.tolist()))
 
     def populations(self, sid: int):
         nx, ny, n = self.shapes[sid]

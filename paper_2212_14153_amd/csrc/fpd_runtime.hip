@@ -1277,6 +1277,12 @@ int fpd_batch_read_fields(fpd_batch* b, int64_t id, double* rho, double* ux, dou
     return fpd_read_fields(e->sim, rho, ux, uy, eta);
 }
 
+int fpd_batch_particle_stats(fpd_batch* b, int64_t id, int32_t bead, double* out) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    return fpd_particle_stats(e->sim, bead, out);
+}
+
 int fpd_batch_sim_info(fpd_batch* b, int64_t id, int64_t* steps, int32_t* status,
                        uint32_t* health) {
     BatchEntry* e = b ? find_entry(b, id) : nullptr;

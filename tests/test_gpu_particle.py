@@ -174,3 +174,17 @@ def test_driven_particle_batch_equals_alone():
         for sid, (f, R) in zip(ids, alone):
             assert np.array_equal(b.populations(sid), f)
             assert np.array_equal(b.beads(sid)[0], R)
+
+
+def test_batch_particle_stats_equal_the_single_simulation():
+    w = workloads.driven_particle(n=64, radius=4.0, storage="f64", force=3e-4)
+    print("[case] batch particle stats", flush=True)
+    with _lib.simulation_from_workload(w, storage="f64") as sim:
+        sim.step(120)
+        alone = sim.particle_stats(0)
+    p = _lib.params_from_mapping(w.params(), storage="f64")
+    with _lib.Batch(4 * _lib.fpd_sim_footprint(p), 2, storage="f64") as b:
+        sid = b.add(p, w.beads(), 120)
+        while b.run(64):
+            pass
+        assert b.particle_stats(sid) == alone
