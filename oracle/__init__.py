@@ -48,6 +48,7 @@ class _Params(ctypes.Structure):
         ("periodic_y", ctypes.c_int),
         ("fx_ext", ctypes.c_double), ("fy_ext", ctypes.c_double),
         ("gx_body", ctypes.c_double), ("gy_body", ctypes.c_double),
+        ("phi_static", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -74,12 +75,18 @@ class OracleParams:
     fy_ext: float = 0.0
     gx_body: float = 0.0      # uniform body force density on every node
     gy_body: float = 0.0
+    phi_static: object = None  # None or [ny]: fixed profile phi_s(y) added in Eq. (1)
 
     def c(self) -> _Params:
+        ps = None
+        if self.phi_static is not None:
+            self._phi_keep = np.ascontiguousarray(self.phi_static, dtype=np.float64)
+            assert self._phi_keep.shape == (self.ny,)
+            ps = self._phi_keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         return _Params(self.nx, self.ny, self.u_wall, self.nu_f, self.eta_ratio, self.xi,
                        self.n_beads, self.radius, self.l0, self.k_s, self.k_b, self.s_e,
                        self.s_eps, self.s_q_fixed, self.clamp_phi, self.periodic_y,
-                       self.fx_ext, self.fy_ext, self.gx_body, self.gy_body)
+                       self.fx_ext, self.fy_ext, self.gx_body, self.gy_body, ps)
 
     @classmethod
     def from_mapping(cls, m) -> "OracleParams":

@@ -49,6 +49,8 @@
  *     The viscous and pressure parts are returned separately.
  *   - Eq. (15): V0 is the phi-weighted mean velocity of the particle, i.e. Eq. (5)
  *     evaluated on the current state.
+ *   - the sandwich benchmark of Sec. III.A: its solid slabs are a fixed profile
+ *     phi_s(y) (Eq. (14)) that enters Eq. (1) next to the beads' sum_i phi_i.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -72,6 +74,8 @@ typedef struct orc_params {
     int    periodic_y;    /* 1: no walls, y periodic too (Sec. III.B benchmark box)      */
     double fx_ext, fy_ext;   /* external force F0 on every bead                          */
     double gx_body, gy_body; /* uniform body force density on every node                 */
+    const double *phi_static; /* NULL or [ny]: a fixed interface profile phi_s(y) added to
+                                 sum_i phi_i in Eq. (1) (the solid slabs of Eq. (14))      */
 } orc_params;
 
 /* ---------------------------------------------------------- D2Q9 lattice ---------- */
@@ -268,6 +272,7 @@ static void stage1_compute(const orc_params *p, const double *R, stage1 *s1)
     }
     for (size_t s = 0; s < S; ++s) {
         double sp = sphi[s];
+        if (p->phi_static) sp += p->phi_static[s / (size_t)nx];
         if (p->clamp_phi && sp > 1.0) sp = 1.0;
         s1->eta[s] = eta_f + (eta_s - eta_f) * sp;         /* Eq. (1) */
         s1->fx[s] += p->gx_body;                           /* uniform body force */

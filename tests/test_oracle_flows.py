@@ -130,3 +130,21 @@ def test_mass_conserved_with_moving_walls(orc):
     m0 = st.f.sum()
     orc.run(st, 300)
     assert abs(st.f.sum() - m0) <= 1e-13 * 300 * m0
+
+
+def test_static_profile_in_the_full_step_is_the_sandwich(orc):
+    """A fixed profile phi_s(y) in the full step (no beads) is the sandwich of Sec. III.A:
+    the same populations as the LBM stage driven with eta(y) directly."""
+    ny, U, tau_f, r_eta, xi = 48, 0.01, 0.8, 50.0, 0.5
+    nu_f = (tau_f - 0.5) / 3
+    y = np.arange(ny) + 0.5
+    phi = sandwich_profile(y, ny, xi)
+    p = orc.OracleParams(nx=2, ny=ny, u_wall=U, nu_f=nu_f, eta_ratio=r_eta, phi_static=phi)
+    st = orc.make_state(p, 1)
+    orc.run(st, 400)
+    eta = nu_f + (r_eta * nu_f - nu_f) * phi
+    snu = np.repeat((1 / (3 * eta + 0.5))[:, None], 2, axis=1)
+    zero = np.zeros((ny, 2))
+    p0 = orc.OracleParams(nx=2, ny=ny, u_wall=U, nu_f=nu_f)
+    f = run_fields(orc, p0, orc.init(p0, 1), snu, zero, zero, 400)
+    assert np.abs(st.f - f).max() < 1e-14
