@@ -198,6 +198,12 @@ int fpd_write_populations(fpd_sim *s, const double *f);
 /* Host [n_beads][2] each, NULL to skip: R^n, V^n (velocity of the last step), F^n. */
 int fpd_read_beads(fpd_sim *s, double *R, double *V, double *F);
 
+/* A fixed interface profile phi_s(y), host [ny] (>= 0), added to sum_i phi_i in Eq. (1)
+ * at every node of row y: the solid slabs of the sandwich benchmark (Sec. III.A,
+ * Eq. 14).  NULL removes it.  The library keeps a device copy; checkpoints do not hold
+ * it (set it again after fpd_load).  Synchronises. */
+int fpd_set_static_phi(fpd_sim *s, const double *phi);
+
 /* Diagnostics of the driven-particle benchmark (Sec. III.B) for bead `bead` on the
  * current state (pre-collision populations at step n, positions R^n, force density f^n
  * of that state), computed on the device with fixed-order FP64 sums; synchronises.
@@ -287,6 +293,8 @@ int fpd_batch_read_populations(fpd_batch *b, int64_t sim_id, double *f);
 int fpd_batch_read_fields(fpd_batch *b, int64_t sim_id, double *rho, double *ux, double *uy,
                           double *eta);
 int fpd_batch_particle_stats(fpd_batch *b, int64_t sim_id, int32_t bead, double *out);
+/* fpd_set_static_phi for a simulation of the batch. */
+int fpd_batch_set_static_phi(fpd_batch *b, int64_t sim_id, const double *phi);
 int fpd_batch_sim_info(fpd_batch *b, int64_t sim_id, int64_t *steps, int32_t *status,
                        uint32_t *health);
 

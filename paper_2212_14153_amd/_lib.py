@@ -84,6 +84,7 @@ SIGNATURES = [
     ("fpd_write_populations", ctypes.c_int, [_SIM, _D]),
     ("fpd_read_beads", ctypes.c_int, [_SIM, _D, _D, _D]),
     ("fpd_particle_stats", ctypes.c_int, [_SIM, ctypes.c_int32, _D]),
+    ("fpd_set_static_phi", ctypes.c_int, [_SIM, _D]),
     ("fpd_set_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_get_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_set_flags", ctypes.c_int, [_SIM, ctypes.c_uint32]),
@@ -107,6 +108,7 @@ SIGNATURES = [
     ("fpd_batch_read_populations", ctypes.c_int, [_SIM, ctypes.c_int64, _D]),
     ("fpd_batch_read_fields", ctypes.c_int, [_SIM, ctypes.c_int64, _D, _D, _D, _D]),
     ("fpd_batch_particle_stats", ctypes.c_int, [_SIM, ctypes.c_int64, ctypes.c_int32, _D]),
+    ("fpd_batch_set_static_phi", ctypes.c_int, [_SIM, ctypes.c_int64, _D]),
     ("fpd_batch_sim_info", ctypes.c_int,
      [_SIM, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
       ctypes.POINTER(ctypes.c_uint32)]),
@@ -283,6 +285,14 @@ class Simulation:
         check(lib().fpd_read_fields(self.h, *[_ptr(o) for o in out]))
         return tuple(out)
 
+    def set_static_phi(self, phi):
+        """Fixed profile phi_s(y) [ny] added to sum_i phi_i in Eq. (1); None removes it."""
+        if phi is None:
+            check(lib().fpd_set_static_phi(self.h, None))
+            return
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.ny)
+        check(lib().fpd_set_static_phi(self.h, _ptr(phi)))
+
     STATS_FIELDS = ("A", "V0x", "V0y", "eps_v", "Fvisc_x", "Fvisc_y", "Fpres_x", "Fpres_y")
 
     def particle_stats(self, bead: int = 0) -> dict:
@@ -417,6 +427,14 @@ class Batch:
         if n:
             check(lib().fpd_batch_read_beads(self.h, sid, _ptr(R), _ptr(V), _ptr(F)))
         return R, V, F
+
+    def set_static_phi(self, sid: int, phi):
+        """Fixed profile phi_s(y) for one simulation of the batch (None removes it)."""
+        if phi is None:
+            check(lib().fpd_batch_set_static_phi(self.h, int(sid), None))
+            return
+        arr = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.shapes[sid][1])
+        check(lib().fpd_batch_set_static_phi(self.h, int(sid), _ptr(arr)))
 
     def particle_stats(self, sid: int, bead: int = 0) -> dict:
         out = np.empty(8)

@@ -72,6 +72,7 @@ struct StepArgs {
     double s_nu_f, s_q_f;     // fluid shear and heat-flux rates away from the fiber
     double s_e, s_eps;
     double gx, gy;            // uniform body force density on every node
+    const double* row_phi;    // NULL or [ny]: fixed profile phi_s(y) added in Eq. (1)
     Fiber fib;
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
     int rows_per_block;       // block_y * rows_per_thread

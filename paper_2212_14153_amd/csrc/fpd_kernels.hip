@@ -243,9 +243,9 @@ __device__ inline Window tile_window(const StepArgs& a) {
                          a.fib.rect_hmax);
 }
 
-// Step (1) at one node (x, y) of a fiber tile: phi_i^n (Eq. 2), eta^n (Eq. 1) and the
-// relaxation rates, f^n (Eq. 4, plus the uniform body force), recorded in the force
-// window.  Fx, Fy are overwritten; s_nu, s_q keep the fluid values where sum phi = 0.
+// Step (1) at one node (x, y) of a fiber tile: phi_i^n (Eq. 2), eta^n (Eq. 1, with a
+// fixed profile phi_s(y) if one is set) and the relaxation rates, f^n (Eq. 4, plus the
+// uniform body force), recorded in the force window.  Fx, Fy are overwritten; s_nu, s_q keep the fluid values where sum phi = 0.
 template <typename T>
 __device__ inline void fiber_node(const StepArgs& a, bool per, const double (*sR)[2],
                                   const double (*sC)[2], int nb, int x, int y, int wx0,
@@ -263,6 +263,7 @@ __device__ inline void fiber_node(const StepArgs& a, bool per, const double (*sR
     }
     Fx = fx + (T)a.gx;
     Fy = fy + (T)a.gy;
+    if (a.row_phi) sphi += (T)a.row_phi[y];  // fixed profile phi_s(y) (sandwich slabs)
     if (a.fib.clamp && sphi > T(1)) sphi = T(1);
     if (sphi > T(0)) {  // else the fluid rates, exactly as on the other tiles
         const T nu_f = (T)a.fib.nu_f;
@@ -338,6 +339,9 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
                               a.forces_ready != 0);
     }
 
+    // a fixed profile phi_s(y) makes every tile take the fiber path (with no beads to
+    // gather outside the window); plain: no force and no viscosity change on this tile
+    if (a.row_phi) fiber_tile = true;
     const bool plain = !fiber_tile && a.gx == 0.0 && a.gy == 0.0;  // block-uniform
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
@@ -411,6 +415,9 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
                               a.forces_ready != 0);
     }
 
+    // a fixed profile phi_s(y) makes every tile take the fiber path (with no beads to
+    // gather outside the window); plain: no force and no viscosity change on this tile
+    if (a.row_phi) fiber_tile = true;
     const bool plain = !fiber_tile && a.gx == 0.0 && a.gy == 0.0;  // block-uniform
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
@@ -834,6 +841,7 @@ __device__ inline void node_fields(const StepArgs& a, int x, int y, double& rho,
     }
     fx += a.gx;
     fy += a.gy;
+    if (a.row_phi) sphi += a.row_phi[y];
     if (fib.clamp && sphi > 1.0) sphi = 1.0;
     rho = 1.0 + drho;
     ux = (jx + 0.5 * fx) / rho;

@@ -78,6 +78,7 @@ struct fpd_sim {
     bool own_stream = false;
     BeadState* bs = nullptr;
     void* rect_f = nullptr;
+    double* row_phi = nullptr;   // fixed profile phi_s(y) [ny], device (fpd_set_static_phi)
     int rect_wmax = 0, rect_hmax = 0;
     double rc = 0.0;
     bool fiber = false;
@@ -102,6 +103,7 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     a.u6 = s->p.u_wall / 6.0;
     a.gx = s->p.g_body[0];
     a.gy = s->p.g_body[1];
+    a.row_phi = s->row_phi;
     const double tau_f = 3.0 * s->p.nu_f + 0.5;
     a.s_nu_f = 1.0 / tau_f;
     a.s_q_f = s->p.s_q_fixed > 0.0 ? s->p.s_q_fixed
@@ -442,6 +444,7 @@ void fpd_destroy(fpd_sim* s) {
             if (b) (void)hipFree(b);
     if (s->bs) (void)hipFree(s->bs);
     if (s->rect_f) (void)hipFree(s->rect_f);
+    if (s->row_phi) (void)hipFree(s->row_phi);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -610,6 +613,30 @@ int fpd_read_fields(fpd_sim* s, double* rho, double* ux, double* uy, double* eta
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(FPD_EDEVICE, "read_fields: %s", hipGetErrorString(e));
+    return FPD_OK;
+}
+
+int fpd_set_static_phi(fpd_sim* s, const double* phi) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    const int ny = s->p.ny;
+    if (phi)
+        for (int j = 0; j < ny; ++j)
+            if (!isfinite(phi[j]) || phi[j] < 0.0)
+                return fail(FPD_EINVAL, "phi_s[%d] must be finite and >= 0", j);
+    int rc = sync_check(s);
+    if (rc) return rc;
+    if (!phi) {
+        if (s->row_phi) (void)hipFree(s->row_phi);
+        s->row_phi = nullptr;
+    } else {
+        if (!s->row_phi && hipMalloc((void**)&s->row_phi, sizeof(double) * ny) != hipSuccess) {
+            (void)hipGetLastError();
+            s->row_phi = nullptr;
+            return fail(FPD_ENOMEM, "static profile allocation failed");
+        }
+        HIP_TRY(hipMemcpy(s->row_phi, phi, sizeof(double) * ny, hipMemcpyHostToDevice));
+    }
+    drop_graphs(s);  // the captured arguments name the profile
     return FPD_OK;
 }
 
@@ -1275,6 +1302,15 @@ int fpd_batch_read_fields(fpd_batch* b, int64_t id, double* rho, double* ux, dou
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     return fpd_read_fields(e->sim, rho, ux, uy, eta);
+}
+
+int fpd_batch_set_static_phi(fpd_batch* b, int64_t id, const double* phi) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int rc = fpd_set_static_phi(e->sim, phi);
+    if (rc == FPD_OK) b->dirty = true;  // the argument table names the profile
+    return rc;
 }
 
 int fpd_batch_particle_stats(fpd_batch* b, int64_t id, int32_t bead, double* out) {

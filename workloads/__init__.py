@@ -187,6 +187,34 @@ def driven_particle(n: int = 48, radius: float = 3.0, xi: float = 1.0, force: fl
         g_body=(-force / (n * n), 0.0))
 
 
+def sandwich_phi_at(y, H: float, xi: float) -> np.ndarray:
+    """Eq. (14) at heights y: the solid | fluid | solid sandwich of Sec. III.A with the
+    interfaces at z_L = H/3 and z_R = 2H/3."""
+    y = np.asarray(y, dtype=np.float64)
+    zl, zr = H / 3.0, 2.0 * H / 3.0
+    return np.where(y <= H / 2.0, 0.5 * (np.tanh((zl - y) / xi) + 1.0),
+                    0.5 * (np.tanh((y - zr) / xi) + 1.0))
+
+
+def sandwich_phi(ny: int, xi: float) -> np.ndarray:
+    """Eq. (14) at the row centres y = j + 1/2 of a channel of height H = ny."""
+    return sandwich_phi_at(np.arange(ny, dtype=np.float64) + 0.5, float(ny), xi)
+
+
+def sandwich(ny: int = 200, nx: int = 200, r_eta: float = 50.0, r_xi: float = 0.01,
+             re: float = 0.1, u_wall: float = 0.005, storage: str = "f64",
+             steps: int = 6000) -> Workload:
+    """The Couette benchmark of Sec. III.A: walls at y = 0 and y = H moving at -U and +U
+    (the paper's 0 and V0 = 2U, shifted by V0/2), Re = V0 H / nu_f, solid slabs of
+    viscosity r_eta eta_f given by sandwich_phi(H, r_xi H); the paper's grid has
+    dx / H = 0.005, i.e. H = 200.  No beads."""
+    nu_f = 2.0 * u_wall * ny / re
+    return Workload(
+        name=f"sandwich_{ny}_r{r_eta:g}_x{r_xi:g}_{storage}", nx=nx, ny=ny, u_wall=u_wall,
+        nu_f=nu_f, eta_ratio=r_eta, xi=r_xi * ny, n_beads=0, radius=1.0, l0=2.0, k_s=0.0,
+        k_b=0.0, theta0=0.0, cx=0.0, cy=0.0, steps=steps, storage=storage, init_flow=1)
+
+
 def perturbation(shape, amplitude: float, seed: int) -> np.ndarray:
     """Seeded uniform noise in [-amplitude, amplitude] (float64)."""
     rng = np.random.default_rng(seed)
