@@ -19,7 +19,10 @@ Other modes (each prints one JSON line):
                  and simulations per second, against a single-simulation FIFO server;
   --mode particle  the driven-particle benchmark of Sec. III.B (periodic box, H = 10 d,
                  d = 20) swept over 64 driving forces in one batch (90k steps): C_d(Re_p), eps_v,
-                 the diffuse-interface drag, and throughput.
+                 the diffuse-interface drag, and throughput;
+  --mode sandwich  the Couette sandwich of Sec. III.A (H = 200, Re = 0.1) over a grid of
+                 viscosity ratios and interface widths: steady-profile errors against
+                 Eq. (13) and the exact smooth solution.
 """
 from __future__ import annotations
 
@@ -335,6 +338,75 @@ def main_particle(args):
     print(json.dumps(out), flush=True)
 
 
+def main_sandwich(args):
+    """The Couette sandwich benchmark of Sec. III.A as one batch: H = 200 (dx / H = 0.005),
+    Re = 0.1, r_eta x r_xi grid; the steady v_x(y) against the sharp-interface solution
+    (Eq. 13) and against the exact solution of the smooth profile (int 1/eta)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2212_14153_amd import _lib
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    storage = args.storage
+    r_etas = [1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0]
+    r_xis = [0.005, 0.01, 0.02, 0.05]
+    H = 200
+    ws = [workloads.sandwich(ny=H, nx=H, r_eta=r, r_xi=x, storage=storage,
+                             steps=args.sandwich_steps)
+          for r in r_etas for x in r_xis]
+    params = sweep_params(_lib, ws, storage)
+    nodes = sum(w.nx * w.ny for w in ws)
+    budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
+    log(f"sandwich sweep: {len(ws)} channels of {H}x{H}, {args.sandwich_steps} steps, {storage}")
+    b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
+    ids = [b.add(p, w.beads(), args.sandwich_steps) for p, w in zip(params, ws)]
+    for sid, w in zip(ids, ws):
+        b.set_static_phi(sid, workloads.sandwich_phi(H, w.xi))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    while b.run(args.sandwich_steps):
+        pass
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    rows = []
+    y = np.arange(H) + 0.5
+    yy = np.linspace(0, H, 400001)
+    for sid, w in zip(ids, ws):
+        u = b.fields(sid)[1][:, 0]
+        U = w.u_wall
+        inv = 1 / (w.nu_f * (1 + (w.eta_ratio - 1) * workloads.sandwich_phi_at(yy, H, w.xi)))
+        cum = np.concatenate([[0], np.cumsum(0.5 * (inv[1:] + inv[:-1]) * np.diff(yy))])
+        smooth = -U + 2 * U * np.interp(y, yy, cum) / cum[-1]
+        sharp = np.clip(-U + 2 * U * (y - H / 3) / (H / 3), -U, U)
+        rows.append({"r_eta": w.eta_ratio, "r_xi": w.xi / H,
+                     "err_vs_sharp_eq13": float(np.abs(u - sharp).max() / (2 * U)),
+                     "err_vs_smooth_exact": float(np.abs(u - smooth).max() / (2 * U))})
+    b.close()
+    steps = args.sandwich_steps
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    bytes_alg = 18 * BYTES_PER_VALUE[storage] * nodes
+    achieved = bytes_alg * steps / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "sandwich sweep MLUPS", "value": round(mlups, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(ms / steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": storage,
+        "data": "synthetic",
+        "config": {"workload": f"{len(ws)} sandwich channels {H}x{H}, Re = 0.1, "
+                               "r_eta 1-100 x r_xi 0.005-0.05", "nodes_total": nodes,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "whole batch step",
+                     "bytes_per_launch_alg": bytes_alg},
+        "profiles": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,7 +417,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "particle"])
+    ap.add_argument("--mode", default="plain",
+                    choices=["plain", "batch", "serve", "particle", "sandwich"])
+    ap.add_argument("--sandwich-steps", type=int, default=4000)
     ap.add_argument("--particles", type=int, default=64)
     ap.add_argument("--particle-steps", type=int, default=90000)
     ap.add_argument("--f-min", type=float, default=1e-4)
@@ -374,6 +448,8 @@ def main():
         return main_serve(args)
     if args.mode == "particle":
         return main_particle(args)
+    if args.mode == "sandwich":
+        return main_sandwich(args)
 
     import torch
     from paper_2212_14153_amd import _lib
