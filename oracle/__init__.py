@@ -49,6 +49,7 @@ class _Params(ctypes.Structure):
         ("fx_ext", ctypes.c_double), ("fy_ext", ctypes.c_double),
         ("gx_body", ctypes.c_double), ("gy_body", ctypes.c_double),
         ("phi_static", ctypes.POINTER(ctypes.c_double)),
+        ("n_chains", ctypes.c_int),
     ]
 
 
@@ -76,6 +77,7 @@ class OracleParams:
     gx_body: float = 0.0      # uniform body force density on every node
     gy_body: float = 0.0
     phi_static: object = None  # None or [ny]: fixed profile phi_s(y) added in Eq. (1)
+    n_chains: int = 1          # fibers of n_beads / n_chains consecutive beads each
 
     def c(self) -> _Params:
         ps = None
@@ -86,7 +88,8 @@ class OracleParams:
         return _Params(self.nx, self.ny, self.u_wall, self.nu_f, self.eta_ratio, self.xi,
                        self.n_beads, self.radius, self.l0, self.k_s, self.k_b, self.s_e,
                        self.s_eps, self.s_q_fixed, self.clamp_phi, self.periodic_y,
-                       self.fx_ext, self.fy_ext, self.gx_body, self.gy_body, ps)
+                       self.fx_ext, self.fy_ext, self.gx_body, self.gy_body, ps,
+                       self.n_chains)
 
     @classmethod
     def from_mapping(cls, m) -> "OracleParams":

@@ -76,6 +76,8 @@ typedef struct orc_params {
     double gx_body, gy_body; /* uniform body force density on every node                 */
     const double *phi_static; /* NULL or [ny]: a fixed interface profile phi_s(y) added to
                                  sum_i phi_i in Eq. (1) (the solid slabs of Eq. (14))      */
+    int    n_chains;      /* fibers: beads c*L .. c*L+L-1 form fiber c, L = N / n_chains
+                             (<= 1: one fiber)                                             */
 } orc_params;
 
 /* ---------------------------------------------------------- D2Q9 lattice ---------- */
@@ -132,11 +134,10 @@ static void proj_over_len(const double v[2], const double t[2], double L, double
 }
 
 /* F_i = F_i^s + F_i^b, Eq. (10): stretching force Eq. (11a,b) and bending force
- * Eq. (12a-e), each bead i = 1..N evaluated from the printed per-bead formulas; plus the
- * external force F0 of the driven-particle benchmark (Sec. III.B). */
-void orc_bead_forces(const orc_params *p, const double *R, double *F)
+ * Eq. (12a-e), each bead i = 1..N of one fiber evaluated from the printed per-bead
+ * formulas. */
+static void fiber_forces(const orc_params *p, const double *R, int N, double *F)
 {
-    const int N = p->n_beads;
     const double ks = p->k_s / (p->l0 * p->l0);
     for (int i = 1; i <= N; ++i) {
         double Fs[2] = {0.0, 0.0}, Fb[2] = {0.0, 0.0};
@@ -170,8 +171,22 @@ void orc_bead_forces(const orc_params *p, const double *R, double *F)
             Fb[0] -= p->k_b * q[0];
             Fb[1] -= p->k_b * q[1];
         }
-        F[2 * (i - 1)] = Fs[0] + Fb[0] + p->fx_ext;
-        F[2 * (i - 1) + 1] = Fs[1] + Fb[1] + p->fy_ext;
+        F[2 * (i - 1)] = Fs[0] + Fb[0];
+        F[2 * (i - 1) + 1] = Fs[1] + Fb[1];
+    }
+}
+
+/* Forces on every bead: each fiber on its own (no interaction between fibers: the
+ * excluded volume the paper leaves unspecified is not modelled), plus the external force
+ * F0 of the driven-particle benchmark (Sec. III.B). */
+void orc_bead_forces(const orc_params *p, const double *R, double *F)
+{
+    const int C = p->n_chains > 1 ? p->n_chains : 1;
+    const int L = p->n_beads / C;
+    for (int c = 0; c < C; ++c) fiber_forces(p, R + 2 * c * L, L, F + 2 * c * L);
+    for (int b = 0; b < p->n_beads; ++b) {
+        F[2 * b] += p->fx_ext;
+        F[2 * b + 1] += p->fy_ext;
     }
 }
 
