@@ -107,6 +107,11 @@ typedef struct fpd_params {
                                F0 of Sec. III.B), spread by Eq. (4) like F_i               */
     double   g_body[2];     /* uniform body force density on every node; in a periodic box
                                g = -N f_ext / (nx ny) keeps the total momentum constant     */
+    int32_t  n_chains;      /* fibers: beads c L .. c L + L - 1 form fiber c, L = n_beads /
+                               n_chains (<= 1: one fiber); springs and bending act inside a
+                               fiber only, fibers meet through the fluid alone (no
+                               excluded-volume force); the force window then spans the
+                               whole lattice                                                 */
 } fpd_params;
 
 /* Launch shape of the fused lattice kernel; any field <= 0 keeps the current value. */

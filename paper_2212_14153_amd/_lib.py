@@ -43,6 +43,7 @@ class fpd_params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("boundary", ctypes.c_int32),
         ("f_ext", ctypes.c_double * 2), ("g_body", ctypes.c_double * 2),
+        ("n_chains", ctypes.c_int32),
     ]
 
 

@@ -52,6 +52,7 @@ struct Lattice {
 struct Fiber {
     BeadState* bs;
     int n;                    // beads (0: no fiber)
+    int chain_len;            // beads per fiber: fiber c is beads c L .. c L + L - 1
     double a, xi, inv_xi;     // radius and interface thickness
     double rc, rc2;           // support radius a + cutoff * xi and its square
     double nu_f, nu_s;        // fluid and solid kinematic viscosity (rho0 = 1)

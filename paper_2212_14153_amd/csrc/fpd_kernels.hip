@@ -78,27 +78,30 @@ __device__ inline void add_proj(const Bonds& B, int u, int v, double sg_kb, doub
     F[1] += (v1 - vt * t1) * inv;
 }
 
-__device__ inline void bead_force(const Bonds& B, int N, int t, double ks_l02, double l0,
+// Bead t of a fiber of L beads (tc = t mod L is its index inside its fiber; the bonds of
+// the whole bead list are indexed globally, and a bond between two fibers is never used).
+__device__ inline void bead_force(const Bonds& B, int L, int t, double ks_l02, double l0,
                                   double kb, const double fext[2], double F[2]) {
+    const int tc = t % L;
     F[0] = fext[0];  // external driving force (Sec. III.B), zero for the fiber runs
     F[1] = fext[1];
-    if (t >= 1) {  // bond (t-1, t): pulls t back towards t-1 when stretched
+    if (tc >= 1) {  // bond (t-1, t): pulls t back towards t-1 when stretched
         const double s = ks_l02 * (B.L[t - 1] - l0);
         F[0] -= s * B.t[t - 1][0];
         F[1] -= s * B.t[t - 1][1];
     }
-    if (t <= N - 2) {  // bond (t, t+1)
+    if (tc <= L - 2) {  // bond (t, t+1)
         const double s = ks_l02 * (B.L[t] - l0);
         F[0] += s * B.t[t][0];
         F[1] += s * B.t[t][1];
     }
     if (kb == 0.0) return;
-    if (t <= N - 3) add_proj(B, t, t + 1, -kb, F);          // pair (t, t+1): -k_b a_t
-    if (t >= 1 && t <= N - 2) {                             // pair (t-1, t): middle bead
+    if (tc <= L - 3) add_proj(B, t, t + 1, -kb, F);         // pair (t, t+1): -k_b a_t
+    if (tc >= 1 && tc <= L - 2) {                           // pair (t-1, t): middle bead
         add_proj(B, t - 1, t, kb, F);                       //   + k_b a_{t-1}
         add_proj(B, t, t - 1, -kb, F);                      //   - k_b b_{t-1}
     }
-    if (t >= 2) add_proj(B, t - 1, t - 2, kb, F);           // pair (t-2, t-1): + k_b b_{t-2}
+    if (tc >= 2) add_proj(B, t - 1, t - 2, kb, F);          // pair (t-2, t-1): + k_b b_{t-2}
 }
 
 // Window slot (raw bounds) -> x0 (mod nx), width, y0, height; clamped to the reserved
@@ -147,14 +150,14 @@ __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
 
 // The tile that contains node (floor Rx mod nx, floor Ry) owns bead b: it publishes F_b,
 // C_b and the strain of bond (b, b+1).
-__device__ inline void own_bead(const Fiber& fib, const Bonds& B, int N, int b,
-                                const double F[2], double C0, double C1) {
+__device__ inline void own_bead(const Fiber& fib, const Bonds& B, int b, const double F[2],
+                                double C0, double C1) {
     BeadState* bs = fib.bs;
     bs->F[b][0] = F[0];
     bs->F[b][1] = F[1];
     bs->C[b][0] = C0;
     bs->C[b][1] = C1;
-    if (b <= N - 2) {
+    if (b % fib.chain_len <= fib.chain_len - 2) {  // bond (b, b+1) inside the fiber
         const double strain = fabs(B.L[b] - fib.l0) / fib.l0;
         if (!(strain <= 0.5)) atomicOr(&bs->health, FPD_HEALTH_STRAIN);
         atomic_max_nonneg(&bs->max_strain_bits, strain);
@@ -205,7 +208,7 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
             } else {
                 // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
                 double F[2];
-                bead_force(B, fib.n, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+                bead_force(B, fib.chain_len, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
                 const double A = bs->A[b];
                 const double C0 = F[0] / A, C1 = F[1] / A;
                 sC[off + before][0] = C0;
@@ -213,7 +216,7 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
                 const int ox = imod((int)floor(Rx), nx);
                 const int oy = per ? imod((int)floor(Ry), ny) : (int)floor(Ry);
                 if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
-                    own_bead(fib, B, fib.n, b, F, C0, C1);
+                    own_bead(fib, B, b, F, C0, C1);
             }
         }
         total += chunk;
@@ -339,6 +342,9 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
                               a.forces_ready != 0);
     }
 
+    // a tile inside the window that no bead's support reaches is fluid only: no node of
+    // it lies in a support box, so its force-window entries are never read
+    if (fiber_tile && nb == 0) fiber_tile = false;
     // a fixed profile phi_s(y) makes every tile take the fiber path (with no beads to
     // gather outside the window); plain: no force and no viscosity change on this tile
     if (a.row_phi) fiber_tile = true;
@@ -415,6 +421,9 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
                               a.forces_ready != 0);
     }
 
+    // a tile inside the window that no bead's support reaches is fluid only: no node of
+    // it lies in a support box, so its force-window entries are never read
+    if (fiber_tile && nb == 0) fiber_tile = false;
     // a fixed profile phi_s(y) makes every tile take the fiber path (with no beads to
     // gather outside the window); plain: no force and no viscosity change on this tile
     if (a.row_phi) fiber_tile = true;
@@ -706,7 +715,7 @@ __global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
     fill_bonds(bs, fib.n, B);
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
-        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+        bead_force(B, fib.chain_len, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
         bs->F[t][0] = F[0];
         bs->F[t][1] = F[1];
         bs->C[t][0] = F[0] / bs->A[t];
@@ -1052,8 +1061,8 @@ __global__ void __launch_bounds__(kBeadThreads) batch_forces_kernel(BatchArgs b)
     fill_bonds(bs, fib.n, B);
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
-        bead_force(B, fib.n, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
-        own_bead(fib, B, fib.n, t, F, F[0] / bs->A[t], F[1] / bs->A[t]);
+        bead_force(B, fib.chain_len, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+        own_bead(fib, B, t, F, F[0] / bs->A[t], F[1] / bs->A[t]);
     }
 }
 

@@ -54,6 +54,21 @@ size_t storage_elem(int st) {
 
 int padded_stride(int nx) { return (nx + 63) / 64 * 64; }
 
+int chains_of(const fpd_params* p) { return p->n_chains > 1 ? p->n_chains : 1; }
+
+// Reserved force window (columns, rows): around one fiber, 1.5 times its contour plus the
+// support on both sides; several fibers may spread over the whole lattice.
+void window_size(const fpd_params* p, double rc, int& w, int& h) {
+    if (chains_of(p) > 1) {
+        w = p->nx;
+        h = p->ny;
+        return;
+    }
+    const double span = 1.5 * (p->n_beads - 1) * p->l0 + 2.0 * rc + 4.0;
+    w = (int)ceil(span) < p->nx ? (int)ceil(span) : p->nx;
+    h = (int)ceil(span) < p->ny ? (int)ceil(span) : p->ny;
+}
+
 // Launch shapes measured best on MI355X at 8192 x 2048 (default block order, no XCD remap):
 // 128 x 2 for float64, 256 x 1 for float32, 64 x 4 with two rows per thread for the
 // two-byte formats (whose lanes update two nodes each).
@@ -113,6 +128,7 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     Fiber& f = a.fib;
     f.bs = s->bs;
     f.n = s->fiber ? s->p.n_beads : 0;
+    f.chain_len = s->p.n_beads > 0 ? s->p.n_beads / chains_of(&s->p) : 1;
     f.a = s->p.radius;
     f.xi = s->p.xi;
     f.inv_xi = 1.0 / s->p.xi;
@@ -157,6 +173,9 @@ int validate(const fpd_params* p) {
         return fail(FPD_EINVAL, "unknown init_flow %d", p->init_flow);
     if (p->n_beads < 0 || p->n_beads > FPD_MAX_BEADS)
         return fail(FPD_EINVAL, "n_beads must be in [0, %d]", FPD_MAX_BEADS);
+    if (p->n_chains < 0 || (p->n_beads > 0 && p->n_beads % chains_of(p) != 0))
+        return fail(FPD_EINVAL, "n_beads (%d) must be a multiple of n_chains (%d)", p->n_beads,
+                    p->n_chains);
     if (p->boundary != FPD_WALLS && p->boundary != FPD_PERIODIC)
         return fail(FPD_EINVAL, "unknown boundary %d", p->boundary);
     if (p->boundary == FPD_PERIODIC && (p->u_wall != 0.0 || p->init_flow != FPD_INIT_REST))
@@ -345,9 +364,7 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
         return bail(fail(FPD_EDEVICE, "hipMemset failed"));
     if (p->n_beads > 0) {
         // window large enough for the chain stretched by 50% in any orientation
-        const double span = 1.5 * (p->n_beads - 1) * p->l0 + 2.0 * s->rc + 4.0;
-        s->rect_wmax = (int)ceil(span) < p->nx ? (int)ceil(span) : p->nx;
-        s->rect_hmax = (int)ceil(span) < p->ny ? (int)ceil(span) : p->ny;
+        window_size(p, s->rc, s->rect_wmax, s->rect_hmax);
         const size_t tb = p->storage == FPD_F64 ? 8 : 4;
         if (hipMalloc(&s->rect_f, (size_t)s->rect_wmax * s->rect_hmax * 2 * tb) != hipSuccess)
             return bail(fail(FPD_ENOMEM, "fiber window allocation failed"));
@@ -460,7 +477,9 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
             (y - s->p.radius - s->p.xi < 0.0 || y + s->p.radius + s->p.xi > s->p.ny))
             return fail(FPD_EINVAL, "bead %d lies within a + xi of a wall", i);
     }
+    const int Lc = N / chains_of(&s->p);
     for (int i = 0; i + 1 < N; ++i) {
+        if ((i + 1) % Lc == 0) continue;  // last bead of a fiber: no bond to the next one
         const double dx = R[2 * i + 2] - R[2 * i], dy = R[2 * i + 3] - R[2 * i + 1];
         const double span = sqrt(dx * dx + dy * dy);
         if (!(span > 0.0)) return fail(FPD_EINVAL, "beads %d and %d coincide", i, i + 1);
@@ -961,10 +980,9 @@ size_t footprint_of(const fpd_params* p) {
     size_t rect = 0;
     if (p->n_beads > 0) {
         const double rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
-        const double span = 1.5 * (p->n_beads - 1) * p->l0 + 2.0 * rc + 4.0;
-        const size_t w = (size_t)fmin(ceil(span), (double)p->nx);
-        const size_t h = (size_t)fmin(ceil(span), (double)p->ny);
-        rect = w * h * 2 * (p->storage == FPD_F64 ? 8 : 4);
+        int w = 0, h = 0;
+        window_size(p, rc, w, h);
+        rect = (size_t)w * (size_t)h * 2 * (p->storage == FPD_F64 ? 8 : 4);
     }
     return 2 * pop + rect + sizeof(BeadState);
 }

@@ -59,6 +59,8 @@ class Workload:
     boundary: int = 0                    # 0 moving walls, 1 periodic box (no walls)
     f_ext: tuple = (0.0, 0.0)            # external force on every bead
     g_body: tuple = (0.0, 0.0)           # uniform body force density on every node
+    n_chains: int = 1                    # fibers of n_beads / n_chains consecutive beads
+    centres: tuple = ()                  # several fibers: ((cx, cy, theta), ...)
 
     def params(self) -> dict:
         """Lattice parameters as a plain mapping (both sides read what they need; the
@@ -69,6 +71,10 @@ class Workload:
         return d
 
     def beads(self) -> np.ndarray:
+        if self.n_chains > 1:
+            L = self.n_beads // self.n_chains
+            return np.concatenate([straight_fiber(L, self.l0, th, x, y)
+                                   for (x, y, th) in self.centres])
         return straight_fiber(self.n_beads, self.l0, self.theta0, self.cx, self.cy)
 
     def with_(self, **kw) -> "Workload":
@@ -185,6 +191,36 @@ def driven_particle(n: int = 48, radius: float = 3.0, xi: float = 1.0, force: fl
         k_b=0.0, theta0=0.0, cx=n / 2 + offset[0], cy=n / 2 + offset[1], steps=steps,
         storage=storage, init_flow=0, boundary=1, f_ext=(force, 0.0),
         g_body=(-force / (n * n), 0.0))
+
+
+def fiber_suspension(n_fibers: int = 8, beads: int = 10, nx: int = 1024, ny: int = 256,
+                     radius: float = 3.0, re_ps: float = 5.0, kappa: float = 1.0,
+                     u_wall: float = 0.01, storage: str = "f32", seed: int = 4447,
+                     steps: int = 5000) -> Workload:
+    """Several straight fibers (touching beads, l0 = 2a) at seeded random positions and
+    angles in the +-U Couette channel, kept apart by at least one contour length and away
+    from the walls; the groups of Eq. (18) are those of one fiber."""
+    l0 = 2.0 * radius
+    lc = beads * l0
+    gamma = 2.0 * u_wall / ny
+    nu = gamma * lc * lc / (4.0 * re_ps)
+    rng = np.random.default_rng(seed)
+    centres = []
+    reach = 0.5 * lc + radius + 2.0
+    while len(centres) < n_fibers:
+        th = float(rng.uniform(0, math.pi))
+        x = float(rng.uniform(0, nx))
+        y = float(rng.uniform(reach, ny - reach))
+        if all(min(abs(x - cx), nx - abs(x - cx)) ** 2 + (y - cy) ** 2 > (1.2 * lc) ** 2
+               for cx, cy, _ in centres):
+            centres.append((x, y, th))
+    return Workload(
+        name=f"suspension_{n_fibers}x{beads}_{nx}x{ny}_{storage}", nx=nx, ny=ny,
+        u_wall=u_wall, nu_f=nu, eta_ratio=50.0, xi=1.0, n_beads=n_fibers * beads,
+        radius=radius, l0=l0, k_s=0.1 * math.pi * radius ** 2 * l0 ** 2,
+        k_b=kappa * nu * gamma * lc * lc / 2.0, theta0=0.0, cx=0.0, cy=0.0, steps=steps,
+        storage=storage, kappa=kappa, re_ps=re_ps, confinement=lc / ny, n_chains=n_fibers,
+        centres=tuple(centres))
 
 
 def sandwich_phi_at(y, H: float, xi: float) -> np.ndarray:
