@@ -52,6 +52,10 @@ def workload(name, storage):
         return workloads.c1_small_fp64().with_(storage=storage)
     if name == "c2":
         return workloads.c2_medium_fp32().with_(storage=storage)
+    if name == "suspension":   # 25 fibers of 10 beads with C3's fiber and flow parameters
+        return workloads.fiber_suspension(n_fibers=25, beads=10, nx=8192, ny=2048,
+                                          radius=4.0, re_ps=5.0, kappa=3.3, u_wall=0.01,
+                                          storage=storage)
     return workloads.c3_large(storage)
 
 
@@ -413,7 +417,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_VALUE))
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "suspension"])
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")

@@ -13,6 +13,8 @@ constexpr int kBeadThreads = 256;   // finish kernel (one thread per bead)
 // Bead kernels (single and batched) use one block size: the per-bead FP64 reduction tree
 // follows it, so a simulation's bead velocities are bitwise the same alone and in a batch.
 constexpr int kBeadBlock = 256;
+// Occupancy bitmap of the fiber supports: one bit per square cell of 2^occ_shift nodes.
+constexpr int kOccWords = 1024;   // up to 32768 cells per slot
 
 // Device-resident fiber state, float64 (bead integration and reductions stay in FP64
 // whatever the population storage).
@@ -27,6 +29,10 @@ struct BeadState {
     // slot the next step reads with atomic min / max, so the result does not depend on the
     // order in which beads finish.
     int win[2][4];
+    // Cells any bead's support touches, one bitmap per parity like the window: the bead
+    // kernel marks the slot the next step reads (atomic or), tile 0 of a step clears the
+    // slot the step's bead kernel fills.  Only tiles over a marked cell gather beads.
+    unsigned int occ[2][kOccWords];
     unsigned int health;                 // FPD_HEALTH_* bits, sticky (atomic or)
     unsigned int reserved;
     unsigned long long max_strain_bits;  // bits of the largest |L - l0| / l0 (atomic max)
@@ -53,6 +59,8 @@ struct Fiber {
     BeadState* bs;
     int n;                    // beads (0: no fiber)
     int chain_len;            // beads per fiber: fiber c is beads c L .. c L + L - 1
+    int occ_shift;            // occupancy cell side 2^occ_shift nodes
+    int occ_nx, occ_ny;       // cells per row and rows of cells
     double a, xi, inv_xi;     // radius and interface thickness
     double rc, rc2;           // support radius a + cutoff * xi and its square
     double nu_f, nu_s;        // fluid and solid kinematic viscosity (rho0 = 1)

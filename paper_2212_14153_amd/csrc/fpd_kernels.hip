@@ -148,6 +148,65 @@ __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
     if (v >= 0.0) atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
+// ------------------------------------------------------------ occupancy bitmap ----
+
+__device__ inline int occ_words(const Fiber& fib) { return (fib.occ_nx * fib.occ_ny + 31) >> 5; }
+
+// Does any cell under the tile's nodes (columns [x0, x0 + w), rows [y0, y0 + h), clipped
+// to the lattice) hold a mark in `slot`?
+// The cells of one cell row are consecutive bits, so a tile (at most 256 nodes wide and
+// 16 rows high, i.e. at most 9 x 2 cells of 32) reads a few words, all issued together.
+__device__ inline bool occ_hit(const Fiber& fib, int slot, int x0, int w, int y0, int h,
+                               int nx, int ny) {
+    const unsigned* m = fib.bs->occ[slot];
+    const int s = fib.occ_shift;
+    const int c0 = x0 >> s, c1 = (min(x0 + w, nx) - 1) >> s;
+    const int r0 = y0 >> s, r1 = (min(y0 + h, ny) - 1) >> s;
+    unsigned any = 0u;
+    for (int r = r0; r <= r1; ++r) {
+        const int b0 = r * fib.occ_nx + c0, b1 = r * fib.occ_nx + c1;  // bit range
+        for (int wd = b0 >> 5; wd <= (b1 >> 5); ++wd) {
+            const int lo = max(b0 - (wd << 5), 0), hi = min(b1 - (wd << 5), 31);
+            const unsigned mask = (hi - lo == 31) ? 0xffffffffu
+                                                  : (((1u << (hi - lo + 1)) - 1u) << lo);
+            any |= m[wd] & mask;
+        }
+    }
+    return any != 0u;
+}
+
+// Mark the cells of the unwrapped node range [lo, hi] x [jlo, jhi] (x wraps; y wraps in a
+// periodic box, else it is clipped to the channel).
+__device__ inline void occ_mark(const Fiber& fib, int slot, long long lo, long long hi,
+                                long long jlo, long long jhi, int nx, int ny, bool per) {
+    unsigned* m = fib.bs->occ[slot];
+    const int s = fib.occ_shift;
+    if (!per) {
+        jlo = jlo < 0 ? 0 : jlo;
+        jhi = jhi > ny - 1 ? ny - 1 : jhi;
+    }
+    if (hi - lo + 1 >= nx) {
+        lo = 0;
+        hi = nx - 1;
+    }
+    if (per && jhi - jlo + 1 >= ny) {
+        jlo = 0;
+        jhi = ny - 1;
+    }
+    for (long long y = jlo; y <= jhi;) {
+        const int yw = (int)(per ? ((y % ny) + ny) % ny : y);
+        const int r = yw >> s;
+        for (long long x = lo; x <= hi;) {
+            const int xw = (int)(((x % nx) + nx) % nx);
+            const int c = xw >> s;
+            const int cell = r * fib.occ_nx + c;
+            atomicOr(&m[cell >> 5], 1u << (cell & 31));
+            x += min((c + 1) << s, nx) - xw;  // to the next cell (or the wrap)
+        }
+        y += min((r + 1) << s, ny) - yw;
+    }
+}
+
 // The tile that contains node (floor Rx mod nx, floor Ry) owns bead b: it publishes F_b,
 // C_b and the strain of bond (b, b+1).
 __device__ inline void own_bead(const Fiber& fib, const Bonds& B, int b, const double F[2],
@@ -167,15 +226,15 @@ __device__ inline void own_bead(const Fiber& fib, const Bonds& B, int b, const d
 // ------------------------------------------------- bead list for a tile (LDS) ------
 // Ordered compaction of the beads whose support box meets the tile's columns
 // [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
-// beads run in the same order as in a full loop.
+// beads run in the same order as in a full loop.  Bond tangents and forces are computed
+// only when some bead is near (with several fibers most window tiles have none).
 __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, int cx0, int cw,
                                    int ry0, int rh, double (*sR)[2], double (*sC)[2],
-                                   int* s_wave, Bonds& B, bool forces_ready) {
+                                   int* sIdx, int* s_wave, Bonds& B, bool forces_ready) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthreads = blockDim.x * blockDim.y;
     const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
     const BeadState* bs = fib.bs;
-    if (!forces_ready) fill_bonds(bs, fib.n, B);
     int total = 0;
     for (int base = 0; base < fib.n; base += nthreads) {
         const int b = base + tid;
@@ -202,26 +261,37 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
         if (hit) {
             sR[off + before][0] = Rx;
             sR[off + before][1] = Ry;
-            if (forces_ready) {
-                sC[off + before][0] = bs->C[b][0];
-                sC[off + before][1] = bs->C[b][1];
-            } else {
-                // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
-                double F[2];
-                bead_force(B, fib.chain_len, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
-                const double A = bs->A[b];
-                const double C0 = F[0] / A, C1 = F[1] / A;
-                sC[off + before][0] = C0;
-                sC[off + before][1] = C1;
-                const int ox = imod((int)floor(Rx), nx);
-                const int oy = per ? imod((int)floor(Ry), ny) : (int)floor(Ry);
-                if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
-                    own_bead(fib, B, b, F, C0, C1);
-            }
+            sIdx[off + before] = b;
         }
         total += chunk;
         __syncthreads();
     }
+    if (total == 0) return 0;  // block-uniform
+    if (forces_ready) {
+        for (int i = tid; i < total; i += nthreads) {
+            const int b = sIdx[i];
+            sC[i][0] = bs->C[b][0];
+            sC[i][1] = bs->C[b][1];
+        }
+    } else {
+        fill_bonds(bs, fib.n, B);
+        for (int i = tid; i < total; i += nthreads) {
+            // F_b^n from the current positions, C_b = F_b / A_b (Eq. 4 coefficient)
+            const int b = sIdx[i];
+            double F[2];
+            bead_force(B, fib.chain_len, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+            const double A = bs->A[b];
+            const double C0 = F[0] / A, C1 = F[1] / A;
+            sC[i][0] = C0;
+            sC[i][1] = C1;
+            const double Rx = sR[i][0], Ry = sR[i][1];
+            const int ox = imod((int)floor(Rx), nx);
+            const int oy = per ? imod((int)floor(Ry), ny) : (int)floor(Ry);
+            if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
+                own_bead(fib, B, b, F, C0, C1);
+        }
+    }
+    __syncthreads();
     return total;
 }
 
@@ -232,6 +302,7 @@ struct TileLds {
     double R[kMaxBeads][2];
     double C[kMaxBeads][2];
     Bonds bonds;
+    int idx[kMaxBeads];
     int wave[16];
 };
 
@@ -323,22 +394,28 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
         wy0 = win.y0;
         ww = win.w;
         wh = win.h;
-        if (tile == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-            // the bead kernel of this step fills the other slot from scratch
-            int* nxt = bs->win[1 - a.parity];
-            nxt[0] = 0x7fffffff;
-            nxt[1] = -0x7fffffff;
-            nxt[2] = 0x7fffffff;
-            nxt[3] = -0x7fffffff;
-            if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
+        if (tile == 0) {
+            // the bead kernel of this step fills the other slots from scratch
+            const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+            if (tid == 0) {
+                int* nxt = bs->win[1 - a.parity];
+                nxt[0] = 0x7fffffff;
+                nxt[1] = -0x7fffffff;
+                nxt[2] = 0x7fffffff;
+                nxt[3] = -0x7fffffff;
+                if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
+            }
+            for (int i = tid; i < occ_words(a.fib); i += blockDim.x * blockDim.y)
+                bs->occ[1 - a.parity][i] = 0u;
         }
         const bool rows_hit =
             per ? cols_overlap(ytile, a.rows_per_block, wy0, wh, ny)
                          : (ytile <= wy0 + wh - 1 && ytile + a.rows_per_block - 1 >= wy0);
-        fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx);
+        fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx) &&
+                     occ_hit(a.fib, a.parity, xtile, tw, ytile, a.rows_per_block, nx, ny);
         if (fiber_tile)
             nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
-                              a.rows_per_block, sR, sC, s_wave, lds.bonds,
+                              a.rows_per_block, sR, sC, lds.idx, s_wave, lds.bonds,
                               a.forces_ready != 0);
     }
 
@@ -403,21 +480,28 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
         wy0 = win.y0;
         ww = win.w;
         wh = win.h;
-        if (tile == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-            int* nxt = bs->win[1 - a.parity];
-            nxt[0] = 0x7fffffff;
-            nxt[1] = -0x7fffffff;
-            nxt[2] = 0x7fffffff;
-            nxt[3] = -0x7fffffff;
-            if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
+        if (tile == 0) {
+            // the bead kernel of this step fills the other slots from scratch
+            const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+            if (tid == 0) {
+                int* nxt = bs->win[1 - a.parity];
+                nxt[0] = 0x7fffffff;
+                nxt[1] = -0x7fffffff;
+                nxt[2] = 0x7fffffff;
+                nxt[3] = -0x7fffffff;
+                if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
+            }
+            for (int i = tid; i < occ_words(a.fib); i += blockDim.x * blockDim.y)
+                bs->occ[1 - a.parity][i] = 0u;
         }
         const bool rows_hit =
             per ? cols_overlap(ytile, a.rows_per_block, wy0, wh, ny)
                          : (ytile <= wy0 + wh - 1 && ytile + a.rows_per_block - 1 >= wy0);
-        fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx);
+        fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx) &&
+                     occ_hit(a.fib, a.parity, xtile, tw, ytile, a.rows_per_block, nx, ny);
         if (fiber_tile)
             nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
-                              a.rows_per_block, lds.R, lds.C, lds.wave, lds.bonds,
+                              a.rows_per_block, lds.R, lds.C, lds.idx, lds.wave, lds.bonds,
                               a.forces_ready != 0);
     }
 
@@ -669,10 +753,13 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
         // this bead's share of the next support window and its health bits
         int* nw = bs->win[win_out];
         if (bead_sane(Rx, Ry)) {
-            atomicMin(&nw[0], (int)floor(Rx - 0.5 - fib.rc));
-            atomicMax(&nw[1], (int)ceil(Rx - 0.5 + fib.rc));
-            atomicMin(&nw[2], (int)floor(Ry - 0.5 - fib.rc));
-            atomicMax(&nw[3], (int)ceil(Ry - 0.5 + fib.rc));
+            const int lo = (int)floor(Rx - 0.5 - fib.rc), hi = (int)ceil(Rx - 0.5 + fib.rc);
+            const int jlo = (int)floor(Ry - 0.5 - fib.rc), jhi = (int)ceil(Ry - 0.5 + fib.rc);
+            atomicMin(&nw[0], lo);
+            atomicMax(&nw[1], hi);
+            atomicMin(&nw[2], jlo);
+            atomicMax(&nw[3], jhi);
+            occ_mark(fib, win_out, lo, hi, jlo, jhi, nx, ny, per);
         }
         const double Vx = bs->V[b][0], Vy = bs->V[b][1];
         unsigned h = 0u;

@@ -56,6 +56,17 @@ int padded_stride(int nx) { return (nx + 63) / 64 * 64; }
 
 int chains_of(const fpd_params* p) { return p->n_chains > 1 ? p->n_chains : 1; }
 
+// Occupancy cells: the smallest power-of-two side >= 32 nodes whose grid fits the bitmap.
+void occupancy_cells(int nx, int ny, int& shift, int& cx, int& cy) {
+    shift = 5;
+    for (;;) {
+        cx = (nx + (1 << shift) - 1) >> shift;
+        cy = (ny + (1 << shift) - 1) >> shift;
+        if ((long long)cx * cy <= 32LL * kOccWords) return;
+        ++shift;
+    }
+}
+
 // Reserved force window (columns, rows): around one fiber, 1.5 times its contour plus the
 // support on both sides; several fibers may spread over the whole lattice.
 void window_size(const fpd_params* p, double rc, int& w, int& h) {
@@ -129,6 +140,7 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.bs = s->bs;
     f.n = s->fiber ? s->p.n_beads : 0;
     f.chain_len = s->p.n_beads > 0 ? s->p.n_beads / chains_of(&s->p) : 1;
+    occupancy_cells(s->p.nx, s->p.ny, f.occ_shift, f.occ_nx, f.occ_ny);
     f.a = s->p.radius;
     f.xi = s->p.xi;
     f.inv_xi = 1.0 / s->p.xi;
@@ -506,6 +518,7 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
         h.R[i][1] = R[2 * i + 1];
         h.V[i][0] = h.V[i][1] = 0.0;
     }
+    memset(h.occ, 0, sizeof h.occ);  // empty occupancy; the bead kernel fills slot `cur`
     for (int k = 0; k < 2; ++k) {  // empty windows; the bead kernel fills slot `cur`
         h.win[k][0] = 0x7fffffff;
         h.win[k][1] = -0x7fffffff;
@@ -849,7 +862,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 
 // ---------------------------------------------------------------- checkpoint -------
 
-static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '4'};
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '5'};
 
 int fpd_save(fpd_sim* s, const char* path) {
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
