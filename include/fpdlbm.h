@@ -209,6 +209,20 @@ int fpd_read_beads(fpd_sim *s, double *R, double *V, double *F);
  * it (set it again after fpd_load).  Synchronises. */
 int fpd_set_static_phi(fpd_sim *s, const double *phi);
 
+/* Fiber-ends recorder for the tumbling analysis of Sec. IV (orientation theta(t),
+ * angular velocity, period, end-to-end length): from now on, every `every` steps the
+ * state R^n of each fiber is summarised on the device (at the start of the step, by the
+ * lattice kernel) as its end-to-end vector R_last - R_first and its centroid, into a ring
+ * of `capacity` records (older records are overwritten).  Restarts any recording.
+ * FPD_ESTATE without a fiber. */
+int fpd_record_start(fpd_sim *s, int32_t every, int64_t capacity);
+int fpd_record_stop(fpd_sim *s);
+
+/* The records held, oldest first: *n_records receives their number (out may be NULL to
+ * ask); out[n][1 + 4 * fibers] receives [step n, then (ex, ey, cx, cy) per fiber].
+ * FPD_EINVAL if cap_records is smaller than the number held. */
+int fpd_record_read(fpd_sim *s, double *out, int64_t cap_records, int64_t *n_records);
+
 /* Diagnostics of the driven-particle benchmark (Sec. III.B) for bead `bead` on the
  * current state (pre-collision populations at step n, positions R^n, force density f^n
  * of that state), computed on the device with fixed-order FP64 sums; synchronises.
@@ -298,8 +312,11 @@ int fpd_batch_read_populations(fpd_batch *b, int64_t sim_id, double *f);
 int fpd_batch_read_fields(fpd_batch *b, int64_t sim_id, double *rho, double *ux, double *uy,
                           double *eta);
 int fpd_batch_particle_stats(fpd_batch *b, int64_t sim_id, int32_t bead, double *out);
-/* fpd_set_static_phi for a simulation of the batch. */
+/* fpd_set_static_phi, fpd_record_start, fpd_record_read for a simulation of the batch. */
 int fpd_batch_set_static_phi(fpd_batch *b, int64_t sim_id, const double *phi);
+int fpd_batch_record_start(fpd_batch *b, int64_t sim_id, int32_t every, int64_t capacity);
+int fpd_batch_record_read(fpd_batch *b, int64_t sim_id, double *out, int64_t cap_records,
+                          int64_t *n_records);
 int fpd_batch_sim_info(fpd_batch *b, int64_t sim_id, int64_t *steps, int32_t *status,
                        uint32_t *health);
 

@@ -86,6 +86,9 @@ SIGNATURES = [
     ("fpd_read_beads", ctypes.c_int, [_SIM, _D, _D, _D]),
     ("fpd_particle_stats", ctypes.c_int, [_SIM, ctypes.c_int32, _D]),
     ("fpd_set_static_phi", ctypes.c_int, [_SIM, _D]),
+    ("fpd_record_start", ctypes.c_int, [_SIM, ctypes.c_int32, ctypes.c_int64]),
+    ("fpd_record_stop", ctypes.c_int, [_SIM]),
+    ("fpd_record_read", ctypes.c_int, [_SIM, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     ("fpd_set_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_get_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_set_flags", ctypes.c_int, [_SIM, ctypes.c_uint32]),
@@ -110,6 +113,9 @@ SIGNATURES = [
     ("fpd_batch_read_fields", ctypes.c_int, [_SIM, ctypes.c_int64, _D, _D, _D, _D]),
     ("fpd_batch_particle_stats", ctypes.c_int, [_SIM, ctypes.c_int64, ctypes.c_int32, _D]),
     ("fpd_batch_set_static_phi", ctypes.c_int, [_SIM, ctypes.c_int64, _D]),
+    ("fpd_batch_record_start", ctypes.c_int, [_SIM, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64]),
+    ("fpd_batch_record_read", ctypes.c_int, [_SIM, ctypes.c_int64, _D, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64)]),
     ("fpd_batch_sim_info", ctypes.c_int,
      [_SIM, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
       ctypes.POINTER(ctypes.c_uint32)]),
@@ -294,6 +300,18 @@ class Simulation:
         phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.ny)
         check(lib().fpd_set_static_phi(self.h, _ptr(phi)))
 
+    def record_start(self, every: int = 1, capacity: int = 1 << 16):
+        """Record each fiber's end-to-end vector and centroid every `every` steps."""
+        check(lib().fpd_record_start(self.h, int(every), int(capacity)))
+
+    def record_stop(self):
+        check(lib().fpd_record_stop(self.h))
+
+    def record(self) -> np.ndarray:
+        """[records, 1 + 4 fibers]: step, then (ex, ey, cx, cy) per fiber, oldest first."""
+        return _read_record(lambda out, cap, n: lib().fpd_record_read(self.h, out, cap, n),
+                            self.p.n_chains)
+
     STATS_FIELDS = ("A", "V0x", "V0y", "eps_v", "Fvisc_x", "Fvisc_y", "Fpres_x", "Fpres_y")
 
     def particle_stats(self, bead: int = 0) -> dict:
@@ -356,6 +374,16 @@ def fpd_sim_footprint(p: fpd_params) -> int:
     return int(lib().fpd_sim_footprint(ctypes.byref(p)))
 
 
+def _read_record(call, n_chains: int) -> np.ndarray:
+    width = 1 + 4 * max(int(n_chains), 1)
+    n = ctypes.c_int64()
+    check(call(None, 0, ctypes.byref(n)))
+    out = np.empty((n.value, width))
+    if n.value:
+        check(call(_ptr(out), n.value, ctypes.byref(n)))
+    return out
+
+
 class Batch:
     """A batch of independent simulations advanced together (C ABI fpd_batch_*)."""
 
@@ -367,6 +395,7 @@ class Batch:
         self.h = h
         self.storage = st
         self.shapes = {}
+        self.chains = {}
 
     def close(self):
         if self.h:
@@ -400,6 +429,7 @@ class Batch:
         check(lib().fpd_batch_add(self.h, ctypes.byref(params), Rp, int(n_steps),
                                   ctypes.byref(sid)))
         self.shapes[sid.value] = (params.nx, params.ny, params.n_beads)
+        self.chains[sid.value] = max(int(params.n_chains), 1)
         return sid.value
 
     def try_add(self, params: fpd_params, R, n_steps: int):
@@ -428,6 +458,14 @@ class Batch:
         if n:
             check(lib().fpd_batch_read_beads(self.h, sid, _ptr(R), _ptr(V), _ptr(F)))
         return R, V, F
+
+    def record_start(self, sid: int, every: int = 1, capacity: int = 1 << 16):
+        check(lib().fpd_batch_record_start(self.h, int(sid), int(every), int(capacity)))
+
+    def record(self, sid: int) -> np.ndarray:
+        chains = self.chains.get(sid, 1)
+        return _read_record(lambda out, cap, n: lib().fpd_batch_record_read(self.h, int(sid), out,
+                                                                             cap, n), chains)
 
     def set_static_phi(self, sid: int, phi):
         """Fixed profile phi_s(y) for one simulation of the batch (None removes it)."""

@@ -82,11 +82,22 @@ struct StepArgs {
     double s_e, s_eps;
     double gx, gy;            // uniform body force density on every node
     const double* row_phi;    // NULL or [ny]: fixed profile phi_s(y) added in Eq. (1)
+    struct RecordBuf* rec;    // NULL or the fiber-ends recorder
     Fiber fib;
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
     int rows_per_block;       // block_y * rows_per_thread
     int xcd_remap;
     int forces_ready;         // 1: F^n and F/A were computed by a forces kernel this step
+};
+
+// Fiber-ends recorder (device memory): at the start of every step tile 0 counts the step
+// and, every `every` steps, stores the end-to-end vector R_last - R_first and the centroid
+// of each fiber of the state R^n into a ring of `cap` records [step, (ex, ey, cx, cy) per
+// fiber] (the step relative to the start of the recording).
+struct RecordBuf {
+    unsigned long long count;  // steps seen since the start
+    int every, cap, fibers, pad;
+    double data[1];            // [cap][1 + 4 * fibers]
 };
 
 // A batch step: per simulation two StepArgs (the step parities of a chunk), prefix sums of
@@ -119,6 +130,8 @@ hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
                        hipStream_t st);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);
+// fiber-ends record of the step about to run (nothing unless a recording runs)
+hipError_t launch_record(const StepArgs& a, hipStream_t st);
 // any_periodic: some simulation of the batch has no walls (the kernel then reads the
 // boundary of each simulation from its arguments)
 hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int rows_per_thread,

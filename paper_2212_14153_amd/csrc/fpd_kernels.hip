@@ -578,6 +578,38 @@ __device__ inline void tile_any(const StepArgs& a, const Window& win, int tile, 
         lattice_tile<ST, SPT, BC>(a, win, tile, lds);
 }
 
+// Called by every thread of one block ahead of the step's lattice kernel, and only while a
+// recording runs, so the lattice kernels carry no trace of it.
+__device__ inline void record_ends(const StepArgs& a) {
+    RecordBuf* r = a.rec;
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const unsigned long long n = r->count;
+    if (n % (unsigned long long)r->every == 0ull) {
+        const int width = 1 + 4 * r->fibers;
+        double* rec = r->data + (size_t)((n / r->every) % (unsigned long long)r->cap) * width;
+        if (tid == 0) rec[0] = (double)n;
+        const int L = a.fib.chain_len;
+        for (int c = tid; c < r->fibers; c += blockDim.x * blockDim.y) {
+            const double(*R)[2] = a.fib.bs->R + c * L;
+            double cx = 0.0, cy = 0.0;
+            for (int i = 0; i < L; ++i) {
+                cx += R[i][0];
+                cy += R[i][1];
+            }
+            rec[1 + 4 * c] = R[L - 1][0] - R[0][0];
+            rec[2 + 4 * c] = R[L - 1][1] - R[0][1];
+            rec[3 + 4 * c] = cx / L;
+            rec[4 + 4 * c] = cy / L;
+        }
+    }
+    __syncthreads();  // every thread has read the count
+    if (tid == 0) r->count = n + 1ull;
+}
+
+__global__ void __launch_bounds__(kBeadThreads) record_kernel(StepArgs a) {
+    record_ends(a);
+}
+
 template <int ST, int SPT, int BC>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ TileLds lds;
@@ -1151,6 +1183,7 @@ __global__ void __launch_bounds__(kBeadThreads) batch_forces_kernel(BatchArgs b)
         bead_force(B, fib.chain_len, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
         own_bead(fib, B, t, F, F[0] / bs->A[t], F[1] / bs->A[t]);
     }
+    if (a.rec) record_ends(a);  // positions of the step's start, as for one simulation
 }
 
 template <int ST, int BC>
@@ -1192,6 +1225,12 @@ hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int sp
         case FPD_BF16DEV: return launch_batch_t<FPD_BF16DEV>(b, block, spt, counts, any_periodic, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_record(const StepArgs& a, hipStream_t st) {
+    if (!a.rec || a.fib.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(record_kernel, dim3(1), dim3(kBeadThreads), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_forces(const StepArgs& a, hipStream_t st) {

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stddef.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -105,6 +106,8 @@ struct fpd_sim {
     BeadState* bs = nullptr;
     void* rect_f = nullptr;
     double* row_phi = nullptr;   // fixed profile phi_s(y) [ny], device (fpd_set_static_phi)
+    RecordBuf* rec = nullptr;    // fiber-ends recorder (fpd_record_start)
+    int64_t rec_start = 0;       // step count when the recording started
     int rect_wmax = 0, rect_hmax = 0;
     double rc = 0.0;
     bool fiber = false;
@@ -130,6 +133,7 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     a.gx = s->p.g_body[0];
     a.gy = s->p.g_body[1];
     a.row_phi = s->row_phi;
+    a.rec = s->rec;
     const double tau_f = 3.0 * s->p.nu_f + 0.5;
     a.s_nu_f = 1.0 / tau_f;
     a.s_q_f = s->p.s_q_fixed > 0.0 ? s->p.s_q_fixed
@@ -222,6 +226,7 @@ void drop_graphs(fpd_sim* s) {
 int enqueue_step(fpd_sim* s, int from) {
     const StepArgs a = make_args(s, from);
     const dim3 block(s->launch.block_x, s->launch.block_y);
+    HIP_TRY(launch_record(a, s->stream));
     HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
     if (a.fib.n > 0) HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - from, s->stream));
     return FPD_OK;
@@ -263,6 +268,7 @@ int step_timed(fpd_sim* s, int64_t n) {
             const StepArgs a = make_args(s, s->cur);
             const dim3 block(s->launch.block_x, s->launch.block_y);
             hipEvent_t* ev = &s->events[(size_t)i * per];
+            HIP_TRY(launch_record(a, s->stream));
             HIP_TRY(hipEventRecord(ev[0], s->stream));
             HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
             HIP_TRY(hipEventRecord(ev[1], s->stream));
@@ -474,6 +480,7 @@ void fpd_destroy(fpd_sim* s) {
     if (s->bs) (void)hipFree(s->bs);
     if (s->rect_f) (void)hipFree(s->rect_f);
     if (s->row_phi) (void)hipFree(s->row_phi);
+    if (s->rec) (void)hipFree(s->rec);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -669,6 +676,72 @@ int fpd_set_static_phi(fpd_sim* s, const double* phi) {
         HIP_TRY(hipMemcpy(s->row_phi, phi, sizeof(double) * ny, hipMemcpyHostToDevice));
     }
     drop_graphs(s);  // the captured arguments name the profile
+    return FPD_OK;
+}
+
+int fpd_record_start(fpd_sim* s, int32_t every, int64_t capacity) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    if (s->p.n_beads <= 0) return fail(FPD_ESTATE, "the simulation has no fiber");
+    if (every < 1 || capacity < 1 || capacity > (1LL << 28))
+        return fail(FPD_EINVAL, "every >= 1 and 1 <= capacity <= 2^28 required");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    if (s->rec) (void)hipFree(s->rec);
+    s->rec = nullptr;
+    const int fibers = chains_of(&s->p);
+    const size_t bytes = offsetof(RecordBuf, data) +
+                         sizeof(double) * (size_t)capacity * (size_t)(1 + 4 * fibers);
+    if (hipMalloc((void**)&s->rec, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        s->rec = nullptr;
+        return fail(FPD_ENOMEM, "recorder allocation failed");
+    }
+    RecordBuf h;
+    memset(&h, 0, sizeof h);
+    h.every = every;
+    h.cap = (int)capacity;
+    h.fibers = fibers;
+    HIP_TRY(hipMemcpy(s->rec, &h, offsetof(RecordBuf, data), hipMemcpyHostToDevice));
+    s->rec_start = s->steps;
+    drop_graphs(s);  // the captured arguments name the recorder
+    return FPD_OK;
+}
+
+int fpd_record_stop(fpd_sim* s) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    if (s->rec) (void)hipFree(s->rec);
+    s->rec = nullptr;
+    drop_graphs(s);
+    return FPD_OK;
+}
+
+int fpd_record_read(fpd_sim* s, double* out, int64_t cap, int64_t* n) {
+    if (!s || !n) return fail(FPD_EINVAL, "NULL argument");
+    if (!s->rec) return fail(FPD_ESTATE, "no recording");
+    int rc = sync_check(s);
+    if (rc) return rc;
+    RecordBuf h;
+    HIP_TRY(hipMemcpy(&h, s->rec, offsetof(RecordBuf, data), hipMemcpyDeviceToHost));
+    const int64_t taken = (int64_t)((h.count + h.every - 1) / (unsigned long long)h.every);
+    const int64_t have = taken < h.cap ? taken : h.cap;
+    *n = have;
+    if (!out || have == 0) return FPD_OK;
+    if (cap < have)
+        return fail(FPD_EINVAL, "output holds %lld records, %lld needed", (long long)cap,
+                    (long long)have);
+    const int width = 1 + 4 * h.fibers;
+    std::vector<double> ring((size_t)h.cap * width);
+    HIP_TRY(hipMemcpy(ring.data(), (char*)s->rec + offsetof(RecordBuf, data),
+                      sizeof(double) * ring.size(), hipMemcpyDeviceToHost));
+    const int64_t first = taken - have;  // oldest record still held
+    for (int64_t k = 0; k < have; ++k) {
+        const double* src = ring.data() + (size_t)((first + k) % h.cap) * width;
+        double* dst = out + (size_t)k * width;
+        dst[0] = src[0] + (double)s->rec_start;  // absolute step of the state R^n
+        for (int j = 1; j < width; ++j) dst[j] = src[j];
+    }
     return FPD_OK;
 }
 
@@ -1342,6 +1415,22 @@ int fpd_batch_set_static_phi(fpd_batch* b, int64_t id, const double* phi) {
     const int rc = fpd_set_static_phi(e->sim, phi);
     if (rc == FPD_OK) b->dirty = true;  // the argument table names the profile
     return rc;
+}
+
+int fpd_batch_record_start(fpd_batch* b, int64_t id, int32_t every, int64_t capacity) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int rc = fpd_record_start(e->sim, every, capacity);
+    if (rc == FPD_OK) b->dirty = true;  // the argument table names the recorder
+    return rc;
+}
+
+int fpd_batch_record_read(fpd_batch* b, int64_t id, double* out, int64_t cap, int64_t* n) {
+    BatchEntry* e = b ? find_entry(b, id) : nullptr;
+    if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return fpd_record_read(e->sim, out, cap, n);
 }
 
 int fpd_batch_particle_stats(fpd_batch* b, int64_t id, int32_t bead, double* out) {
