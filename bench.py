@@ -22,7 +22,10 @@ Other modes (each prints one JSON line):
                  the diffuse-interface drag, and throughput;
   --mode sandwich  the Couette sandwich of Sec. III.A (H = 200, Re = 0.1) over a grid of
                  viscosity ratios and interface widths: steady-profile errors against
-                 Eq. (13) and the exact smooth solution.
+                 Eq. (13) and the exact smooth solution;
+  --mode shapes  the shape diagrams of Sec. IV.C (K x C at Re_ps = 1.5, Re_ps x C at
+                 K = 3.3e-5, and the stuck cases of rigid and slightly flexible fibers) as
+                 one batch of recorded runs, each classified from its fiber-ends record.
 """
 from __future__ import annotations
 
@@ -411,6 +414,114 @@ def main_sandwich(args):
     print(json.dumps(out), flush=True)
 
 
+SHAPE_CONF = [0.3, 0.5, 0.6, 0.7, 0.8, 0.87]
+SHAPE_KAPPA = [3.3e-5, 3.3e-4, 3.3e-3, 3.3e-2, 3.3e-1, 3.3, 33.0]
+SHAPE_RE = [0.5, 1.5, 3.0, 4.5, 6.0, 7.5]
+
+
+def shape_points():
+    """(diagram, K, C, Re_ps) of every run: Fig. 10(a) K x C at Re_ps = 1.5, Fig. 10(b)
+    Re_ps x C at K = 3.3e-5 (its Re_ps = 1.5 row is the K = 3.3e-5 row of (a)), and the
+    stuck cases of Fig. 7 for K = 3.3 and 0.33 at (Re_ps, C) = (6, 0.5) and (6, 0.87)
+    (their (1.5, 0.87) cases are in (a)), and the rigid fiber of Fig. 5 (K = 33): Re_ps
+    from 0.5 to 4 at C = 0.2, and C = 0.2, 0.65, 0.75 at Re_ps = 1.5."""
+    pts = [("a", k, c, 1.5) for k in SHAPE_KAPPA for c in SHAPE_CONF]
+    pts += [("b", 3.3e-5, c, r) for r in SHAPE_RE if r != 1.5 for c in SHAPE_CONF]
+    pts += [("stuck", k, c, r) for k in (3.3, 0.33) for r, c in ((6.0, 0.5), (6.0, 0.87))]
+    pts += [("rigid", 33.0, 0.2, r) for r in (0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 4.0)]
+    pts += [("rigid", 33.0, c, 1.5) for c in (0.65, 0.75)]
+    return pts
+
+
+def main_shapes(args):
+    """Shape diagrams of Sec. IV.C: N = 10 touching beads of d = 8 (r_c = 0.1), H = N d / C,
+    L_x = 25 d, r_eta = 100, xi / d = 0.125, fiber flat at the centre, gamma = 1.5e-4 for
+    every run; the fiber ends are recorded every 100 steps and each run is classified
+    (stuck / Jeffery / S-turn / S-coiled) with its periods and stuck angle."""
+    import math
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2212_14153_amd import _lib, tumbling
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    storage = args.storage
+    steps, every, gamma = args.shape_steps, 100, 1.5e-4
+    pts = shape_points()
+    ws = [workloads.flexible_fiber(k, c, r, gamma=gamma, storage=storage, steps=steps)
+          for _, k, c, r in pts]
+    params = sweep_params(_lib, ws, storage)
+    nodes = sum(w.nx * w.ny for w in ws)
+    budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
+    log(f"shape sweep: {len(ws)} channels, {nodes / 1e6:.2f}M nodes, {steps} steps "
+        f"(gamma t = {gamma * steps:.0f}), storage {storage}")
+    b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
+    ids = [b.add(p, w.beads(), steps) for p, w in zip(params, ws)]
+    for sid in ids:
+        b.record_start(sid, every, steps // every + 8)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    left, t0 = steps, time.perf_counter()
+    while left > 0:
+        adv = b.run(min(left, 25000))
+        if adv == 0:
+            break
+        left -= adv
+        log(f"  {steps - left} steps, {time.perf_counter() - t0:.1f} s")
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    rows = []
+    for (diag, k, c, r), w, sid in zip(pts, ws, ids):
+        done, status, hflags = b.info(sid)
+        row = {"diagram": diag, "K": k, "C": round(w.confinement, 4), "Re_ps": r,
+               "status": int(status), "health": int(hflags), "steps": int(done)}
+        rec = b.record(sid) if status == _lib.FPD_SIM_DONE else []
+        if len(rec) > 8:
+            a = tumbling.analyse(rec, straight_length=(w.n_beads - 1) * w.l0, gamma=gamma)
+            cross = tumbling.crossing_times(a["t"], a["theta"])
+            final = math.degrees(a["theta"][-1])
+            final = (final + 90.0) % 180.0 - 90.0
+            row.update(orbit=tumbling.classify(a, gamma), turns=round(a["turns"], 3),
+                       gT_first=round(gamma * cross[0], 2) if len(cross) else None,
+                       gT_later=round(gamma * a["period"], 2) if len(cross) >= 2 else None,
+                       L_min=round(a["L_min"], 3), L_mean=round(a["L_mean"], 3),
+                       r_c_fit=round(a["r_c_fit"], 4),
+                       final_angle_deg=round(final, 1),
+                       turn_sense="clockwise" if a["theta"][-1] < a["theta"][0] else
+                       "counter-clockwise")
+        else:
+            row["orbit"] = "failed"
+        rows.append(row)
+    b.close()
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    bytes_alg = 18 * BYTES_PER_VALUE[storage] * nodes
+    achieved = bytes_alg * steps / (ms * 1e-3) / 1e9
+    for row in rows:
+        log(f"  {row['diagram']:5s} K={row['K']:<8.3g} C={row['C']:.3f} Re={row['Re_ps']:<4g} "
+            f"{row['orbit']:9s} turns={row.get('turns')} gT1={row.get('gT_first')} "
+            f"gT={row.get('gT_later')} Lmin={row.get('L_min')} rfit={row.get('r_c_fit')} "
+            f"angle={row.get('final_angle_deg')} {row.get('turn_sense', '')}")
+    out = {
+        "metric": "shape sweep MLUPS", "value": round(mlups, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(ms / steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": storage,
+        "data": "synthetic",
+        "config": {"workload": f"{len(ws)} confined-Couette fiber runs, N = 10, d = 8, "
+                               f"H = N d / C, L_x = 25 d, r_eta = 100, xi = d / 8, "
+                               f"gamma = {gamma:g}, recorded every {every} steps",
+                   "nodes_total": nodes, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "whole batch step (all kernels)",
+                     "bytes_per_launch_alg": bytes_alg},
+        "runs": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,7 +533,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
     ap.add_argument("--mode", default="plain",
-                    choices=["plain", "batch", "serve", "particle", "sandwich"])
+                    choices=["plain", "batch", "serve", "particle", "sandwich", "shapes"])
+    ap.add_argument("--shape-steps", type=int, default=400000)
     ap.add_argument("--sandwich-steps", type=int, default=4000)
     ap.add_argument("--particles", type=int, default=64)
     ap.add_argument("--particle-steps", type=int, default=90000)
@@ -454,6 +566,8 @@ def main():
         return main_particle(args)
     if args.mode == "sandwich":
         return main_sandwich(args)
+    if args.mode == "shapes":
+        return main_shapes(args)
 
     import torch
     from paper_2212_14153_amd import _lib

@@ -100,3 +100,24 @@ def test_oracle_stiff_fiber_tumbles_on_a_jeffery_orbit():
     assert tumbling.classify(an, gamma) == "jeffery"
     r_geo = 2 * a / lc
     assert r_geo < an["r_c_fit"] < 2 * r_geo
+
+
+@pytest.mark.parametrize("kappa,conf,re", [(3.3e-5, 0.5, 1.5), (3.3, 0.87, 6.0),
+                                           (0.33, 0.3, 0.5)])
+def test_shape_diagram_points_have_the_papers_groups(kappa, conf, re):
+    """Each shape-diagram run sets K, C and Re_ps of Eq. (18) (C up to rounding H to whole
+    nodes), r_c = 0.1 with touching beads, L_x = 25 d, r_eta = 100, xi / d = 0.125, and
+    the walls move at +-gamma H / 2."""
+    import workloads
+    w = workloads.flexible_fiber(kappa, conf, re)
+    d = 2 * w.radius
+    lc = w.n_beads * w.l0
+    gamma = 2 * w.u_wall / w.ny
+    assert w.l0 == d and d / lc == pytest.approx(0.1)
+    assert gamma == pytest.approx(1.5e-4)
+    assert gamma * lc ** 2 / (4 * w.nu_f) == pytest.approx(re)
+    assert 2 * w.k_b / (w.nu_f * gamma * lc ** 2) == pytest.approx(kappa)
+    assert abs(lc / w.ny - conf) <= lc / w.ny ** 2
+    assert w.nx == 25 * d and w.eta_ratio == 100 and w.xi / d == 0.125
+    R = w.beads()
+    assert np.allclose(R[:, 1], w.ny / 2) and R[:, 0].mean() == pytest.approx(w.nx / 2)

@@ -171,6 +171,26 @@ def sweep_sims(count: int = 256, seed: int = 14153, steps: int = 20000,
     return out
 
 
+def flexible_fiber(kappa: float, confinement: float, re_ps: float, n_beads: int = 10,
+                   diameter: float = 8.0, gamma: float = 1.5e-4, eta_ratio: float = 100.0,
+                   xi: float = 1.0, theta0: float = 0.0, storage: str = "f32",
+                   steps: int = 400000) -> Workload:
+    """One point of the shape diagrams of Sec. IV.C: a fiber of N touching beads
+    (l_0 = d, r_c = d / l_c = 1 / N) lying flat (theta = 0) at the centre of a channel of
+    height H = N d / C (rounded to whole nodes) and length L_x = 25 d, r_eta = 100 and
+    xi / d = 0.125 as in the paper's fiber runs.  The shear rate is the same for every
+    point (so all runs cover the same strain per step); Re_ps sets nu_f and K sets k_b
+    through Eq. (18)."""
+    lc = n_beads * diameter
+    ny = int(round(lc / confinement))
+    nx = int(round(25 * diameter))
+    u = 0.5 * gamma * ny
+    name = f"shape_K{kappa:.3g}_C{lc / ny:.3f}_Re{re_ps:g}"
+    return _make(name, nx=nx, ny=ny, n_beads=n_beads, radius=diameter / 2.0, l0=diameter,
+                 u_wall=u, re_ps=re_ps, kappa=kappa, theta0=theta0, steps=steps,
+                 storage=storage, eta_ratio=eta_ratio, xi=xi)
+
+
 def poisson_arrivals(count: int, rate: float = 50.0, seed: int = 50) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)
