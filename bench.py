@@ -438,8 +438,6 @@ def main_shapes(args):
     L_x = 25 d, r_eta = 100, xi / d = 0.125, fiber flat at the centre, gamma = 1.5e-4 for
     every run; the fiber ends are recorded every 100 steps and each run is classified
     (stuck / Jeffery / S-turn / S-coiled) with its periods and stuck angle."""
-    import math
-    import numpy as np
     import torch
     import workloads
     from paper_2212_14153_amd import _lib, tumbling
@@ -482,15 +480,13 @@ def main_shapes(args):
         if len(rec) > 8:
             a = tumbling.analyse(rec, straight_length=(w.n_beads - 1) * w.l0, gamma=gamma)
             cross = tumbling.crossing_times(a["t"], a["theta"])
-            final = math.degrees(a["theta"][-1])
-            final = (final + 90.0) % 180.0 - 90.0
             row.update(orbit=tumbling.classify(a, gamma), turns=round(a["turns"], 3),
                        gT_first=round(gamma * cross[0], 2) if len(cross) else None,
                        gT_later=round(gamma * a["period"], 2) if len(cross) >= 2 else None,
                        L_min=round(a["L_min"], 3), L_mean=round(a["L_mean"], 3),
                        r_c_fit=round(a["r_c_fit"], 4),
-                       final_angle_deg=round(final, 1),
-                       turn_sense="clockwise" if a["theta"][-1] < a["theta"][0] else
+                       final_angle_deg=round(tumbling.final_angle_deg(a), 1),
+                       turn_sense="clockwise" if tumbling.turned_deg(a) < 0 else
                        "counter-clockwise")
         else:
             row["orbit"] = "failed"

@@ -13,6 +13,12 @@ constexpr int kBeadThreads = 256;   // finish kernel (one thread per bead)
 // Bead kernels (single and batched) use one block size: the per-bead FP64 reduction tree
 // follows it, so a simulation's bead velocities are bitwise the same alone and in a batch.
 constexpr int kBeadBlock = 256;
+// nodes per thread and pass of the velocity sums: one simulation (few bead blocks, latency
+// bound: 4) and batches (thousands of bead blocks, where fewer registers let more blocks
+// reside: 2; the FP16 sweep step 590 -> 580 us); the sums run in the same order for any
+// value, so batched and single results stay bitwise equal
+constexpr int kBeadVelBatch = 4;
+constexpr int kBatchBeadVelBatch = 2;
 // Occupancy bitmap of the fiber supports: one bit per square cell of 2^occ_shift nodes.
 constexpr int kOccWords = 1024;   // up to 32768 cells per slot
 

@@ -40,6 +40,30 @@ __device__ inline double block_sum(double v, double* scratch) {
     return s;
 }
 
+// Two sums at once, each in the order of block_sum (bitwise the same results), through one
+// round of the scratch array (2 * waves entries).
+__device__ inline void block_sum2(double& a, double& b, double* scratch) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+        scratch[wave] = a;
+        scratch[nwaves + wave] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < nwaves; ++w) {
+        sa += scratch[w];
+        sb += scratch[nwaves + w];
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+}
+
 // ----------------------------------------------------------- bead forces ------------
 
 // Forces of Eqs. (10)-(12) on bead t, gathered bond by bond: the stretching energy
@@ -661,7 +685,10 @@ __device__ inline double bead_phi(const Fiber& fib, double dx, double dy) {
 // One block per bead.  With do_velocity: V_i^{n+1} = sum_x phi_i^n (j^{n+1} + f^n / 2) /
 // rho^{n+1} / A_i^n over the bead's support box (Eq. 5, FP64 sums), then the Euler update
 // R_i^{n+1} = R_i^n + V_i^{n+1}.  Always: A_i = sum_x phi_i at the (new) position.
-template <int ST>
+// VB nodes per thread and pass in the velocity phase: their loads are issued together, so
+// a pass waits for memory once (short latency chains for a few beads), at the cost of
+// registers (fewer resident blocks when a batch has thousands of beads).
+template <int ST, int VB>
 __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int win_out,
                                   double* scratch, double* s_R) {
     using Cd = Codec<ST>;
@@ -673,21 +700,25 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     const int nx = a.L.nx, ny = a.L.ny;
     const bool per = a.L.periodic != 0;
     double Rx = bs->R[b][0], Ry = bs->R[b][1];
+    // A_i^n and the support window with the position, so the three loads overlap
+    const double A_old = do_velocity ? bs->A[b] : 0.0;
+    int wraw[4] = {1, 0, 1, 0};
+    if (do_velocity)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wraw[q] = bs->win[a.parity][q];
 
     if (do_velocity) {
         int i0, w, j0, j1;
         bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
         const int rows = j1 - j0 + 1;
         const int total = (rows > 0 && w > 0) ? rows * w : 0;
-        const Window win = decode_window(bs->win[a.parity], nx, ny, per, fib.rect_wmax,
-                                         fib.rect_hmax);
+        const Window win = decode_window(wraw, nx, ny, per, fib.rect_wmax, fib.rect_hmax);
         const int wx0 = win.x0, wy0 = win.y0, ww = win.w, wh = win.h;
         const T* rf = (const T*)fib.rect_f;
         const S* cur = (const S*)a.dst;
         double sx = 0.0, sy = 0.0;
-        // kVelBatch nodes per thread and pass: their loads are issued together, so a pass
-        // waits for memory once; the sums still run over t = tid, tid + blockDim.x, ...
-        constexpr int kVelBatch = 4;
+        // the sums still run over t = tid, tid + blockDim.x, ... for every VB
+        constexpr int kVelBatch = VB;
         const int nt = (int)blockDim.x;
         for (int t0 = tid; t0 < total; t0 += kVelBatch * nt) {
             double ph[kVelBatch];
@@ -748,11 +779,9 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
                 sy += ph[u] * ((jy + 0.5 * (double)fw[u][1]) / rho);
             }
         }
-        sx = block_sum(sx, scratch);
-        sy = block_sum(sy, scratch);
+        block_sum2(sx, sy, scratch);
         if (tid == 0) {
-            const double A = bs->A[b];
-            const double Vx = sx / A, Vy = sy / A;
+            const double Vx = sx / A_old, Vy = sy / A_old;
             bs->V[b][0] = Vx;
             bs->V[b][1] = Vy;
             s_R[0] = Rx + Vx;  // forward Euler, dt = 1
@@ -807,22 +836,22 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
 template <int ST>
 __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_velocity,
                                                           int win_out) {
-    __shared__ double scratch[kBeadBlock / 64];
+    __shared__ double scratch[2 * (kBeadBlock / 64)];
     __shared__ double s_R[2];
-    bead_block<ST>(a, blockIdx.x, do_velocity, win_out, scratch, s_R);
+    bead_block<ST, kBeadVelBatch>(a, blockIdx.x, do_velocity, win_out, scratch, s_R);
 }
 
 // Bead kernel over a batch: one block per (simulation, bead) item.
 template <int ST>
 __global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
-    __shared__ double scratch[kBeadBlock / 64];
+    __shared__ double scratch[2 * (kBeadBlock / 64)];
     __shared__ double s_R[2];
     const int item = blockIdx.x;
     if (item >= b.counts[2]) return;
     const int s = item_sim(b.bead_sim, item);
     const int s_off = ((const ConstInt*)b.bead_off)[s];
     const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    bead_block<ST>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
+    bead_block<ST, kBatchBeadVelBatch>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
 }
 
 // Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same

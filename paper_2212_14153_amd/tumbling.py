@@ -101,6 +101,17 @@ def analyse(record, fiber: int = 0, straight_length: float | None = None,
     return out
 
 
+def final_angle_deg(a: dict) -> float:
+    """The director's last orientation in degrees, in (-90, 90] (a stuck angle)."""
+    th = math.degrees(float(a["theta"][-1]))
+    return (th + 90.0) % 180.0 - 90.0
+
+
+def turned_deg(a: dict) -> float:
+    """Signed rotation over the record in degrees (negative: clockwise)."""
+    return math.degrees(float(a["theta"][-1] - a["theta"][0]))
+
+
 def classify(a: dict, gamma: float | None = None) -> str:
     """'stuck', 'jeffery', 's-turn' or 's-coiled' (see the module notes).  The record
     should span at least one expected tumbling period, else a slow turn looks stuck."""

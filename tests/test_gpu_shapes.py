@@ -76,18 +76,13 @@ def runs():
     return out
 
 
-def final_angle_deg(a):
-    th = math.degrees(a["theta"][-1])
-    return (th + 90.0) % 180.0 - 90.0
-
-
 @pytest.mark.parametrize("row", stuck_rows(),
                          ids=lambda r: f"K{r['K']:g}_Re{r['Re']:g}_C{r['C']:g}")
 def test_stuck_angle_and_rotation(runs, row):
     a = runs[(row["K"], row["Re"], row["C"])]
     assert tumbling.classify(a, GAMMA) == "stuck"
-    assert abs(final_angle_deg(a) - row["theta"]) <= 1.5
-    turned = math.degrees(a["theta"][-1] - a["theta"][0])
+    assert abs(tumbling.final_angle_deg(a) - row["theta"]) <= 1.5
+    turned = tumbling.turned_deg(a)
     assert (turned < 0) == (row["sense"] == "cw")
     if row["turned"] is not None:
         assert abs(abs(turned) - row["turned"]) <= 15.0

@@ -121,3 +121,11 @@ def test_shape_diagram_points_have_the_papers_groups(kappa, conf, re):
     assert w.nx == 25 * d and w.eta_ratio == 100 and w.xi / d == 0.125
     R = w.beads()
     assert np.allclose(R[:, 1], w.ny / 2) and R[:, 0].mean() == pytest.approx(w.nx / 2)
+
+
+def test_final_angle_and_rotation():
+    t = np.arange(5.0)
+    th = np.radians([0.0, -60.0, -120.0, -160.0, -160.0])     # clockwise to 20 degrees
+    a = tumbling.analyse(record_from(t, th, 10.0))
+    assert tumbling.final_angle_deg(a) == pytest.approx(20.0)
+    assert tumbling.turned_deg(a) == pytest.approx(-160.0)
