@@ -644,6 +644,7 @@ def main():
         "bead_kernel_ms": round(bead_ms, 5),
         "ms_per_step_instrumented": round(ms_timed_step, 5),
         "copy_probe_gbps": round(copy_gbps, 1),
+        "frac_of_copy_probe": round(achieved / copy_gbps, 4),
         "health_flags": flags, "max_bond_strain": strain,
     }
     if not args.no_cpu_baseline:
