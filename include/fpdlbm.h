@@ -109,9 +109,13 @@ typedef struct fpd_params {
                                g = -N f_ext / (nx ny) keeps the total momentum constant     */
     int32_t  n_chains;      /* fibers: beads c L .. c L + L - 1 form fiber c, L = n_beads /
                                n_chains (<= 1: one fiber); springs and bending act inside a
-                               fiber only, fibers meet through the fluid alone (no
-                               excluded-volume force); the force window then spans the
+                               fiber only, and fibers meet through the fluid (and the
+                               excluded volume below); the force window then spans the
                                whole lattice                                                 */
+    double   ev_k;          /* excluded volume between fibers, which the paper does not
+                               specify (0: none): beads of different fibers closer than d
+                               repel with the force of (ev_k / 2)(d - r)^2 (>= 0)          */
+    double   ev_range;      /* d; <= 0 selects 2 a (contact of the bead surfaces)          */
 } fpd_params;
 
 /* Launch shape of the fused lattice kernel; any field <= 0 keeps the current value. */

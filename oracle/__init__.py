@@ -50,6 +50,7 @@ class _Params(ctypes.Structure):
         ("gx_body", ctypes.c_double), ("gy_body", ctypes.c_double),
         ("phi_static", ctypes.POINTER(ctypes.c_double)),
         ("n_chains", ctypes.c_int),
+        ("ev_k", ctypes.c_double), ("ev_range", ctypes.c_double),
     ]
 
 
@@ -78,6 +79,8 @@ class OracleParams:
     gy_body: float = 0.0
     phi_static: object = None  # None or [ny]: fixed profile phi_s(y) added in Eq. (1)
     n_chains: int = 1          # fibers of n_beads / n_chains consecutive beads each
+    ev_k: float = 0.0          # excluded volume between fibers (0: none)
+    ev_range: float = 0.0      # its range d (<= 0: 2a)
 
     def c(self) -> _Params:
         ps = None
@@ -89,7 +92,7 @@ class OracleParams:
                        self.n_beads, self.radius, self.l0, self.k_s, self.k_b, self.s_e,
                        self.s_eps, self.s_q_fixed, self.clamp_phi, self.periodic_y,
                        self.fx_ext, self.fy_ext, self.gx_body, self.gy_body, ps,
-                       self.n_chains)
+                       self.n_chains, self.ev_k, self.ev_range)
 
     @classmethod
     def from_mapping(cls, m) -> "OracleParams":

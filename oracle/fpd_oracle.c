@@ -51,6 +51,11 @@
  *     evaluated on the current state.
  *   - the sandwich benchmark of Sec. III.A: its solid slabs are a fixed profile
  *     phi_s(y) (Eq. (14)) that enters Eq. (1) next to the beads' sum_i phi_i.
+ *   - several fibers (the outlook of Sec. V): Eqs. (10)-(12) act inside each fiber; the
+ *     paper names no force between fibers, so by default they meet through the fluid
+ *     alone, and an optional excluded volume (a soft pair repulsion between beads of
+ *     different fibers closer than d, 2a by default) keeps them from passing through
+ *     each other.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -78,6 +83,8 @@ typedef struct orc_params {
                                  sum_i phi_i in Eq. (1) (the solid slabs of Eq. (14))      */
     int    n_chains;      /* fibers: beads c*L .. c*L+L-1 form fiber c, L = N / n_chains
                              (<= 1: one fiber)                                             */
+    double ev_k;          /* excluded volume between fibers: pair energy k/2 (d - r)^2     */
+    double ev_range;      /* d (<= 0: 2a); beads of one fiber do not repel                 */
 } orc_params;
 
 /* ---------------------------------------------------------- D2Q9 lattice ---------- */
@@ -176,14 +183,37 @@ static void fiber_forces(const orc_params *p, const double *R, int N, double *F)
     }
 }
 
-/* Forces on every bead: each fiber on its own (no interaction between fibers: the
- * excluded volume the paper leaves unspecified is not modelled), plus the external force
- * F0 of the driven-particle benchmark (Sec. III.B). */
+/* Excluded volume between fibers (the paper names none; off unless ev_k > 0): beads i, j
+ * of different fibers whose centres are r < d apart repel with the force of the pair
+ * energy (k/2)(d - r)^2, k (d - r) along R_i - R_j (minimum image along periodic
+ * directions).  Added to F_i as a sum over j in increasing order. */
+static void excluded_volume(const orc_params *p, const double *R, int L, double *F)
+{
+    const double d = p->ev_range > 0.0 ? p->ev_range : 2.0 * p->radius;
+    for (int i = 0; i < p->n_beads; ++i) {
+        for (int j = 0; j < p->n_beads; ++j) {
+            if (j / L == i / L) continue;          /* same fiber */
+            double dx = R[2 * i] - R[2 * j], dy = R[2 * i + 1] - R[2 * j + 1];
+            dx -= (double)p->nx * floor(dx / (double)p->nx + 0.5);
+            if (p->periodic_y) dy -= (double)p->ny * floor(dy / (double)p->ny + 0.5);
+            const double r = sqrt(dx * dx + dy * dy);
+            if (!(r < d) || r == 0.0) continue;
+            const double s = p->ev_k * (d - r) / r;
+            F[2 * i] += s * dx;
+            F[2 * i + 1] += s * dy;
+        }
+    }
+}
+
+/* Forces on every bead: each fiber on its own, the excluded volume between fibers when
+ * it is switched on, plus the external force F0 of the driven-particle benchmark
+ * (Sec. III.B). */
 void orc_bead_forces(const orc_params *p, const double *R, double *F)
 {
     const int C = p->n_chains > 1 ? p->n_chains : 1;
     const int L = p->n_beads / C;
     for (int c = 0; c < C; ++c) fiber_forces(p, R + 2 * c * L, L, F + 2 * c * L);
+    if (p->ev_k > 0.0 && C > 1) excluded_volume(p, R, L, F);
     for (int b = 0; b < p->n_beads; ++b) {
         F[2 * b] += p->fx_ext;
         F[2 * b + 1] += p->fy_ext;

@@ -44,6 +44,7 @@ class fpd_params(ctypes.Structure):
         ("boundary", ctypes.c_int32),
         ("f_ext", ctypes.c_double * 2), ("g_body", ctypes.c_double * 2),
         ("n_chains", ctypes.c_int32),
+        ("ev_k", ctypes.c_double), ("ev_range", ctypes.c_double),
     ]
 
 

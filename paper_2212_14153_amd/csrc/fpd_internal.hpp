@@ -76,6 +76,7 @@ struct Fiber {
     int rect_wmax, rect_hmax; // reserved window
     double l0, ks_l02, kb;    // spring rest length, k_s / l0^2, k_b
     double fext[2];           // external force on every bead
+    double ev_k, ev_d;        // excluded volume between fibers: strength (0: off), range
 };
 
 struct StepArgs {

@@ -128,6 +128,28 @@ __device__ inline void bead_force(const Bonds& B, int L, int t, double ks_l02, d
     if (tc >= 2) add_proj(B, t - 1, t - 2, kb, F);          // pair (t-2, t-1): + k_b b_{t-2}
 }
 
+// Excluded volume between fibers (no force the paper names; off unless ev_k > 0): bead t
+// is pushed away from every bead j of another fiber closer than ev_d with the force of the
+// pair energy (k/2)(d - r)^2, summed over j in increasing order (minimum image along the
+// periodic directions; the positions are those of the step's start).
+__device__ inline void ev_force(const Fiber& fib, int nx, int ny, bool per, int t,
+                                double F[2]) {
+    if (!(fib.ev_k > 0.0)) return;
+    const int L = fib.chain_len, ct = t / L;
+    const double Rx = fib.bs->R[t][0], Ry = fib.bs->R[t][1];
+    for (int j = 0; j < fib.n; ++j) {
+        if (j / L == ct) continue;
+        double dx = Rx - fib.bs->R[j][0], dy = Ry - fib.bs->R[j][1];
+        dx = min_image(dx, nx);
+        dy = y_image(dy, ny, per);
+        const double r = sqrt(dx * dx + dy * dy);
+        if (!(r < fib.ev_d) || r == 0.0) continue;
+        const double s = fib.ev_k * (fib.ev_d - r) / r;
+        F[0] += s * dx;
+        F[1] += s * dy;
+    }
+}
+
 // Window slot (raw bounds) -> x0 (mod nx), width, y0, height; clamped to the reserved
 // window (a clamp means the fiber outgrew it: FPD_HEALTH_SUPPORT is raised by block 0).
 struct Window {
@@ -304,6 +326,7 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
             const int b = sIdx[i];
             double F[2];
             bead_force(B, fib.chain_len, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+            ev_force(fib, nx, ny, per, b, F);
             const double A = bs->A[b];
             const double C0 = F[0] / A, C1 = F[1] / A;
             sC[i][0] = C0;
@@ -864,6 +887,7 @@ __global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
         bead_force(B, fib.chain_len, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+        ev_force(fib, a.L.nx, a.L.ny, a.L.periodic != 0, t, F);
         bs->F[t][0] = F[0];
         bs->F[t][1] = F[1];
         bs->C[t][0] = F[0] / bs->A[t];
@@ -1214,6 +1238,7 @@ __global__ void __launch_bounds__(kBeadThreads) batch_forces_kernel(BatchArgs b)
     for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
         double F[2];
         bead_force(B, fib.chain_len, t, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
+        ev_force(fib, a.L.nx, a.L.ny, a.L.periodic != 0, t, F);
         own_bead(fib, B, t, F, F[0] / bs->A[t], F[1] / bs->A[t]);
     }
     if (a.rec) record_ends(a);  // positions of the step's start, as for one simulation

@@ -162,6 +162,8 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.kb = s->p.k_b;
     f.fext[0] = s->p.f_ext[0];
     f.fext[1] = s->p.f_ext[1];
+    f.ev_k = chains_of(&s->p) > 1 ? s->p.ev_k : 0.0;  // one fiber: nothing to exclude
+    f.ev_d = s->p.ev_range > 0.0 ? s->p.ev_range : 2.0 * s->p.radius;
     const fpd_launch& c = s->launch;
     a.rows_per_block = c.block_y * c.rows_per_thread;
     const int tw = c.block_x * nodes_per_lane(s->p.storage);
@@ -199,6 +201,8 @@ int validate(const fpd_params* p) {
     if (!isfinite(p->f_ext[0]) || !isfinite(p->f_ext[1]) || !isfinite(p->g_body[0]) ||
         !isfinite(p->g_body[1]))
         return fail(FPD_EINVAL, "f_ext and g_body must be finite");
+    if (!(p->ev_k >= 0.0) || !isfinite(p->ev_k) || !isfinite(p->ev_range))
+        return fail(FPD_EINVAL, "ev_k must be finite and >= 0, ev_range finite");
     if (p->n_beads > 0) {
         if (!(p->radius > 0.0) || !(p->xi > 0.0) || !(p->l0 > 0.0))
             return fail(FPD_EINVAL, "radius, xi and l0 must be > 0");
@@ -935,7 +939,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 
 // ---------------------------------------------------------------- checkpoint -------
 
-static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '5'};
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '6'};
 
 int fpd_save(fpd_sim* s, const char* path) {
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");

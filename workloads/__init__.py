@@ -61,6 +61,8 @@ class Workload:
     g_body: tuple = (0.0, 0.0)           # uniform body force density on every node
     n_chains: int = 1                    # fibers of n_beads / n_chains consecutive beads
     centres: tuple = ()                  # several fibers: ((cx, cy, theta), ...)
+    ev_k: float = 0.0                    # excluded volume between fibers (0: none)
+    ev_range: float = 0.0                # its range (<= 0: 2a)
 
     def params(self) -> dict:
         """Lattice parameters as a plain mapping (both sides read what they need; the
