@@ -42,6 +42,10 @@ struct BeadState {
     unsigned int health;                 // FPD_HEALTH_* bits, sticky (atomic or)
     unsigned int reserved;
     unsigned long long max_strain_bits;  // bits of the largest |L - l0| / l0 (atomic max)
+    // excluded volume between fibers: strength (0: off) and range (set with the fiber),
+    // and each bead's share of it at the step's start (ev_kernel, read by the tiles)
+    double ev_k, ev_d;
+    double Fev[kMaxBeads][2];
 };
 
 // Value (k, y, x) of a population buffer sits at y * stride + k * plane + x.  The nine
@@ -76,7 +80,6 @@ struct Fiber {
     int rect_wmax, rect_hmax; // reserved window
     double l0, ks_l02, kb;    // spring rest length, k_s / l0^2, k_b
     double fext[2];           // external force on every bead
-    double ev_k, ev_d;        // excluded volume between fibers: strength (0: off), range
 };
 
 struct StepArgs {
@@ -94,7 +97,6 @@ struct StepArgs {
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
     int rows_per_block;       // block_y * rows_per_thread
     int xcd_remap;
-    int forces_ready;         // 1: F^n and F/A were computed by a forces kernel this step
 };
 
 // Fiber-ends recorder (device memory): at the start of every step tile 0 counts the step
@@ -137,6 +139,9 @@ hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
                        hipStream_t st);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);
+// excluded-volume forces of the step's start into BeadState::Fev (before the lattice step;
+// needed only when BeadState::ev_k > 0)
+hipError_t launch_ev(const StepArgs& a, hipStream_t st);
 // fiber-ends record of the step about to run (nothing unless a recording runs)
 hipError_t launch_record(const StepArgs& a, hipStream_t st);
 // any_periodic: some simulation of the batch has no walls (the kernel then reads the

@@ -134,17 +134,19 @@ __device__ inline void bead_force(const Bonds& B, int L, int t, double ks_l02, d
 // periodic directions; the positions are those of the step's start).
 __device__ inline void ev_force(const Fiber& fib, int nx, int ny, bool per, int t,
                                 double F[2]) {
-    if (!(fib.ev_k > 0.0)) return;
+    const BeadState* bs = fib.bs;
+    const double k = bs->ev_k, d = bs->ev_d;
+    if (!(k > 0.0)) return;
     const int L = fib.chain_len, ct = t / L;
-    const double Rx = fib.bs->R[t][0], Ry = fib.bs->R[t][1];
+    const double Rx = bs->R[t][0], Ry = bs->R[t][1];
     for (int j = 0; j < fib.n; ++j) {
         if (j / L == ct) continue;
-        double dx = Rx - fib.bs->R[j][0], dy = Ry - fib.bs->R[j][1];
+        double dx = Rx - bs->R[j][0], dy = Ry - bs->R[j][1];
         dx = min_image(dx, nx);
         dy = y_image(dy, ny, per);
         const double r = sqrt(dx * dx + dy * dy);
-        if (!(r < fib.ev_d) || r == 0.0) continue;
-        const double s = fib.ev_k * (fib.ev_d - r) / r;
+        if (!(r < d) || r == 0.0) continue;
+        const double s = k * (d - r) / r;
         F[0] += s * dx;
         F[1] += s * dy;
     }
@@ -326,7 +328,10 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
             const int b = sIdx[i];
             double F[2];
             bead_force(B, fib.chain_len, b, fib.ks_l02, fib.l0, fib.kb, fib.fext, F);
-            ev_force(fib, nx, ny, per, b, F);
+            if (bs->ev_k > 0.0) {  // the excluded volume, summed by ev_kernel this step
+                F[0] += bs->Fev[b][0];
+                F[1] += bs->Fev[b][1];
+            }
             const double A = bs->A[b];
             const double C0 = F[0] / A, C1 = F[1] / A;
             sC[i][0] = C0;
@@ -408,7 +413,9 @@ __device__ inline bool periodic_of(int bc, const StepArgs& a) {
     return bc == kAnyBoundary ? a.L.periodic != 0 : bc == kPeriodic;
 }
 
-template <int ST, int SPT, int BC>
+// FR: the forces F^n and F/A of this step come from a forces kernel (a batch); else the
+// tiles near the fiber compute them from the positions.
+template <int ST, int SPT, int BC, bool FR>
 __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int tile,
                                     TileLds& lds) {
     using Cd = Codec<ST>;
@@ -463,7 +470,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
         if (fiber_tile)
             nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
                               a.rows_per_block, sR, sC, lds.idx, s_wave, lds.bonds,
-                              a.forces_ready != 0);
+                              FR);
     }
 
     // a tile inside the window that no bead's support reaches is fluid only: no node of
@@ -495,7 +502,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
 
 // lattice_tile for 2-byte storage: a tile is G * block_x nodes wide and each lane updates
 // G neighbouring nodes with the same per-node arithmetic as the one-node path.
-template <int ST, int SPT, int BC>
+template <int ST, int SPT, int BC, bool FR>
 __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, int tile,
                                           TileLds& lds) {
     using Cd = Codec<ST>;
@@ -549,7 +556,7 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
         if (fiber_tile)
             nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
                               a.rows_per_block, lds.R, lds.C, lds.idx, lds.wave, lds.bonds,
-                              a.forces_ready != 0);
+                              FR);
     }
 
     // a tile inside the window that no bead's support reaches is fluid only: no node of
@@ -617,12 +624,12 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
     }
 }
 
-template <int ST, int SPT, int BC>
+template <int ST, int SPT, int BC, bool FR>
 __device__ inline void tile_any(const StepArgs& a, const Window& win, int tile, TileLds& lds) {
     if constexpr (nodes_per_lane(ST) > 1)
-        lattice_tile_group<ST, SPT, BC>(a, win, tile, lds);
+        lattice_tile_group<ST, SPT, BC, FR>(a, win, tile, lds);
     else
-        lattice_tile<ST, SPT, BC>(a, win, tile, lds);
+        lattice_tile<ST, SPT, BC, FR>(a, win, tile, lds);
 }
 
 // Called by every thread of one block ahead of the step's lattice kernel, and only while a
@@ -661,7 +668,7 @@ template <int ST, int SPT, int BC>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ TileLds lds;
     const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    tile_any<ST, SPT, BC>(a, tile_window(a), tile, lds);
+    tile_any<ST, SPT, BC, false>(a, tile_window(a), tile, lds);
 }
 
 // The argument table is read-only while a batch kernel runs: viewing it in the constant
@@ -693,7 +700,7 @@ __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     const int s = item_sim(b.tile_sim, item);
     const int s_off = ((const ConstInt*)b.tile_off)[s];
     const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    tile_any<ST, SPT, BC>(a, tile_window(a), item - s_off, lds);
+    tile_any<ST, SPT, BC, true>(a, tile_window(a), item - s_off, lds);
 }
 
 // ----------------------------------------------------------------- bead kernel -----
@@ -879,6 +886,17 @@ __global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
 
 // Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same
 // values for the beads near its tiles).
+// Excluded-volume forces of every bead at the step's start (one block).
+__global__ void __launch_bounds__(kBeadThreads) ev_kernel(StepArgs a) {
+    const Fiber& fib = a.fib;
+    for (int t = threadIdx.x; t < fib.n; t += blockDim.x) {
+        double F[2] = {0.0, 0.0};
+        ev_force(fib, a.L.nx, a.L.ny, a.L.periodic != 0, t, F);
+        fib.bs->Fev[t][0] = F[0];
+        fib.bs->Fev[t][1] = F[1];
+    }
+}
+
 __global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
     __shared__ Bonds B;
     const Fiber& fib = a.fib;
@@ -1288,6 +1306,12 @@ hipError_t launch_batch_step(int storage, const BatchArgs& b, dim3 block, int sp
 hipError_t launch_record(const StepArgs& a, hipStream_t st) {
     if (!a.rec || a.fib.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(record_kernel, dim3(1), dim3(kBeadThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ev(const StepArgs& a, hipStream_t st) {
+    if (a.fib.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ev_kernel, dim3(1), dim3(kBeadThreads), 0, st, a);
     return hipGetLastError();
 }
 

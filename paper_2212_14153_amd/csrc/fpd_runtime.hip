@@ -162,8 +162,6 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     f.kb = s->p.k_b;
     f.fext[0] = s->p.f_ext[0];
     f.fext[1] = s->p.f_ext[1];
-    f.ev_k = chains_of(&s->p) > 1 ? s->p.ev_k : 0.0;  // one fiber: nothing to exclude
-    f.ev_d = s->p.ev_range > 0.0 ? s->p.ev_range : 2.0 * s->p.radius;
     const fpd_launch& c = s->launch;
     a.rows_per_block = c.block_y * c.rows_per_thread;
     const int tw = c.block_x * nodes_per_lane(s->p.storage);
@@ -226,11 +224,18 @@ void drop_graphs(fpd_sim* s) {
     s->graph_chunk = 0;
 }
 
+// The excluded volume between fibers is switched on (then a small kernel sums it before
+// every lattice step).
+bool has_ev(const fpd_sim* s) {
+    return s->fiber && chains_of(&s->p) > 1 && s->p.ev_k > 0.0;
+}
+
 // One step from buffer `from` (launches only).
 int enqueue_step(fpd_sim* s, int from) {
     const StepArgs a = make_args(s, from);
     const dim3 block(s->launch.block_x, s->launch.block_y);
     HIP_TRY(launch_record(a, s->stream));
+    if (has_ev(s)) HIP_TRY(launch_ev(a, s->stream));
     HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
     if (a.fib.n > 0) HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - from, s->stream));
     return FPD_OK;
@@ -273,6 +278,7 @@ int step_timed(fpd_sim* s, int64_t n) {
             const dim3 block(s->launch.block_x, s->launch.block_y);
             hipEvent_t* ev = &s->events[(size_t)i * per];
             HIP_TRY(launch_record(a, s->stream));
+            if (has_ev(s)) HIP_TRY(launch_ev(a, s->stream));
             HIP_TRY(hipEventRecord(ev[0], s->stream));
             HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream));
             HIP_TRY(hipEventRecord(ev[1], s->stream));
@@ -530,6 +536,8 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
         h.V[i][0] = h.V[i][1] = 0.0;
     }
     memset(h.occ, 0, sizeof h.occ);  // empty occupancy; the bead kernel fills slot `cur`
+    h.ev_k = chains_of(&s->p) > 1 ? s->p.ev_k : 0.0;  // one fiber: nothing to exclude
+    h.ev_d = s->p.ev_range > 0.0 ? s->p.ev_range : 2.0 * s->p.radius;
     for (int k = 0; k < 2; ++k) {  // empty windows; the bead kernel fills slot `cur`
         h.win[k][0] = 0x7fffffff;
         h.win[k][1] = -0x7fffffff;
@@ -1089,8 +1097,6 @@ int batch_rebuild(fpd_batch* b) {
         fpd_sim* s = e.sim;
         b->h_args[2 * r] = make_args(s, s->cur);
         b->h_args[2 * r + 1] = make_args(s, 1 - s->cur);
-        b->h_args[2 * r].forces_ready = 1;      // the batch's forces kernel runs first
-        b->h_args[2 * r + 1].forces_ready = 1;
         tiles += b->h_args[2 * r].n_tiles;
         beads += b->h_args[2 * r].fib.n;
         b->h_tile_off[r + 1] = tiles;
