@@ -604,7 +604,8 @@ def main():
     mlups = nodes / (ms_step * 1e-3) / 1e6
     log(f"graph replay: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS (wall {wall:.2f} s)")
 
-    # same simulation, every kernel bracketed by events on its stream
+    # same simulation, the lattice and bead kernels launched one by one with start and
+    # stop events stamped by each dispatch on the simulation's stream
     sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
     sim.reset_kernel_times()
     e2 = torch.cuda.Event(enable_timing=True)

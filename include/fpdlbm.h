@@ -71,7 +71,7 @@ extern "C" {
 /* flags */
 #define FPD_FLAG_CLAMP_PHI     0x1u  /* clamp sum_i phi_i to 1 in Eq. (1)                 */
 #define FPD_FLAG_NO_GRAPH      0x2u  /* launch every kernel directly (no graph replay)    */
-#define FPD_FLAG_TIME_KERNELS  0x4u  /* time every kernel with events (implies NO_GRAPH)  */
+#define FPD_FLAG_TIME_KERNELS  0x4u  /* time the lattice and bead kernels (implies NO_GRAPH) */
 
 /* health bits, sticky until fpd_clear_health */
 #define FPD_HEALTH_NAN      0x1u   /* NaN or Inf in a bead position or velocity           */
@@ -250,8 +250,10 @@ int fpd_set_launch(fpd_sim *s, const fpd_launch *cfg);
 int fpd_set_flags(fpd_sim *s, uint32_t flags);
 int fpd_get_launch(fpd_sim *s, fpd_launch *cfg);
 
-/* Kernel timing with FPD_FLAG_TIME_KERNELS: summed event time (ms) and launch count of the
- * fused lattice kernel and of the bead kernel since the last reset. */
+/* Kernel timing with FPD_FLAG_TIME_KERNELS: summed duration (ms) and launch count of the
+ * fused lattice kernel and of the bead kernel since the last reset.  Each duration is that
+ * of the dispatch itself: its events are stamped by the launch (hipExtLaunchKernel), not
+ * recorded as separate queue entries around it. */
 int fpd_kernel_times(fpd_sim *s, double *ms_lattice, int64_t *n_lattice, double *ms_bead,
                      int64_t *n_bead);
 int fpd_reset_kernel_times(fpd_sim *s);

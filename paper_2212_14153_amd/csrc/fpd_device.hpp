@@ -166,31 +166,45 @@ __device__ inline double y_image(double dy, int ny, bool per) {
     return per ? min_image(dy, ny) : dy;
 }
 
-// phi of Eq. (2): 1/2 (tanh((a - r)/xi) + 1).
+// phi of Eq. (2), 1/2 (tanh((a - r)/xi) + 1), in the equal logistic form
+// 1 / (1 + exp(2 (r - a)/xi)): one exponential and one division instead of a tanh (whose
+// FP64 library form is a chain of some 200 dependent double-double operations), and no
+// cancellation against 1 in the tail far from the bead.
 __device__ inline double phi_f64(double r, double a, double xi) {
-    return 0.5 * (tanh((a - r) / xi) + 1.0);
+    return 1.0 / (1.0 + exp(2.0 * (r - a) / xi));
 }
 __device__ inline float phi_f32(float r, float a, float inv_xi) {
-    return 0.5f * (tanhf((a - r) * inv_xi) + 1.0f);
+    return 1.0f / (1.0f + expf(2.0f * (r - a) * inv_xi));
 }
 
 template <typename T> struct PhiEval;
+// dist2 is the one expression of the squared distance: the cutoff test and phi
+// itself always see the same value.
+__device__ inline double dist2(double dx, double dy) { return dx * dx + dy * dy; }
+
 template <> struct PhiEval<double> {
-    __device__ static inline double eval(double dx, double dy, double rc2, double a,
-                                         double xi, double) {
-        const double r2 = dx * dx + dy * dy;
-        if (r2 >= rc2) return 0.0;
+    // phi at squared distance r2 < rc2
+    __device__ static inline double of_r2(double r2, double a, double xi, double) {
         return phi_f64(sqrt(r2), a, xi);
+    }
+    __device__ static inline double eval(double dx, double dy, double rc2, double a,
+                                         double xi, double inv_xi) {
+        const double r2 = dist2(dx, dy);
+        if (r2 >= rc2) return 0.0;
+        return of_r2(r2, a, xi, inv_xi);
     }
 };
 // The cutoff test stays in FP64 in both variants: it is the same predicate as the
 // support boxes, so whether a node sees a bead never depends on the tiling.
 template <> struct PhiEval<float> {
-    __device__ static inline float eval(double dx, double dy, double rc2, double a, double,
-                                        double inv_xi) {
-        const double r2 = dx * dx + dy * dy;
-        if (r2 >= rc2) return 0.0f;
+    __device__ static inline float of_r2(double r2, double a, double, double inv_xi) {
         return phi_f32(sqrtf((float)r2), (float)a, (float)inv_xi);
+    }
+    __device__ static inline float eval(double dx, double dy, double rc2, double a, double xi,
+                                        double inv_xi) {
+        const double r2 = dist2(dx, dy);
+        if (r2 >= rc2) return 0.0f;
+        return of_r2(r2, a, xi, inv_xi);
     }
 };
 

@@ -133,11 +133,13 @@ struct NodeBox {
     bool wrap_x, wrap_y;
 };
 
-// Kernel launchers (fpd_kernels.hip).
+// Kernel launchers (fpd_kernels.hip).  Given events t0 and t1, the lattice and bead
+// launches stamp them with the dispatch's own start and end (hipExtLaunchKernel); they are
+// then not for stream capture.
 hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);
 // excluded-volume forces of the step's start into BeadState::Fev (before the lattice step;
 // needed only when BeadState::ev_k > 0)

@@ -225,8 +225,9 @@ __device__ inline bool occ_hit(const Fiber& fib, int slot, int x0, int w, int y0
 
 // Mark the cells of the unwrapped node range [lo, hi] x [jlo, jhi] (x wraps; y wraps in a
 // periodic box, else it is clipped to the channel).
-__device__ inline void occ_mark(const Fiber& fib, int slot, long long lo, long long hi,
-                                long long jlo, long long jhi, int nx, int ny, bool per) {
+// (Positions pass bead_sane, so every index here fits an int.)
+__device__ inline void occ_mark(const Fiber& fib, int slot, int lo, int hi, int jlo, int jhi,
+                                int nx, int ny, bool per) {
     unsigned* m = fib.bs->occ[slot];
     const int s = fib.occ_shift;
     if (!per) {
@@ -241,11 +242,11 @@ __device__ inline void occ_mark(const Fiber& fib, int slot, long long lo, long l
         jlo = 0;
         jhi = ny - 1;
     }
-    for (long long y = jlo; y <= jhi;) {
-        const int yw = (int)(per ? ((y % ny) + ny) % ny : y);
+    for (int y = jlo; y <= jhi;) {
+        const int yw = per ? imod(y, ny) : y;
         const int r = yw >> s;
-        for (long long x = lo; x <= hi;) {
-            const int xw = (int)(((x % nx) + nx) % nx);
+        for (int x = lo; x <= hi;) {
+            const int xw = imod(x, nx);
             const int c = xw >> s;
             const int cell = r * fib.occ_nx + c;
             atomicOr(&m[cell >> 5], 1u << (cell & 31));
@@ -358,9 +359,6 @@ struct TileLds {
     int wave[16];
 };
 
-// One tile (block_x nodes on rows_per_block rows) of one simulation.
-// Must be reached by every thread of the block (it synchronises when the tile meets the
-// fiber).  The tile numbered 0 also resets the window slot the bead kernel fills next.
 // The fiber's support window for this step (empty without a fiber).
 __device__ inline Window tile_window(const StepArgs& a) {
     if (a.fib.n <= 0) return Window{0, 0, 0, 0, false};
@@ -371,7 +369,8 @@ __device__ inline Window tile_window(const StepArgs& a) {
 
 // Step (1) at one node (x, y) of a fiber tile: phi_i^n (Eq. 2), eta^n (Eq. 1, with a
 // fixed profile phi_s(y) if one is set) and the relaxation rates, f^n (Eq. 4, plus the
-// uniform body force), recorded in the force window.  Fx, Fy are overwritten; s_nu, s_q keep the fluid values where sum phi = 0.
+// uniform body force), recorded in the force window.  Fx, Fy are overwritten; s_nu and
+// s_q keep the fluid values where sum phi = 0.
 template <typename T>
 __device__ inline void fiber_node(const StepArgs& a, bool per, const double (*sR)[2],
                                   const double (*sC)[2], int nb, int x, int y, int wx0,
@@ -413,6 +412,9 @@ __device__ inline bool periodic_of(int bc, const StepArgs& a) {
     return bc == kAnyBoundary ? a.L.periodic != 0 : bc == kPeriodic;
 }
 
+// One tile (block_x nodes on rows_per_block rows) of one simulation.
+// Must be reached by every thread of the block (it synchronises when the tile meets the
+// fiber).  The tile numbered 0 also resets the window slot the bead kernel fills next.
 // FR: the forces F^n and F/A of this step come from a forces kernel (a batch); else the
 // tiles near the fiber compute them from the positions.
 template <int ST, int SPT, int BC, bool FR>
@@ -705,11 +707,33 @@ __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
 
 // ----------------------------------------------------------------- bead kernel -----
 
-// phi of one bead at a node in the arithmetic of the storage (FP64 for FPD_F64, FP32
-// otherwise); the cutoff test is the FP64 predicate shared with the support boxes.
+// phi of one bead in the arithmetic of the storage (FP64 for FPD_F64, FP32 otherwise) at
+// squared distance r2 = dist2(dx, dy) < rc2 (the FP64 cutoff test of PhiEval, shared with
+// the support boxes).
 template <typename T>
-__device__ inline double bead_phi(const Fiber& fib, double dx, double dy) {
-    return (double)PhiEval<T>::eval(dx, dy, fib.rc2, fib.a, fib.xi, fib.inv_xi);
+__device__ inline double bead_phi_r2(const Fiber& fib, double r2) {
+    return (double)PhiEval<T>::of_r2(r2, fib.a, fib.xi, fib.inv_xi);
+}
+
+// Squared distance of node t of a bead's support box (columns i0 .. i0 + w - 1, rows from
+// j0, both wrapped) from (Rx, Ry), and whether it is inside the cutoff; t >= total: out.
+__device__ inline void box_node(const Fiber& fib, int t, int total, int i0, int w, int j0,
+                                int nx, int ny, bool per, double Rx, double Ry, int& x,
+                                int& y, double& r2, bool& in) {
+    x = i0;
+    y = j0;
+    r2 = 0.0;
+    in = false;
+    if (t < total) {
+        y = j0 + t / w;
+        if (y >= ny) y -= ny;  // periodic box: rows wrap
+        x = i0 + t % w;
+        if (x >= nx) x -= nx;
+        const double dx = min_image((double)x + 0.5 - Rx, nx);
+        const double dy = y_image((double)y + 0.5 - Ry, ny, per);
+        r2 = dist2(dx, dy);
+        in = r2 < fib.rc2;  // the cutoff test of PhiEval
+    }
 }
 
 // One block per bead.  With do_velocity: V_i^{n+1} = sum_x phi_i^n (j^{n+1} + f^n / 2) /
@@ -717,7 +741,9 @@ __device__ inline double bead_phi(const Fiber& fib, double dx, double dy) {
 // R_i^{n+1} = R_i^n + V_i^{n+1}.  Always: A_i = sum_x phi_i at the (new) position.
 // VB nodes per thread and pass in the velocity phase: their loads are issued together, so
 // a pass waits for memory once (short latency chains for a few beads), at the cost of
-// registers (fewer resident blocks when a batch has thousands of beads).
+// registers (fewer resident blocks when a batch has thousands of beads).  The loads depend
+// only on the cutoff test, so phi is evaluated while they are in flight.  Per-thread sums
+// still run over t = tid, tid + blockDim.x, ... in increasing t, whatever VB.
 template <int ST, int VB>
 __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int win_out,
                                   double* scratch, double* s_R) {
@@ -737,6 +763,7 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
 #pragma unroll
         for (int q = 0; q < 4; ++q) wraw[q] = bs->win[a.parity][q];
 
+    double Vx = 0.0, Vy = 0.0;  // valid in thread 0
     if (do_velocity) {
         int i0, w, j0, j1;
         bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
@@ -747,37 +774,22 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
         const T* rf = (const T*)fib.rect_f;
         const S* cur = (const S*)a.dst;
         double sx = 0.0, sy = 0.0;
-        // the sums still run over t = tid, tid + blockDim.x, ... for every VB
-        constexpr int kVelBatch = VB;
         const int nt = (int)blockDim.x;
-        for (int t0 = tid; t0 < total; t0 += kVelBatch * nt) {
-            double ph[kVelBatch];
-            int ii[kVelBatch], jj[kVelBatch];
-            T g[kVelBatch][9];
-            T fw[kVelBatch][2];
+        for (int t0 = tid; t0 < total; t0 += VB * nt) {
+            double ph[VB], r2[VB];
+            bool in[VB];
+            int ii[VB], jj[VB];
+            T g[VB][9];
+            T fw[VB][2];
 #pragma unroll
-            for (int u = 0; u < kVelBatch; ++u) {
-                const int t = t0 + u * nt;
-                ph[u] = 0.0;
-                ii[u] = i0;
-                jj[u] = j0;
-                if (t < total) {
-                    int yy = j0 + t / w;
-                    if (yy >= ny) yy -= ny;  // periodic box: rows wrap
-                    jj[u] = yy;
-                    int x = i0 + t % w;
-                    if (x >= nx) x -= nx;
-                    ii[u] = x;
-                    const double dx = min_image((double)x + 0.5 - Rx, nx);
-                    const double dy = y_image((double)yy + 0.5 - Ry, ny, per);
-                    ph[u] = bead_phi<T>(fib, dx, dy);
-                }
-            }
+            for (int u = 0; u < VB; ++u)
+                box_node(fib, t0 + u * nt, total, i0, w, j0, nx, ny, per, Rx, Ry, ii[u], jj[u],
+                         r2[u], in[u]);
 #pragma unroll
-            for (int u = 0; u < kVelBatch; ++u) {
+            for (int u = 0; u < VB; ++u) {
                 fw[u][0] = (T)a.gx;  // outside the window f^n is the body force alone
                 fw[u][1] = (T)a.gy;
-                if (ph[u] != 0.0) {
+                if (in[u]) {
                     pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii[u], jj[u], per, (T)a.u6,
                              g[u]);
                     // f^n at this node from the window the lattice kernel filled (the window
@@ -793,7 +805,9 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kVelBatch; ++u) {
+            for (int u = 0; u < VB; ++u) ph[u] = in[u] ? bead_phi_r2<T>(fib, r2[u]) : 0.0;
+#pragma unroll
+            for (int u = 0; u < VB; ++u) {
                 if (ph[u] == 0.0) continue;
                 double drho = 0.0;
 #pragma unroll
@@ -811,7 +825,8 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
         }
         block_sum2(sx, sy, scratch);
         if (tid == 0) {
-            const double Vx = sx / A_old, Vy = sy / A_old;
+            Vx = sx / A_old;
+            Vy = sy / A_old;
             bs->V[b][0] = Vx;
             bs->V[b][1] = Vy;
             s_R[0] = Rx + Vx;  // forward Euler, dt = 1
@@ -830,13 +845,11 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     const int total = (rows > 0 && w > 0) ? rows * w : 0;
     double s = 0.0;
     for (int t = tid; t < total; t += blockDim.x) {
-        int jj = j0 + t / w;
-        if (jj >= ny) jj -= ny;
-        int ii = i0 + t % w;
-        if (ii >= nx) ii -= nx;
-        const double dx = min_image((double)ii + 0.5 - Rx, nx);
-        const double dy = y_image((double)jj + 0.5 - Ry, ny, per);
-        s += bead_phi<T>(fib, dx, dy);
+        int x, y;
+        double r2;
+        bool in;
+        box_node(fib, t, total, i0, w, j0, nx, ny, per, Rx, Ry, x, y, r2, in);
+        if (in) s += bead_phi_r2<T>(fib, r2);
     }
     s = block_sum(s, scratch);
     if (tid == 0) {
@@ -852,7 +865,10 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
             atomicMax(&nw[3], jhi);
             occ_mark(fib, win_out, lo, hi, jlo, jhi, nx, ny, per);
         }
-        const double Vx = bs->V[b][0], Vy = bs->V[b][1];
+        if (!do_velocity) {
+            Vx = bs->V[b][0];
+            Vy = bs->V[b][1];
+        }
         unsigned h = 0u;
         if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) || !isfinite(s))
             h |= FPD_HEALTH_NAN;
@@ -884,8 +900,6 @@ __global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
     bead_block<ST, kBatchBeadVelBatch>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
 }
 
-// Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same
-// values for the beads near its tiles).
 // Excluded-volume forces of every bead at the step's start (one block).
 __global__ void __launch_bounds__(kBeadThreads) ev_kernel(StepArgs a) {
     const Fiber& fib = a.fib;
@@ -897,6 +911,8 @@ __global__ void __launch_bounds__(kBeadThreads) ev_kernel(StepArgs a) {
     }
 }
 
+// Forces F^n and C = F / A for every bead (read-back; the lattice kernel computes the same
+// values for the beads near its tiles).
 __global__ void __launch_bounds__(kBeadThreads) forces_kernel(StepArgs a) {
     __shared__ Bonds B;
     const Fiber& fib = a.fib;
@@ -1031,7 +1047,7 @@ __device__ inline void node_fields(const StepArgs& a, int x, int y, double& rho,
     for (int b = 0; b < fib.n; ++b) {
         const double dx = min_image((double)x + 0.5 - fib.bs->R[b][0], nx);
         const double dy = y_image((double)y + 0.5 - fib.bs->R[b][1], ny, per);
-        const double r2 = dx * dx + dy * dy;
+        const double r2 = dist2(dx, dy);
         if (r2 >= fib.rc2) continue;
         const double ph = phi_f64(sqrt(r2), fib.a, fib.xi);
         sphi += ph;
@@ -1093,7 +1109,7 @@ __global__ void box_fields_kernel(StepArgs a, NodeBox B, double* __restrict__ fi
 __device__ inline double phi_at_node(const StepArgs& a, double Rx, double Ry, int x, int y) {
     const double dx = min_image((double)x + 0.5 - Rx, a.L.nx);
     const double dy = y_image((double)y + 0.5 - Ry, a.L.ny, a.L.periodic != 0);
-    const double r2 = dx * dx + dy * dy;
+    const double r2 = dist2(dx, dy);
     if (r2 >= a.fib.rc2) return 0.0;
     return phi_f64(sqrt(r2), a.fib.a, a.fib.xi);
 }
@@ -1197,49 +1213,63 @@ __global__ void copy_kernel(const copy_vec* __restrict__ src, copy_vec* __restri
 
 // -------------------------------------------------------------------- launchers ----
 
-template <int ST>
-static hipError_t launch_step_t(const StepArgs& a, dim3 block, int spt, hipStream_t st) {
-    const dim3 grid(a.n_tiles);
-    if (a.L.periodic) {
-        switch (spt) {
-            case 1: hipLaunchKernelGGL((step_kernel<ST, 1, kPeriodic>), grid, block, 0, st, a); break;
-            case 2: hipLaunchKernelGGL((step_kernel<ST, 2, kPeriodic>), grid, block, 0, st, a); break;
-            case 4: hipLaunchKernelGGL((step_kernel<ST, 4, kPeriodic>), grid, block, 0, st, a); break;
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (spt) {
-            case 1: hipLaunchKernelGGL((step_kernel<ST, 1, kWalls>), grid, block, 0, st, a); break;
-            case 2: hipLaunchKernelGGL((step_kernel<ST, 2, kWalls>), grid, block, 0, st, a); break;
-            case 4: hipLaunchKernelGGL((step_kernel<ST, 4, kWalls>), grid, block, 0, st, a); break;
-            default: return hipErrorInvalidValue;
-        }
-    }
-    return hipGetLastError();
+template <class T>
+struct same_type {
+    using type = T;
+};
+
+// One launch of kernel k; with events, hipExtLaunchKernel stamps them with the dispatch's
+// own start and end, without extra packets in the queue around the kernel.
+template <typename... P>
+static hipError_t launch_k(void (*k)(P...), dim3 grid, dim3 block, hipStream_t st,
+                           hipEvent_t t0, hipEvent_t t1, typename same_type<P>::type... args) {
+    void* argv[] = {(void*)&args...};
+    if (t0 || t1) return hipExtLaunchKernel((const void*)k, grid, block, argv, 0, st, t0, t1, 0);
+    return hipLaunchKernel((const void*)k, grid, block, argv, 0, st);
 }
 
-hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int spt, hipStream_t st) {
+template <int ST, int BC>
+static void (*step_kernel_for(int spt))(StepArgs) {
+    switch (spt) {
+        case 1: return step_kernel<ST, 1, BC>;
+        case 2: return step_kernel<ST, 2, BC>;
+        case 4: return step_kernel<ST, 4, BC>;
+    }
+    return nullptr;
+}
+
+template <int ST>
+static hipError_t launch_step_t(const StepArgs& a, dim3 block, int spt, hipStream_t st,
+                                hipEvent_t t0, hipEvent_t t1) {
+    void (*k)(StepArgs) = a.L.periodic ? step_kernel_for<ST, kPeriodic>(spt)
+                                       : step_kernel_for<ST, kWalls>(spt);
+    if (!k) return hipErrorInvalidValue;
+    return launch_k(k, dim3(a.n_tiles), block, st, t0, t1, a);
+}
+
+hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int spt, hipStream_t st,
+                       hipEvent_t t0, hipEvent_t t1) {
     switch (storage) {
-        case FPD_F64: return launch_step_t<FPD_F64>(a, block, spt, st);
-        case FPD_F32: return launch_step_t<FPD_F32>(a, block, spt, st);
-        case FPD_F16DEV: return launch_step_t<FPD_F16DEV>(a, block, spt, st);
-        case FPD_BF16DEV: return launch_step_t<FPD_BF16DEV>(a, block, spt, st);
+        case FPD_F64: return launch_step_t<FPD_F64>(a, block, spt, st, t0, t1);
+        case FPD_F32: return launch_step_t<FPD_F32>(a, block, spt, st, t0, t1);
+        case FPD_F16DEV: return launch_step_t<FPD_F16DEV>(a, block, spt, st, t0, t1);
+        case FPD_BF16DEV: return launch_step_t<FPD_BF16DEV>(a, block, spt, st, t0, t1);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
-                       hipStream_t st) {
+                       hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     if (a.fib.n <= 0) return hipSuccess;
-    const dim3 grid(a.fib.n), block(kBeadBlock);
+    void (*k)(StepArgs, int, int) = nullptr;
     switch (storage) {
-        case FPD_F64: hipLaunchKernelGGL((bead_kernel<FPD_F64>), grid, block, 0, st, a, do_velocity, win_out); break;
-        case FPD_F32: hipLaunchKernelGGL((bead_kernel<FPD_F32>), grid, block, 0, st, a, do_velocity, win_out); break;
-        case FPD_F16DEV: hipLaunchKernelGGL((bead_kernel<FPD_F16DEV>), grid, block, 0, st, a, do_velocity, win_out); break;
-        case FPD_BF16DEV: hipLaunchKernelGGL((bead_kernel<FPD_BF16DEV>), grid, block, 0, st, a, do_velocity, win_out); break;
+        case FPD_F64: k = bead_kernel<FPD_F64>; break;
+        case FPD_F32: k = bead_kernel<FPD_F32>; break;
+        case FPD_F16DEV: k = bead_kernel<FPD_F16DEV>; break;
+        case FPD_BF16DEV: k = bead_kernel<FPD_BF16DEV>; break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return launch_k(k, dim3(a.fib.n), dim3(kBeadBlock), st, t0, t1, a, do_velocity, win_out);
 }
 
 // Forces F^n, F/A and bond strains of every simulation of a batch, one block per
