@@ -67,16 +67,17 @@ def kernel_hash() -> str:
     return kernel_source_hash()
 
 
-def measured_traffic(storage, nodes):
+def measured_traffic(storage, nodes, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source and this storage; else None."""
+    on the current kernel source, this storage and this workload; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     ent = rec.get("entries", {}).get(storage)
-    if not ent or rec.get("kernel_sha") != kernel_hash() or ent.get("nodes") != nodes:
+    if (not ent or rec.get("kernel_sha") != kernel_hash() or ent.get("nodes") != nodes
+            or ent.get("workload") != workload):
         return None
     return ent.get("bytes_per_launch")
 
@@ -628,7 +629,7 @@ def main():
     flags, strain = sim.health()
     sim.close()
 
-    traffic = measured_traffic(args.storage, nodes)
+    traffic = measured_traffic(args.storage, nodes, args.workload)
     out = {
         "metric": "MLUPS & % HBM roofline", "value": round(mlups, 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

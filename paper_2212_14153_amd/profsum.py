@@ -3,14 +3,15 @@
   python -m paper_2212_14153_amd.profsum trace --stats DIR/x_kernel_stats.csv \\
       --command "..." [--bench-json LINE_FILE] --out SUMMARY.md
   python -m paper_2212_14153_amd.profsum traffic --fetch FETCH.csv --write WRITE.csv \\
-      --kernel step_kernel --storage f32 --nodes N --copy-bytes B --command "..." \\
-      --out TRAFFIC.json
+      --kernel step_kernel --storage f32 --workload c3 --nodes N --copy-bytes B \\
+      --command "..." --out TRAFFIC.json
 
 `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of a kernel into HBM bytes per
 launch, each scaled by what the same counter reads for the plain copy kernel of known size
 that the same run dispatches (a copy of B bytes reads B and writes B bytes).  The JSON keeps
-one entry per storage format and the hash of the library sources the counters were taken
-on, so a later change of the kernels or the layout invalidates them.
+one entry per storage format, the workload it was measured on and the hash of the library
+sources the counters were taken on, so a later change of the kernels or the layout
+invalidates them.
 """
 from __future__ import annotations
 
@@ -108,10 +109,10 @@ def traffic_entry(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int):
     f_write = copy_bytes / copy_w
     k_f = statistics.median(_pick(fetch, kernel)) * 1024.0
     k_w = statistics.median(_pick(write, kernel)) * 1024.0
+    read, wrote = round(k_f * f_fetch), round(k_w * f_write)
     return {"fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4),
-            "read_bytes_per_launch": round(k_f * f_fetch),
-            "write_bytes_per_launch": round(k_w * f_write),
-            "bytes_per_launch": round(k_f * f_fetch + k_w * f_write),
+            "read_bytes_per_launch": read, "write_bytes_per_launch": wrote,
+            "bytes_per_launch": read + wrote,
             "dispatches": [len(_pick(fetch, kernel)), len(_pick(write, kernel))]}
 
 
@@ -128,6 +129,7 @@ def main(argv=None):
     c.add_argument("--write", required=True)
     c.add_argument("--kernel", default="step_kernel")
     c.add_argument("--storage", required=True)
+    c.add_argument("--workload", default="c3", help="bench.py --workload of the counted runs")
     c.add_argument("--nodes", type=int, required=True)
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--command", required=True)
@@ -140,7 +142,7 @@ def main(argv=None):
             f.write(text)
         return
     ent = traffic_entry(a.fetch, a.write, a.kernel, a.copy_bytes)
-    ent.update(nodes=a.nodes, kernel=a.kernel, command=a.command)
+    ent.update(nodes=a.nodes, kernel=a.kernel, workload=a.workload, command=a.command)
     try:
         with open(a.out) as f:
             rec = json.load(f)

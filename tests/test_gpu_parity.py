@@ -8,6 +8,7 @@ Tolerances:
     1e-4 lattice units after 1000 steps (the accuracy the FP32 path is held to).
 """
 import math
+import time
 
 import numpy as np
 import pytest
@@ -238,11 +239,18 @@ def test_timed_path_matches_untimed():
     w = workloads.c1_small_fp64()
     print_case("timed", w, "f32")
     with gpu_sim(w, "f32", flags=_lib.FPD_FLAG_TIME_KERNELS) as a, gpu_sim(w, "f32") as b:
+        a.sync()
+        t0 = time.perf_counter()
         a.step(40)
+        a.sync()
+        wall_ms = (time.perf_counter() - t0) * 1e3
         b.step(40)
         assert np.array_equal(a.populations(), b.populations())
         ms_l, n_l, ms_b, n_b = a.kernel_times()
         assert n_l == 40 and n_b == 40 and ms_l > 0 and ms_b > 0
+        # the durations are those of the dispatches, which run one after another on the
+        # simulation's stream: together they fit in the host's wall time of those steps
+        assert ms_l + ms_b <= wall_ms, (ms_l, ms_b, wall_ms)
 
 
 def test_repeat_runs_are_deterministic():

@@ -1,0 +1,83 @@
+"""The counter arithmetic behind the roofline's `traffic` field, on synthetic rocprofv3
+CSVs (no GPU): each counter is scaled by what it reads for the plain copy kernel of
+known size, per dispatch, and bench.py uses an entry only for the kernel source, storage,
+lattice size and workload it was measured on."""
+import csv
+import importlib.util
+import json
+import os
+
+from paper_2212_14153_amd import profsum
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY = "fpd::copy_kernel(float __vector(4) const*, float __vector(4)*, unsigned long)"
+STEP = "void fpd::step_kernel<1, 1, 0>(fpd::StepArgs)"
+GIB = 1 << 30
+
+
+def write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (name, kib) in enumerate(rows):
+            w.writerow([i, name, counter, kib])
+
+
+def counters(tmp_path, fetch_copy_kib, write_copy_kib, fetch_step_kib, write_step_kib):
+    fetch = str(tmp_path / "fetch.csv")
+    write = str(tmp_path / "write.csv")
+    # the copy's median is taken, so one outlier dispatch does not move the factor
+    write_counters(fetch, "FETCH_SIZE", [(COPY, fetch_copy_kib), (COPY, fetch_copy_kib),
+                                         (COPY, 3 * fetch_copy_kib)] +
+                   [(STEP, fetch_step_kib)] * 4)
+    write_counters(write, "WRITE_SIZE", [(COPY, write_copy_kib)] * 3 +
+                   [(STEP, write_step_kib)] * 4)
+    return fetch, write
+
+
+def test_short_names():
+    assert profsum.short_name(STEP) == "step_kernel<1, 1, 0>"
+    assert profsum.short_name(COPY) == "copy_kernel"
+
+
+def test_traffic_is_scaled_by_the_copy_kernel(tmp_path):
+    # FETCH_SIZE reads half of the copy's 1 GiB (factor 2), WRITE_SIZE all of it (factor 1)
+    fetch, write = counters(tmp_path, GIB / 2 / 1024, GIB / 1024, 300_000.0, 600_000.0)
+    ent = profsum.traffic_entry(fetch, write, "step_kernel", GIB)
+    assert ent["fetch_factor"] == 2.0 and ent["write_factor"] == 1.0
+    assert ent["read_bytes_per_launch"] == 2 * 300_000 * 1024
+    assert ent["write_bytes_per_launch"] == 600_000 * 1024
+    assert ent["bytes_per_launch"] == (600_000 + 600_000) * 1024
+    assert ent["dispatches"] == [4, 4]
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_uses_an_entry_only_where_it_was_measured(tmp_path, monkeypatch):
+    bench = load_bench()
+    sha = profsum.kernel_source_hash()
+    path = tmp_path / "traffic.json"
+    rec = {"kernel_sha": sha,
+           "entries": {"f32": {"bytes_per_launch": 1234, "nodes": 4096, "workload": "c3"}}}
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    assert bench.measured_traffic("f32", 4096, "c3") == 1234
+    assert bench.measured_traffic("f32", 4096, "suspension") is None   # same lattice size
+    assert bench.measured_traffic("f32", 8192, "c3") is None
+    assert bench.measured_traffic("f64", 4096, "c3") is None
+    rec["kernel_sha"] = "0" * 16                                         # kernels changed since
+    path.write_text(json.dumps(rec))
+    assert bench.measured_traffic("f32", 4096, "c3") is None
+
+
+def test_committed_traffic_entries_name_their_workload():
+    with open(os.path.join(ROOT, "profiles", "traffic_step_kernel.json")) as f:
+        rec = json.load(f)
+    for storage, ent in rec["entries"].items():
+        assert ent["workload"] == "c3" and f"--storage {storage}" in ent["command"]
+        assert ent["bytes_per_launch"] == ent["read_bytes_per_launch"] + ent["write_bytes_per_launch"]
