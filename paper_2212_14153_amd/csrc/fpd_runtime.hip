@@ -328,12 +328,20 @@ int upload_populations(fpd_sim* s, const double* host_f) {
     return FPD_OK;
 }
 
+// Parameters a checkpoint must share with the simulation it is loaded into: everything
+// that defines the problem (init_flow only shapes the state a checkpoint replaces, and
+// the graph and timing flags can change at any time).
 bool params_equal(const fpd_params& a, const fpd_params& b) {
     return a.nx == b.nx && a.ny == b.ny && a.u_wall == b.u_wall && a.nu_f == b.nu_f &&
            a.eta_ratio == b.eta_ratio && a.xi == b.xi && a.n_beads == b.n_beads &&
            a.radius == b.radius && a.l0 == b.l0 && a.k_s == b.k_s && a.k_b == b.k_b &&
            a.s_e == b.s_e && a.s_eps == b.s_eps && a.s_q_fixed == b.s_q_fixed &&
-           a.cutoff == b.cutoff && a.storage == b.storage;
+           a.cutoff == b.cutoff && a.storage == b.storage && a.boundary == b.boundary &&
+           chains_of(&a) == chains_of(&b) &&
+           (a.flags & FPD_FLAG_CLAMP_PHI) == (b.flags & FPD_FLAG_CLAMP_PHI) &&
+           a.f_ext[0] == b.f_ext[0] && a.f_ext[1] == b.f_ext[1] &&
+           a.g_body[0] == b.g_body[0] && a.g_body[1] == b.g_body[1] && a.ev_k == b.ev_k &&
+           a.ev_range == b.ev_range;
 }
 
 int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t bytes_each,
@@ -544,11 +552,16 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
         h.win[k][3] = -0x7fffffff;
     }
     HIP_TRY(hipMemcpyAsync(s->bs, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
-    s->fiber = true;
     drop_graphs(s);
-    int rc = fiber_init_device(s);
-    if (rc) return rc;
-    return sync_check(s);
+    s->fiber = true;  // make_args hands the beads to the kernels only with a fiber
+    // the stream is synchronised on every path below: the copy reads h from this frame
+    const int rc = fiber_init_device(s);
+    const int rs = sync_check(s);
+    if (rc || rs) {
+        s->fiber = false;
+        return rc ? rc : rs;
+    }
+    return FPD_OK;
 }
 
 int fpd_init_fiber_line(fpd_sim* s, double cx, double cy, double theta) {
@@ -838,6 +851,12 @@ int fpd_write_populations(fpd_sim* s, const double* f) {
     return upload_populations(s, f);
 }
 
+// R, V and F are read with one copy
+constexpr size_t kBeadPairs = sizeof(double) * 2 * kMaxBeads;
+static_assert(offsetof(BeadState, V) == offsetof(BeadState, R) + kBeadPairs &&
+                  offsetof(BeadState, F) == offsetof(BeadState, V) + kBeadPairs,
+              "R, V, F must be adjacent in BeadState");
+
 int fpd_read_beads(fpd_sim* s, double* R, double* V, double* F) {
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     const int N = s->p.n_beads;
@@ -857,9 +876,14 @@ int fpd_read_beads(fpd_sim* s, double* R, double* V, double* F) {
     return FPD_OK;
 }
 
-int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
-    if (!s || !c) return fail(FPD_EINVAL, "NULL argument");
-    fpd_launch n = s->launch;
+}  // extern "C"
+
+namespace {
+
+// `cur` with the fields of `c` that are > 0, checked against the shapes the lattice
+// kernels are built for.
+int merge_launch(const fpd_launch& cur, const fpd_launch* c, fpd_launch& n) {
+    n = cur;
     if (c->block_x > 0) n.block_x = c->block_x;
     if (c->block_y > 0) n.block_y = c->block_y;
     if (c->rows_per_thread > 0) n.rows_per_thread = c->rows_per_thread;
@@ -872,9 +896,22 @@ int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
     if (n.block_x * n.block_y > 256) return fail(FPD_EINVAL, "at most 256 threads per block");
     if (n.rows_per_thread != 1 && n.rows_per_thread != 2 && n.rows_per_thread != 4)
         return fail(FPD_EINVAL, "rows_per_thread must be 1, 2 or 4");
+    if (n.xcd_remap != 1 && n.xcd_remap != 2) return fail(FPD_EINVAL, "xcd_remap must be 1 or 2");
     if (n.graph_chunk < 2 || (n.graph_chunk & 1))
         return fail(FPD_EINVAL, "graph_chunk must be even and >= 2");
-    int rc = sync_check(s);
+    return FPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fpd_set_launch(fpd_sim* s, const fpd_launch* c) {
+    if (!s || !c) return fail(FPD_EINVAL, "NULL argument");
+    fpd_launch n;
+    int rc = merge_launch(s->launch, c, n);
+    if (rc) return rc;
+    rc = sync_check(s);
     if (rc) return rc;
     s->launch = n;
     drop_graphs(s);
@@ -924,7 +961,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
         (void)hipFree(a);
         return fail(FPD_ENOMEM, "copy probe allocation");
     }
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, st);
@@ -935,8 +972,8 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(a);
     (void)hipFree(b);
     if (e != hipSuccess) return fail(FPD_EDEVICE, "copy probe: %s", hipGetErrorString(e));
@@ -1270,19 +1307,14 @@ void fpd_batch_destroy(fpd_batch* b) {
 
 int fpd_batch_set_launch(fpd_batch* b, const fpd_launch* c) {
     if (!b || !c) return fail(FPD_EINVAL, "NULL argument");
+    fpd_launch n;
+    int rc = merge_launch(b->launch, c, n);  // checked before any member changes
+    if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(b->stream));
     for (auto& e : b->entries) {
-        int rc = fpd_set_launch(e.sim, c);
+        rc = fpd_set_launch(e.sim, &n);
         if (rc) return rc;
     }
-    fpd_launch n = b->launch;
-    if (c->block_x > 0) n.block_x = c->block_x;
-    if (c->block_y > 0) n.block_y = c->block_y;
-    if (c->rows_per_thread > 0) n.rows_per_thread = c->rows_per_thread;
-    if (c->xcd_remap > 0) n.xcd_remap = c->xcd_remap;
-    if (c->graph_chunk > 0) n.graph_chunk = c->graph_chunk;
-    if (n.block_x * n.block_y > 256 || (n.graph_chunk & 1) || n.graph_chunk < 2)
-        return fail(FPD_EINVAL, "invalid batch launch");
     b->launch = n;
     batch_drop_graph(b);
     b->dirty = true;

@@ -119,3 +119,23 @@ def test_unstable_simulation_is_evicted_and_others_continue():
         assert status[bad] == _lib.FPD_SIM_FAILED
         assert status[good] == _lib.FPD_SIM_DONE
         assert np.array_equal(b.populations(good), ref)
+
+
+@pytest.mark.parametrize("bad", [dict(block_x=32), dict(block_y=3), dict(rows_per_thread=3),
+                                 dict(xcd_remap=5), dict(graph_chunk=7)])
+def test_invalid_batch_launch_is_refused_before_any_change(bad):
+    ws = small_sweep("f32", count=2)
+    print(f"[case] batch-launch {bad}", flush=True)
+    with _lib.Batch(hbm_budget=1 << 33, max_slots=4, storage="f32") as empty:
+        with pytest.raises(_lib.FpdError) as err:
+            empty.set_launch(bad)
+        assert err.value.code == _lib.FPD_EINVAL
+    with _lib.Batch(hbm_budget=1 << 33, max_slots=4, storage="f32") as b:
+        ids = [b.add(_lib.params_from_mapping(w.params(), storage="f32"), w.beads(), 20)
+               for w in ws]
+        with pytest.raises(_lib.FpdError) as err:
+            b.set_launch(bad)
+        assert err.value.code == _lib.FPD_EINVAL
+        # the batch and its members keep the launch they had and still run
+        assert b.run(20) == 20
+        assert sorted(sid for sid, st in b.poll() if st == _lib.FPD_SIM_DONE) == sorted(ids)

@@ -285,6 +285,22 @@ def test_checkpoint_resume_is_bitwise(tmp_path, first):
         assert np.array_equal(c.beads()[0], Ra)
 
 
+@pytest.mark.parametrize("over", [dict(g_body=(1e-7, 0.0)), dict(flags=_lib.FPD_FLAG_CLAMP_PHI),
+                                  dict(k_b=0.5), dict(n_chains=5)])
+def test_checkpoint_of_another_problem_is_refused(tmp_path, over):
+    w = workloads.c1_small_fp64()
+    print_case(f"checkpoint-mismatch-{sorted(over)}", w, "f32")
+    path = str(tmp_path / "c1.fpd")
+    with gpu_sim(w, "f32") as a:
+        a.step(4)
+        a.save(path)
+    with gpu_sim(w, "f32", **over) as b:
+        with pytest.raises(_lib.FpdError) as err:
+            b.load(path)
+        assert err.value.code == _lib.FPD_EINVAL and "does not match" in str(err.value)
+        assert b.steps == 0
+
+
 def test_zero_steps_is_a_no_op():
     w = workloads.c1_small_fp64()
     with gpu_sim(w, "f64") as sim:
