@@ -217,18 +217,41 @@ class LaunchConfig:
     graph_chunk: int = 64
 
 
+def buffer_args(buffers):
+    """(a, b) or (a, b, nbytes) -> the two device addresses and the usable size of each:
+    objects with data_ptr() (e.g. torch tensors) give their address and size, integers are
+    addresses whose size must be given."""
+    a, b = buffers[0], buffers[1]
+    if len(buffers) > 2:
+        nbytes = int(buffers[2])
+    else:
+        sizes = [x.numel() * x.element_size() if hasattr(x, "element_size") else None
+                 for x in (a, b)]
+        if None in sizes:
+            raise ValueError("integer buffer addresses need their size in bytes")
+        nbytes = min(sizes)
+    pa, pb = (x.data_ptr() if hasattr(x, "data_ptr") else int(x) for x in (a, b))
+    return pa, pb, nbytes
+
+
 class Simulation:
     """One simulation on the current HIP device, driven through the C ABI."""
 
     def __init__(self, params: fpd_params, stream=None, buffers=None):
+        """buffers: None (the library allocates), or (a, b) or (a, b, nbytes) with two device
+        buffers of at least fpd_population_bytes(params) bytes each, 16-byte aligned, given
+        as objects with data_ptr() (e.g. torch tensors, whose sizes are then read) or as
+        integer addresses (nbytes required).  The simulation keeps a reference to them."""
         self.p = params
+        self._buffers = None
         h = _SIM()
         if buffers is None:
             check(lib().fpd_create(ctypes.byref(params), stream, ctypes.byref(h)))
         else:
-            a, b, nbytes = buffers
-            check(lib().fpd_create_with_buffers(ctypes.byref(params), stream, a, b, nbytes,
+            pa, pb, nbytes = buffer_args(buffers)
+            check(lib().fpd_create_with_buffers(ctypes.byref(params), stream, pa, pb, nbytes,
                                                 ctypes.byref(h)))
+            self._buffers = tuple(buffers[:2])  # the owners outlive the simulation's use
         self.h = h
         self.nx, self.ny, self.n = params.nx, params.ny, params.n_beads
 
@@ -237,6 +260,7 @@ class Simulation:
         if self.h:
             lib().fpd_destroy(self.h)
             self.h = _SIM()
+        self._buffers = None
 
     def __del__(self):
         try:

@@ -80,3 +80,28 @@ def test_population_bytes(L):
     p = _lib.fpd_params_default()
     p.nx, p.ny, p.storage = 100, 7, _lib.FPD_F16DEV
     assert _lib.fpd_population_bytes(p) == 9 * 7 * 128 * 2
+
+
+def test_caller_buffer_arguments():
+    """The binding's reading of caller-owned buffers (fpd_create_with_buffers): objects with
+    data_ptr() give address and size (the smaller of the two), integers need a size."""
+    from paper_2212_14153_amd import _lib
+
+    class Tensor:  # the few attributes of a torch tensor the binding reads
+        def __init__(self, ptr, numel, esize):
+            self.ptr, self.n, self.e = ptr, numel, esize
+
+        def data_ptr(self):
+            return self.ptr
+
+        def numel(self):
+            return self.n
+
+        def element_size(self):
+            return self.e
+
+    assert _lib.buffer_args((Tensor(4096, 100, 4), Tensor(8192, 96, 4))) == (4096, 8192, 384)
+    assert _lib.buffer_args((Tensor(4096, 100, 4), Tensor(8192, 96, 4), 200)) == (4096, 8192, 200)
+    assert _lib.buffer_args((4096, 8192, 123)) == (4096, 8192, 123)
+    with pytest.raises(ValueError):
+        _lib.buffer_args((4096, 8192))

@@ -7,6 +7,7 @@ Tolerances:
   * FPD_F32: populations within 1e-5 relative after 100 steps and bead positions within
     1e-4 lattice units after 1000 steps (the accuracy the FP32 path is held to).
 """
+import ctypes
 import math
 import time
 
@@ -299,6 +300,58 @@ def test_checkpoint_of_another_problem_is_refused(tmp_path, over):
             b.load(path)
         assert err.value.code == _lib.FPD_EINVAL and "does not match" in str(err.value)
         assert b.steps == 0
+
+
+def hip_runtime():
+    """The HIP runtime the library links (already loaded with it), for raw allocations."""
+    _lib.lib()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return hip
+
+
+def test_caller_owned_buffers():
+    """fpd_create_with_buffers: the state lives in the caller's device memory and the steps
+    are bitwise those of library-owned buffers; short or misaligned buffers are refused."""
+    w = workloads.c1_small_fp64()
+    print_case("caller-buffers", w, "f32")
+    p = _lib.params_from_mapping(w.params(), storage="f32")
+    n = _lib.fpd_population_bytes(p)
+    hip = hip_runtime()
+    ptrs = []
+    try:
+        for _ in range(2):
+            ptr = ctypes.c_void_p()
+            assert hip.hipMalloc(ctypes.byref(ptr), n) == 0
+            ptrs.append(ptr.value)
+
+        def snapshot():
+            out = np.empty(n, np.uint8)
+            assert hip.hipMemcpy(out.ctypes.data, ptrs[0], n, 2) == 0  # device to host
+            return out
+
+        with _lib.Simulation(p, buffers=(ptrs[0], ptrs[1], n)) as a, gpu_sim(w, "f32") as b:
+            a.init_fiber(w.beads())
+            a.step(30)
+            b.step(30)
+            assert np.array_equal(a.populations(), b.populations())
+            assert np.array_equal(a.beads()[0], b.beads()[0])
+            a.sync()
+            before = snapshot()
+            a.step(2)  # buffer 0 is written again every second step
+            a.sync()
+            assert not np.array_equal(snapshot(), before)
+        with pytest.raises(_lib.FpdError) as err:
+            _lib.Simulation(p, buffers=(ptrs[0], ptrs[1], n - 64))
+        assert err.value.code == _lib.FPD_EINVAL
+        with pytest.raises(_lib.FpdError) as err:  # not 16-byte aligned
+            _lib.Simulation(p, buffers=(ptrs[0] + 8, ptrs[1], n - 8))
+        assert err.value.code == _lib.FPD_EINVAL
+    finally:
+        for ptr in ptrs:
+            hip.hipFree(ptr)
 
 
 def test_zero_steps_is_a_no_op():
