@@ -4,7 +4,6 @@ the C ABI: populations and beads after coupled steps (FP64 1e-12 relative / 1e-1
 1e-5 / 1e-4 lu, the FP32 bound of the single-fiber runs), the forces read back at the
 start, the point symmetry of a symmetric pair, bitwise launch-shape independence, and
 batch equality."""
-import math
 
 import numpy as np
 import pytest

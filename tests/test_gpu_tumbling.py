@@ -2,7 +2,6 @@
 each record is the end-to-end vector and centroid of every fiber of the state R^n at the
 start of step n (FP64: 1e-11 lu), every `every` steps, in a ring of `capacity` records.
 Graph replay, direct launches and batches record the same values."""
-import math
 
 import numpy as np
 import pytest
