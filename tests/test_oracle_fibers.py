@@ -1,11 +1,15 @@
-"""Several fibers (the survey's NEXT-4 widening of Sec. II.B): beads c L .. c L + L - 1
-form fiber c; springs and bending act inside a fiber only, and fibers interact through
-the fluid alone (the paper gives no excluded-volume force, so none is modelled).
+"""Several fibers (the outlook of Sec. V applied to the chain of Sec. II.B): beads
+c L .. c L + L - 1 form fiber c; springs and bending act inside a fiber only. By default
+fibers interact through the fluid alone (the paper gives no excluded-volume force); an
+optional pair repulsion between beads of different fibers, (k/2)(d - r)^2 for r < d,
+can be switched on.
 
-Pins: the forces on a set of fibers are exactly those of each fiber alone; and two
-fibers placed point-symmetrically about the centre of the +-U Couette channel stay
+Pins: the forces on a set of fibers are exactly those of each fiber alone; two fibers
+placed point-symmetrically about the centre of the +-U Couette channel stay
 point-symmetric (the rotation by 180 degrees maps the problem onto itself, swapping the
-fibers and reversing their bead order).
+fibers and reversing their bead order); the repulsion is minus the gradient of its
+energy, has no net force or torque, acts between fibers only and within range, and
+across the periodic boundary.
 """
 import math
 
