@@ -20,9 +20,30 @@ namespace fpd {
 
 // ------------------------------------------------------------------ reductions ------
 
+// One DPP move of a double (two 32-bit halves): lanes outside ROW_MASK, and lanes whose
+// source lies outside their row of 16, receive 0.  Controls of the gfx9 family:
+// row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), in a fixed order, returned to every
+// lane: running sums along each row of 16 lanes by shifts of 1, 2, 4, 8, then rows 0 + 1
+// and 2 + 3 by broadcasting lane 15 of a row into the next, and the two halves by
+// broadcasting lane 31; lane 63 then holds the total.  Register moves only, no LDS.
 __device__ inline double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
+    v += dpp_move<0x111, 0xf>(v);
+    v += dpp_move<0x112, 0xf>(v);
+    v += dpp_move<0x114, 0xf>(v);
+    v += dpp_move<0x118, 0xf>(v);
+    v += dpp_move<0x142, 0xa>(v);
+    v += dpp_move<0x143, 0xc>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Sum over the block in a fixed order (deterministic); result valid in every thread.
