@@ -10,9 +10,20 @@ namespace fpd {
 
 constexpr int kMaxBeads = FPD_MAX_BEADS;
 constexpr int kBeadThreads = 256;   // finish kernel (one thread per bead)
-// Bead kernels (single and batched) use one block size: the per-bead FP64 reduction tree
-// follows it, so a simulation's bead velocities are bitwise the same alone and in a batch.
-constexpr int kBeadBlock = 256;
+// The per-bead FP64 sums of the bead kernels run over kBeadLanes virtual lanes in a fixed
+// order (each lane's nodes in increasing order, a wave tree per 64 lanes, then the waves in
+// order), whatever the block size; a real thread carries kBeadLanes / blockDim of them.
+// One simulation launches kBeadBlock threads per bead (few blocks: latency bound), a batch
+// kBatchBeadBlock (thousands of blocks: throughput bound), and a simulation's bead
+// velocities are bitwise the same alone and in a batch.
+constexpr int kBeadLanes = 512;
+constexpr int kBeadBlock = 512;
+constexpr int kBatchBeadBlock = 256;
+static_assert(kBeadLanes % kBeadBlock == 0 && kBeadLanes % kBatchBeadBlock == 0 &&
+                  kBatchBeadBlock % 64 == 0 && kBeadBlock % 64 == 0,
+              "bead blocks must divide the virtual lanes into whole waves");
+// block of the driven-particle diagnostics (one block, a plain block reduction)
+constexpr int kStatsBlock = 256;
 // nodes per thread and pass of the velocity sums: one simulation (few bead blocks, latency
 // bound: 4) and batches (thousands of bead blocks, where fewer registers let more blocks
 // reside: 2; the FP16 sweep step 590 -> 580 us); the sums run in the same order for any

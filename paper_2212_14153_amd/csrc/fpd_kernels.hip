@@ -61,28 +61,48 @@ __device__ inline double block_sum(double v, double* scratch) {
     return s;
 }
 
-// Two sums at once, each in the order of block_sum (bitwise the same results), through one
-// round of the scratch array (2 * waves entries).
-__device__ inline void block_sum2(double& a, double& b, double* scratch) {
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    const int nthreads = blockDim.x * blockDim.y;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
-    a = wave_sum(a);
-    b = wave_sum(b);
-    __syncthreads();
-    if (lane == 0) {
-        scratch[wave] = a;
-        scratch[nwaves + wave] = b;
+// Sums over kBeadLanes virtual lanes held R per thread (R = kBeadLanes / blockDim.x, 1-D
+// blocks): v[r] is the partial sum of virtual lane tid + r * blockDim.x, which lies in
+// virtual wave (tid >> 6) + r * blockDim.x / 64 at the same lane, so the wave sums and the
+// order over virtual waves are those of a block of kBeadLanes threads.  Result in every
+// thread; scratch holds kBeadLanes / 64 entries per sum.
+template <int R>
+__device__ inline double lanes_sum(const double (&v)[R], double* scratch) {
+    const int tid = threadIdx.x, lane = tid & 63, wpr = (int)blockDim.x >> 6;
+    __syncthreads();  // scratch may still be read by a previous sum
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double w = wave_sum(v[r]);
+        if (lane == 0) scratch[r * wpr + (tid >> 6)] = w;
     }
     __syncthreads();
-    double sa = 0.0, sb = 0.0;
-    for (int w = 0; w < nwaves; ++w) {
-        sa += scratch[w];
-        sb += scratch[nwaves + w];
+    double s = 0.0;
+    for (int q = 0; q < kBeadLanes / 64; ++q) s += scratch[q];
+    return s;
+}
+
+// Two lanes_sum at once (bitwise the same results), through one round of the scratch array.
+template <int R>
+__device__ inline void lanes_sum2(const double (&a)[R], const double (&b)[R], double& sa,
+                                  double& sb, double* scratch) {
+    constexpr int nw = kBeadLanes / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wpr = (int)blockDim.x >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double wa = wave_sum(a[r]), wb = wave_sum(b[r]);
+        if (lane == 0) {
+            scratch[r * wpr + (tid >> 6)] = wa;
+            scratch[nw + r * wpr + (tid >> 6)] = wb;
+        }
     }
     __syncthreads();
-    a = sa;
-    b = sb;
+    sa = 0.0;
+    sb = 0.0;
+    for (int q = 0; q < nw; ++q) {
+        sa += scratch[q];
+        sb += scratch[nw + q];
+    }
 }
 
 // ----------------------------------------------------------- bead forces ------------
@@ -763,11 +783,13 @@ __device__ inline void box_node(const Fiber& fib, int t, int total, int i0, int 
 // VB nodes per thread and pass in the velocity phase: their loads are issued together, so
 // a pass waits for memory once (short latency chains for a few beads), at the cost of
 // registers (fewer resident blocks when a batch has thousands of beads).  The loads depend
-// only on the cutoff test, so phi is evaluated while they are in flight.  Per-thread sums
-// still run over t = tid, tid + blockDim.x, ... in increasing t, whatever VB.
-template <int ST, int VB>
+// only on the cutoff test, so phi is evaluated while they are in flight.  The sums run
+// over kBeadLanes virtual lanes (NT threads of R = kBeadLanes / NT lanes each): lane v
+// takes nodes t = v, v + kBeadLanes, ... in increasing t, whatever VB and NT.
+template <int ST, int VB, int NT>
 __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int win_out,
                                   double* scratch, double* s_R) {
+    constexpr int R = kBeadLanes / NT;
     using Cd = Codec<ST>;
     using T = typename Cd::T;
     using S = typename Cd::store_t;
@@ -794,60 +816,66 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
         const int wx0 = win.x0, wy0 = win.y0, ww = win.w, wh = win.h;
         const T* rf = (const T*)fib.rect_f;
         const S* cur = (const S*)a.dst;
-        double sx = 0.0, sy = 0.0;
-        const int nt = (int)blockDim.x;
-        for (int t0 = tid; t0 < total; t0 += VB * nt) {
-            double ph[VB], r2[VB];
-            bool in[VB];
-            int ii[VB], jj[VB];
-            T g[VB][9];
-            T fw[VB][2];
+        double sx[R], sy[R];
 #pragma unroll
-            for (int u = 0; u < VB; ++u)
-                box_node(fib, t0 + u * nt, total, i0, w, j0, nx, ny, per, Rx, Ry, ii[u], jj[u],
-                         r2[u], in[u]);
+        for (int r = 0; r < R; ++r) {
+            sx[r] = 0.0;
+            sy[r] = 0.0;
+            for (int t0 = tid + r * NT; t0 < total; t0 += VB * kBeadLanes) {
+                double ph[VB], r2[VB];
+                bool in[VB];
+                int ii[VB], jj[VB];
+                T g[VB][9];
+                T fw[VB][2];
 #pragma unroll
-            for (int u = 0; u < VB; ++u) {
-                fw[u][0] = (T)a.gx;  // outside the window f^n is the body force alone
-                fw[u][1] = (T)a.gy;
-                if (in[u]) {
-                    pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii[u], jj[u], per, (T)a.u6,
-                             g[u]);
-                    // f^n at this node from the window the lattice kernel filled (the window
-                    // covers every support box unless it was clamped, which raises
-                    // FPD_HEALTH_SUPPORT)
-                    const int wi = imod(ii[u] - wx0, nx);
-                    const int wj = per ? imod(jj[u] - wy0, ny) : jj[u] - wy0;
-                    if (wi < ww && wj >= 0 && wj < wh) {
-                        const T* fp = rf + 2 * ((long long)wj * fib.rect_wmax + wi);
-                        fw[u][0] = fp[0];
-                        fw[u][1] = fp[1];
+                for (int u = 0; u < VB; ++u)
+                    box_node(fib, t0 + u * kBeadLanes, total, i0, w, j0, nx, ny, per, Rx, Ry,
+                             ii[u], jj[u], r2[u], in[u]);
+#pragma unroll
+                for (int u = 0; u < VB; ++u) {
+                    fw[u][0] = (T)a.gx;  // outside the window f^n is the body force alone
+                    fw[u][1] = (T)a.gy;
+                    if (in[u]) {
+                        pull<Cd>(cur, nx, ny, a.L.stride, a.L.plane, ii[u], jj[u], per,
+                                 (T)a.u6, g[u]);
+                        // f^n at this node from the window the lattice kernel filled (the
+                        // window covers every support box unless it was clamped, which
+                        // raises FPD_HEALTH_SUPPORT)
+                        const int wi = imod(ii[u] - wx0, nx);
+                        const int wj = per ? imod(jj[u] - wy0, ny) : jj[u] - wy0;
+                        if (wi < ww && wj >= 0 && wj < wh) {
+                            const T* fp = rf + 2 * ((long long)wj * fib.rect_wmax + wi);
+                            fw[u][0] = fp[0];
+                            fw[u][1] = fp[1];
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < VB; ++u) ph[u] = in[u] ? bead_phi_r2<T>(fib, r2[u]) : 0.0;
+                for (int u = 0; u < VB; ++u)
+                    ph[u] = in[u] ? bead_phi_r2<T>(fib, r2[u]) : 0.0;
 #pragma unroll
-            for (int u = 0; u < VB; ++u) {
-                if (ph[u] == 0.0) continue;
-                double drho = 0.0;
+                for (int u = 0; u < VB; ++u) {
+                    if (ph[u] == 0.0) continue;
+                    double drho = 0.0;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) drho += (double)g[u][k];
-                const double jx = ((double)g[u][1] - (double)g[u][3]) +
-                                  ((double)g[u][5] - (double)g[u][6]) -
-                                  ((double)g[u][7] - (double)g[u][8]);
-                const double jy = ((double)g[u][2] - (double)g[u][4]) +
-                                  ((double)g[u][5] + (double)g[u][6]) -
-                                  ((double)g[u][7] + (double)g[u][8]);
-                const double rho = 1.0 + drho;
-                sx += ph[u] * ((jx + 0.5 * (double)fw[u][0]) / rho);
-                sy += ph[u] * ((jy + 0.5 * (double)fw[u][1]) / rho);
+                    for (int k = 0; k < 9; ++k) drho += (double)g[u][k];
+                    const double jx = ((double)g[u][1] - (double)g[u][3]) +
+                                      ((double)g[u][5] - (double)g[u][6]) -
+                                      ((double)g[u][7] - (double)g[u][8]);
+                    const double jy = ((double)g[u][2] - (double)g[u][4]) +
+                                      ((double)g[u][5] + (double)g[u][6]) -
+                                      ((double)g[u][7] + (double)g[u][8]);
+                    const double rho = 1.0 + drho;
+                    sx[r] += ph[u] * ((jx + 0.5 * (double)fw[u][0]) / rho);
+                    sy[r] += ph[u] * ((jy + 0.5 * (double)fw[u][1]) / rho);
+                }
             }
         }
-        block_sum2(sx, sy, scratch);
+        double Sx, Sy;
+        lanes_sum2<R>(sx, sy, Sx, Sy, scratch);
         if (tid == 0) {
-            Vx = sx / A_old;
-            Vy = sy / A_old;
+            Vx = Sx / A_old;
+            Vy = Sy / A_old;
             bs->V[b][0] = Vx;
             bs->V[b][1] = Vy;
             s_R[0] = Rx + Vx;  // forward Euler, dt = 1
@@ -864,17 +892,21 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
     const int rows = j1 - j0 + 1;
     const int total = (rows > 0 && w > 0) ? rows * w : 0;
-    double s = 0.0;
-    for (int t = tid; t < total; t += blockDim.x) {
-        int x, y;
-        double r2;
-        bool in;
-        box_node(fib, t, total, i0, w, j0, nx, ny, per, Rx, Ry, x, y, r2, in);
-        if (in) s += bead_phi_r2<T>(fib, r2);
+    double sa[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        sa[r] = 0.0;
+        for (int t = tid + r * NT; t < total; t += kBeadLanes) {
+            int x, y;
+            double r2;
+            bool in;
+            box_node(fib, t, total, i0, w, j0, nx, ny, per, Rx, Ry, x, y, r2, in);
+            if (in) sa[r] += bead_phi_r2<T>(fib, r2);
+        }
     }
-    s = block_sum(s, scratch);
+    const double A_new = lanes_sum<R>(sa, scratch);
     if (tid == 0) {
-        bs->A[b] = s;
+        bs->A[b] = A_new;
         // this bead's share of the next support window and its health bits
         int* nw = bs->win[win_out];
         if (bead_sane(Rx, Ry)) {
@@ -891,7 +923,8 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
             Vy = bs->V[b][1];
         }
         unsigned h = 0u;
-        if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) || !isfinite(s))
+        if (!isfinite(Rx) || !isfinite(Ry) || !isfinite(Vx) || !isfinite(Vy) ||
+            !isfinite(A_new))
             h |= FPD_HEALTH_NAN;
         if (Vx * Vx + Vy * Vy > 0.09 / 3.0) h |= FPD_HEALTH_MACH;
         if (!per && (Ry - fib.a - fib.xi < 0.0 || Ry + fib.a + fib.xi > (double)ny))
@@ -903,22 +936,24 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
 template <int ST>
 __global__ void __launch_bounds__(kBeadBlock) bead_kernel(StepArgs a, int do_velocity,
                                                           int win_out) {
-    __shared__ double scratch[2 * (kBeadBlock / 64)];
+    __shared__ double scratch[2 * (kBeadLanes / 64)];
     __shared__ double s_R[2];
-    bead_block<ST, kBeadVelBatch>(a, blockIdx.x, do_velocity, win_out, scratch, s_R);
+    bead_block<ST, kBeadVelBatch, kBeadBlock>(a, blockIdx.x, do_velocity, win_out, scratch,
+                                              s_R);
 }
 
 // Bead kernel over a batch: one block per (simulation, bead) item.
 template <int ST>
-__global__ void __launch_bounds__(kBeadBlock) batch_bead_kernel(BatchArgs b) {
-    __shared__ double scratch[2 * (kBeadBlock / 64)];
+__global__ void __launch_bounds__(kBatchBeadBlock) batch_bead_kernel(BatchArgs b) {
+    __shared__ double scratch[2 * (kBeadLanes / 64)];
     __shared__ double s_R[2];
     const int item = blockIdx.x;
     if (item >= b.counts[2]) return;
     const int s = item_sim(b.bead_sim, item);
     const int s_off = ((const ConstInt*)b.bead_off)[s];
     const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    bead_block<ST, kBatchBeadVelBatch>(a, item - s_off, 1, 1 - a.parity, scratch, s_R);
+    bead_block<ST, kBatchBeadVelBatch, kBatchBeadBlock>(a, item - s_off, 1, 1 - a.parity,
+                                                        scratch, s_R);
 }
 
 // Excluded-volume forces of every bead at the step's start (one block).
@@ -1135,10 +1170,10 @@ __device__ inline double phi_at_node(const StepArgs& a, double Rx, double Ry, in
     return phi_f64(sqrt(r2), a.fib.a, a.fib.xi);
 }
 
-__global__ void __launch_bounds__(kBeadBlock)
+__global__ void __launch_bounds__(kStatsBlock)
 particle_stats_kernel(StepArgs a, int b, NodeBox B, const double* __restrict__ fields,
                       double* __restrict__ out) {
-    __shared__ double scratch[kBeadBlock / 64];
+    __shared__ double scratch[kStatsBlock / 64];
     const int tid = threadIdx.x;
     const int nx = a.L.nx, ny = a.L.ny;
     const bool per = a.L.periodic != 0;
@@ -1339,7 +1374,8 @@ static hipError_t launch_batch_t(const BatchArgs& b, dim3 block, int spt, const 
         if (e != hipSuccess) return e;
     }
     if (counts[2] > 0)
-        hipLaunchKernelGGL((batch_bead_kernel<ST>), dim3(counts[2]), dim3(kBeadBlock), 0, st, b);
+        hipLaunchKernelGGL((batch_bead_kernel<ST>), dim3(counts[2]), dim3(kBatchBeadBlock), 0, st,
+                           b);
     return hipGetLastError();
 }
 
@@ -1432,7 +1468,7 @@ hipError_t launch_particle_stats(int storage, const StepArgs& a, int bead, const
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(particle_stats_kernel, dim3(1), dim3(kBeadBlock), 0, st, a, bead, B,
+    hipLaunchKernelGGL(particle_stats_kernel, dim3(1), dim3(kStatsBlock), 0, st, a, bead, B,
                        (const double*)fields, out);
     return hipGetLastError();
 }
