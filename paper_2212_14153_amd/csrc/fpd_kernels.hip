@@ -777,6 +777,22 @@ __device__ inline void box_node(const Fiber& fib, int t, int total, int i0, int 
     }
 }
 
+// This bead's share of the next support window and of the occupancy bitmap (slot
+// win_out), from its position: integer atomics, so the result does not depend on the
+// order in which beads finish.
+__device__ inline void publish_support(const Fiber& fib, int win_out, double Rx, double Ry,
+                                       int nx, int ny, bool per) {
+    if (!bead_sane(Rx, Ry)) return;
+    int* nw = fib.bs->win[win_out];
+    const int lo = (int)floor(Rx - 0.5 - fib.rc), hi = (int)ceil(Rx - 0.5 + fib.rc);
+    const int jlo = (int)floor(Ry - 0.5 - fib.rc), jhi = (int)ceil(Ry - 0.5 + fib.rc);
+    atomicMin(&nw[0], lo);
+    atomicMax(&nw[1], hi);
+    atomicMin(&nw[2], jlo);
+    atomicMax(&nw[3], jhi);
+    occ_mark(fib, win_out, lo, hi, jlo, jhi, nx, ny, per);
+}
+
 // One block per bead.  With do_velocity: V_i^{n+1} = sum_x phi_i^n (j^{n+1} + f^n / 2) /
 // rho^{n+1} / A_i^n over the bead's support box (Eq. 5, FP64 sums), then the Euler update
 // R_i^{n+1} = R_i^n + V_i^{n+1}.  Always: A_i = sum_x phi_i at the (new) position.
@@ -882,6 +898,8 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
             s_R[1] = Ry + Vy;
             bs->R[b][0] = s_R[0];
             bs->R[b][1] = s_R[1];
+            // issued now, its atomics complete while the block sums A_i
+            publish_support(fib, win_out, s_R[0], s_R[1], nx, ny, per);
         }
         __syncthreads();
         Rx = s_R[0];
@@ -907,18 +925,9 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     const double A_new = lanes_sum<R>(sa, scratch);
     if (tid == 0) {
         bs->A[b] = A_new;
-        // this bead's share of the next support window and its health bits
-        int* nw = bs->win[win_out];
-        if (bead_sane(Rx, Ry)) {
-            const int lo = (int)floor(Rx - 0.5 - fib.rc), hi = (int)ceil(Rx - 0.5 + fib.rc);
-            const int jlo = (int)floor(Ry - 0.5 - fib.rc), jhi = (int)ceil(Ry - 0.5 + fib.rc);
-            atomicMin(&nw[0], lo);
-            atomicMax(&nw[1], hi);
-            atomicMin(&nw[2], jlo);
-            atomicMax(&nw[3], jhi);
-            occ_mark(fib, win_out, lo, hi, jlo, jhi, nx, ny, per);
-        }
+        // the support window (after the Euler update, else here) and the health bits
         if (!do_velocity) {
+            publish_support(fib, win_out, Rx, Ry, nx, ny, per);
             Vx = bs->V[b][0];
             Vy = bs->V[b][1];
         }
