@@ -173,8 +173,12 @@ __device__ inline double y_image(double dy, int ny, bool per) {
 __device__ inline double phi_f64(double r, double a, double xi) {
     return 1.0 / (1.0 + exp(2.0 * (r - a) / xi));
 }
+// FP32 (the FP32 and two-byte storage paths): the hardware 2^x, reciprocal and square root
+// (PhiEval), each within about one ulp, instead of the correctly rounded library forms (the
+// fiber tiles evaluate phi for every nearby bead at every node).
 __device__ inline float phi_f32(float r, float a, float inv_xi) {
-    return 1.0f / (1.0f + expf(2.0f * (r - a) * inv_xi));
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * (r - a) * inv_xi);  // 2 log2(e)
+    return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
 template <typename T> struct PhiEval;
@@ -198,7 +202,7 @@ template <> struct PhiEval<double> {
 // support boxes, so whether a node sees a bead never depends on the tiling.
 template <> struct PhiEval<float> {
     __device__ static inline float of_r2(double r2, double a, double, double inv_xi) {
-        return phi_f32(sqrtf((float)r2), (float)a, (float)inv_xi);
+        return phi_f32(__builtin_amdgcn_sqrtf((float)r2), (float)a, (float)inv_xi);
     }
     __device__ static inline float eval(double dx, double dy, double rc2, double a, double xi,
                                         double inv_xi) {

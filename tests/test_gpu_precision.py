@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 # storage: (max |u - u_oracle| / U, max |R - R_oracle| in lu) after 1000 steps.  Measured on
 # MI355X: f32 1.7e-5 U / 9.6e-6 lu; over six starts shifted by 0 .. 5e-7 lu, f16dev
-# 0.9-1.2e-3 U / 1.0-3.7e-4 lu and bf16dev 1.0-1.5e-2 U / 1.4-2.5e-3 lu (the two-byte
+# 0.9-1.2e-3 U / 0.9-3.7e-4 lu and bf16dev 1.0-1.5e-2 U / 1.4-2.5e-3 lu (the two-byte
 # rounding makes the bead error of one start vary by an order of magnitude).
 BOUNDS = {"f32": (5e-5, 1e-4), "f16dev": (5e-3, 2e-3), "bf16dev": (5e-2, 5e-3)}
 
