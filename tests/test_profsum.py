@@ -6,6 +6,8 @@ import csv
 import importlib.util
 import json
 import os
+import subprocess
+import sys
 
 from paper_2212_14153_amd import profsum
 
@@ -81,3 +83,9 @@ def test_committed_traffic_entries_name_their_workload():
     for storage, ent in rec["entries"].items():
         assert ent["workload"] == "c3" and f"--storage {storage}" in ent["command"]
         assert ent["bytes_per_launch"] == ent["read_bytes_per_launch"] + ent["write_bytes_per_launch"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=60, cwd=ROOT)
+    assert out.returncode == 2 and "one GPU only" in out.stderr and out.stdout == ""
