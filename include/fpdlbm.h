@@ -270,6 +270,42 @@ int fpd_copy_probe(void *hip_stream, size_t bytes, int32_t iters, double *gbps);
 int fpd_save(fpd_sim *s, const char *path);
 int fpd_load(fpd_sim *s, const char *path);
 
+/* ---------------------------------------------------- no device allocation ---- */
+/* For callers that cannot allocate device memory: code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  fpd_run_static runs one simulation of p for
+ * n_steps steps with the results of fpd_create_with_buffers + fpd_init_fiber + fpd_step
+ * (bitwise the same populations and bead positions) but calls no allocator: the bead state
+ * and the force-density window live in a device array of FPD_STATIC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends.
+ *   f_a, f_b   caller-owned device buffers of bytes_each >= fpd_population_bytes(p) bytes,
+ *              16-byte aligned, holding populations in the library's storage format.  The
+ *              state is read from f_a; after the call it sits in f_a if n_steps is even,
+ *              in f_b if it is odd (the other buffer is overwritten).
+ *   init_populations  non-zero: first write the initial state of p->init_flow into f_a
+ *              (what fpd_create_with_buffers writes there).
+ *   R_in       device [n_beads][2]: the bead positions to start from (read on the stream
+ *              before any step; NULL when n_beads = 0).
+ *   R_out      device [n_beads][2]: receives the positions after n_steps (may be R_in).
+ *   health     device uint32 or NULL: receives the FPD_HEALTH_* bits of this call; bead
+ *              positions fpd_init_fiber would refuse show here (e.g. FPD_HEALTH_WALL).
+ *   hip_stream hipStream_t, NULL for the null stream.  The call only enqueues work.
+ * FPD_EINVAL, with nothing enqueued, if p is invalid, a buffer is missing, too small or
+ * misaligned, or the bead state and force window need more than FPD_STATIC_SCRATCH_BYTES
+ * (fpd_static_scratch_need gives the size: one fiber whose window side
+ * 1.5 (N - 1) l_0 + 2 (a + cutoff xi) + 4 is up to about 720 nodes in FP64 and 1020
+ * otherwise; several fibers up to about 0.5M (FP64) or 1M lattice nodes).
+ * Every call on a device uses that device's one array, which keeps the last call's
+ * contents (each call clears what it needs): calls that overlap on one device, from other
+ * streams or threads, race and give wrong results. */
+#define FPD_STATIC_SCRATCH_BYTES 8388608
+
+/* Bytes of the static scratch array that fpd_run_static needs for p (0 without beads). */
+size_t fpd_static_scratch_need(const fpd_params *p);
+
+int fpd_run_static(const fpd_params *p, void *hip_stream, void *f_a, void *f_b,
+                   size_t bytes_each, int32_t init_populations, const double *R_in,
+                   double *R_out, uint32_t *health, int64_t n_steps);
+
 /* ------------------------------------------------------------------ batch ---- */
 /* A batch holds independent simulations of different lattice sizes (one storage format)
  * and advances all active ones together: each step is one forces kernel (a block per

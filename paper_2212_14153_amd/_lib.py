@@ -99,6 +99,11 @@ SIGNATURES = [
     ("fpd_copy_probe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, _D]),
     ("fpd_save", ctypes.c_int, [_SIM, ctypes.c_char_p]),
     ("fpd_load", ctypes.c_int, [_SIM, ctypes.c_char_p]),
+    ("fpd_static_scratch_need", ctypes.c_size_t, [ctypes.POINTER(fpd_params)]),
+    ("fpd_run_static", ctypes.c_int,
+     [ctypes.POINTER(fpd_params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_int64]),
     ("fpd_sim_footprint", ctypes.c_size_t, [ctypes.POINTER(fpd_params)]),
     ("fpd_batch_create", ctypes.c_int,
      [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_SIM)]),
@@ -146,6 +151,13 @@ def lib():
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
                 " or `python paper_2212_14153_amd/build.py`")
+        # torch ships its own HIP runtime.  Loading it first makes the library bind to that
+        # runtime (the same soname) in a process that also uses torch; loaded the other way
+        # round, the process would hold two HIP runtimes and torch's would find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             fn = getattr(L, name)
@@ -192,6 +204,26 @@ def fpd_copy_probe(stream, nbytes: int, iters: int) -> float:
     out = ctypes.c_double()
     check(lib().fpd_copy_probe(stream, nbytes, iters, ctypes.byref(out)))
     return out.value
+
+
+FPD_STATIC_SCRATCH_BYTES = 8388608
+
+
+def fpd_static_scratch_need(p: fpd_params) -> int:
+    return int(lib().fpd_static_scratch_need(ctypes.byref(p)))
+
+
+def fpd_run_static(p: fpd_params, stream, f_a, f_b, bytes_each: int, init_populations: bool,
+                   R_in, R_out, health, n_steps: int):
+    """fpd_run_static on device addresses (integers or objects with data_ptr(), e.g. torch
+    tensors; R_in, R_out and health may be None)."""
+    def addr(x):
+        if x is None:
+            return None
+        return x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+    check(lib().fpd_run_static(ctypes.byref(p), stream, addr(f_a), addr(f_b), int(bytes_each),
+                               1 if init_populations else 0, addr(R_in), addr(R_out),
+                               addr(health), int(n_steps)))
 
 
 def params_from_mapping(m, storage=None, **over) -> fpd_params:

@@ -168,6 +168,17 @@ hipError_t launch_stream_out(int storage, const Lattice& L, double u_wall, const
                              double* f64, hipStream_t st);
 hipError_t launch_init_eq(const Lattice& L, double u_wall, int init_flow, double* f64,
                           hipStream_t st);
+// allocation-free set-up (fpd_run_static): the initial state written straight into a
+// population buffer (the values init_eq + unstream give), an 8-byte zero fill (bytes a
+// multiple of 8), a fresh fiber from device positions R [n][2] into a zeroed bead state,
+// and positions (device [n][2]) plus health bits (device, may be NULL) out of a bead state
+hipError_t launch_init_state(int storage, const Lattice& L, double u_wall, int init_flow,
+                             void* dst, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_fiber_setup(BeadState* bs, const double* R, int n, double ev_k, double ev_d,
+                              hipStream_t st);
+hipError_t launch_beads_out(const BeadState* bs, int n, double* R, unsigned* health,
+                            hipStream_t st);
 hipError_t launch_fields(int storage, const StepArgs& a, double* rho, double* ux,
                          double* uy, double* eta, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);

@@ -1073,20 +1073,92 @@ __global__ void stream_out_kernel(Lattice L, double u_wall, const typename Codec
     for (int k = 0; k < 9; ++k) f64[k * S_ + (long long)y * L.nx + x] = lattice_w(k) + g[k];
 }
 
+// Initial flow of row y: u = 0 or u_x = U (2 y / H - 1) (node centres).
+__device__ inline double init_ux(const Lattice& L, double u_wall, int init_flow, int y) {
+    return init_flow == FPD_INIT_LINEAR_COUETTE
+               ? u_wall * (2.0 * ((double)y + 0.5) / (double)L.ny - 1.0)
+               : 0.0;
+}
+
+// Equilibrium f_k at rho = 1 and velocity (ux, 0).  The one expression every kernel that
+// writes an initial state uses, so they all round alike.
+__device__ inline double init_feq(int k, double ux) {
+    const double eu = ex_of(k) * ux;
+    return lattice_w(k) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * ux * ux);
+}
+
 // Equilibrium f at rho = 1 and u = 0 or u_x = U (2 y / H - 1).
 __global__ void init_eq_kernel(Lattice L, double u_wall, int init_flow, double* f64) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= L.nx || y >= L.ny) return;
-    const double ux = init_flow == FPD_INIT_LINEAR_COUETTE
-                          ? u_wall * (2.0 * ((double)y + 0.5) / (double)L.ny - 1.0)
-                          : 0.0;
+    const double ux = init_ux(L, u_wall, init_flow, y);
     const long long S = (long long)L.nx * L.ny;
+    for (int k = 0; k < 9; ++k) f64[k * S + (long long)y * L.nx + x] = init_feq(k, ux);
+}
+
+// The initial state straight into a population buffer, with no FP64 staging array: the
+// post-collision values whose pull gives the equilibrium of init_eq_kernel (what
+// unstream_kernel makes of that kernel's output, value for value).  The equilibrium does
+// not depend on x, so a pulled value needs only the row it comes from.
+template <int ST>
+__global__ void init_state_kernel(Lattice L, double u_wall, int init_flow,
+                                  typename Codec<ST>::store_t* __restrict__ dst) {
+    using Cd = Codec<ST>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= L.nx || y >= L.ny) return;
     for (int k = 0; k < 9; ++k) {
-        const double eu = ex_of(k) * ux;
-        f64[k * S + (long long)y * L.nx + x] =
-            lattice_w(k) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * ux * ux);
+        int yd = y + ey_of(k);
+        if (L.periodic) yd = imod(yd, L.ny);
+        double v;
+        if (yd >= 0 && yd < L.ny) {
+            v = init_feq(k, init_ux(L, u_wall, init_flow, yd)) - lattice_w(k);
+        } else {
+            const int kb = opp_of(k);
+            const double uw = ey_of(kb) > 0 ? -u_wall : u_wall;
+            v = init_feq(kb, init_ux(L, u_wall, init_flow, y)) - lattice_w(kb) -
+                6.0 * lattice_w(kb) * ex_of(kb) * uw;
+        }
+        dst[k * L.plane + (long long)y * L.stride + x] = Cd::from_f64(v);
     }
+}
+
+// 8-byte zero fill (a kernel rather than a memset, so the fill can sit in a captured graph).
+__global__ void zero_kernel(unsigned long long* __restrict__ p, size_t n) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// A fresh fiber in a zeroed bead state: positions from R (device [n][2]), empty support
+// windows (the bead kernel then fills one), the excluded-volume constants.
+__global__ void fiber_setup_kernel(BeadState* bs, const double* __restrict__ R, int n,
+                                   double ev_k, double ev_d) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        bs->R[i][0] = R[2 * i];
+        bs->R[i][1] = R[2 * i + 1];
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 2; ++k) {
+            bs->win[k][0] = 0x7fffffff;
+            bs->win[k][1] = -0x7fffffff;
+            bs->win[k][2] = 0x7fffffff;
+            bs->win[k][3] = -0x7fffffff;
+        }
+        bs->ev_k = ev_k;
+        bs->ev_d = ev_d;
+    }
+}
+
+// Bead positions (device [n][2]) and, if asked, the health bits out of a bead state (no
+// bead state, n = 0: health 0).
+__global__ void beads_out_kernel(const BeadState* bs, int n, double* __restrict__ R,
+                                 unsigned* health) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        R[2 * i] = bs->R[i][0];
+        R[2 * i + 1] = bs->R[i][1];
+    }
+    if (threadIdx.x == 0 && health) *health = bs ? bs->health : 0u;
 }
 
 // rho, u = (j + f^n/2)/rho and eta^n at node (x, y) from the current state (F/A of every
@@ -1448,6 +1520,42 @@ hipError_t launch_stream_out(int storage, const Lattice& L, double u_wall, const
 hipError_t launch_init_eq(const Lattice& L, double u_wall, int init_flow, double* f64,
                           hipStream_t st) {
     hipLaunchKernelGGL(init_eq_kernel, site_grid(L), dim3(128), 0, st, L, u_wall, init_flow, f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(int storage, const Lattice& L, double u_wall, int init_flow,
+                             void* dst, hipStream_t st) {
+    const dim3 grid = site_grid(L), block(128);
+    switch (storage) {
+        case FPD_F64: hipLaunchKernelGGL((init_state_kernel<FPD_F64>), grid, block, 0, st, L, u_wall, init_flow, (double*)dst); break;
+        case FPD_F32: hipLaunchKernelGGL((init_state_kernel<FPD_F32>), grid, block, 0, st, L, u_wall, init_flow, (float*)dst); break;
+        case FPD_F16DEV: hipLaunchKernelGGL((init_state_kernel<FPD_F16DEV>), grid, block, 0, st, L, u_wall, init_flow, (_Float16*)dst); break;
+        case FPD_BF16DEV: hipLaunchKernelGGL((init_state_kernel<FPD_BF16DEV>), grid, block, 0, st, L, u_wall, init_flow, (uint16_t*)dst); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 8;
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (unsigned long long*)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fiber_setup(BeadState* bs, const double* R, int n, double ev_k, double ev_d,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(fiber_setup_kernel, dim3(1), dim3(kBeadThreads), 0, st, bs, R, n, ev_k,
+                       ev_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_beads_out(const BeadState* bs, int n, double* R, unsigned* health,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(beads_out_kernel, dim3(1), dim3(kBeadThreads), 0, st, bs, n, R, health);
     return hipGetLastError();
 }
 

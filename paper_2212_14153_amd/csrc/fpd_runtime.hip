@@ -13,6 +13,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1516,6 +1517,126 @@ int fpd_batch_stats(fpd_batch* b, int32_t* active, int32_t* held, size_t* bytes_
     if (active) *active = a;
     if (held) *held = (int)b->entries.size();
     if (bytes_in_use) *bytes_in_use = b->used;
+    return FPD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- allocation-free entry ----
+//
+// fpd_run_static runs one simulation on caller-owned population buffers with the bead
+// state and the force-density window in `scratch`, a file-scope device array of fixed
+// size: it calls no allocator.  Each device holds its own copy of the array (at its own
+// address, looked up once per device with hipGetSymbolAddress) until the process ends, and
+// every call on a device shares it.
+
+static __device__ __align__(256) unsigned char scratch[FPD_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kScratchBeadBytes = (sizeof(BeadState) + 255) / 256 * 256;
+static_assert(FPD_STATIC_SCRATCH_BYTES % 256 == 0 &&
+                  kScratchBeadBytes < (size_t)FPD_STATIC_SCRATCH_BYTES,
+              "the bead state must fit the static scratch array");
+
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of this device's scratch array (the host-side name is only a stand-in).
+int scratch_ptr(unsigned char** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(FPD_EDEVICE, "device %d beyond the %d the static scratch supports", dev,
+                    kMaxDevices);
+    std::call_once(g_scratch_once[dev], [dev] {
+        g_scratch_err[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return fail(FPD_EDEVICE, "hipGetSymbolAddress(scratch): %s",
+                    hipGetErrorString(g_scratch_err[dev]));
+    *out = (unsigned char*)g_scratch_ptr[dev];
+    return FPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fpd_static_scratch_need(const fpd_params* p) {
+    if (!p || p->n_beads <= 0) return 0;
+    const double rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) *
+                                      p->xi;
+    int w = 0, h = 0;
+    window_size(p, rc, w, h);
+    const size_t tb = p->storage == FPD_F64 ? 8 : 4;
+    return kScratchBeadBytes + (size_t)w * (size_t)h * 2 * tb;
+}
+
+int fpd_run_static(const fpd_params* p, void* hip_stream, void* f_a, void* f_b,
+                   size_t bytes_each, int32_t init_populations, const double* R_in,
+                   double* R_out, uint32_t* health, int64_t n_steps) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
+    if (!f_a || !f_b) return fail(FPD_EINVAL, "buffers must not be NULL");
+    if (((uintptr_t)f_a | (uintptr_t)f_b) & 15)
+        return fail(FPD_EINVAL, "buffers must be 16-byte aligned");
+    const size_t need_buf = fpd_population_bytes(p);
+    if (bytes_each < need_buf)
+        return fail(FPD_EINVAL, "buffers of %zu bytes, %zu needed", bytes_each, need_buf);
+    const int N = p->n_beads;
+    if (N > 0 && (!R_in || !R_out)) return fail(FPD_EINVAL, "R_in and R_out are required");
+    const size_t need = fpd_static_scratch_need(p);
+    if (need > (size_t)FPD_STATIC_SCRATCH_BYTES)
+        return fail(FPD_EINVAL,
+                    "bead state and force window need %zu bytes of static scratch; the "
+                    "maximum is %zu (FPD_STATIC_SCRATCH_BYTES)",
+                    need, (size_t)FPD_STATIC_SCRATCH_BYTES);
+    unsigned char* base = nullptr;
+    rc = scratch_ptr(&base);
+    if (rc) return rc;
+
+    // a simulation record on the stack: nothing below allocates
+    fpd_sim s;
+    s.p = *p;
+    s.L.nx = p->nx;
+    s.L.ny = p->ny;
+    s.L.plane = padded_stride(p->nx);
+    s.L.stride = 9 * padded_stride(p->nx);
+    s.L.periodic = p->boundary == FPD_PERIODIC ? 1 : 0;
+    s.elem = storage_elem(p->storage);
+    s.buf_bytes = need_buf;
+    s.buf[0] = f_a;
+    s.buf[1] = f_b;
+    s.own_bufs = false;
+    s.cur = 0;
+    s.stream = (hipStream_t)hip_stream;
+    s.rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
+    s.launch = default_launch(p->storage, 64);
+    if (init_populations)
+        HIP_TRY(launch_init_state(p->storage, s.L, p->u_wall, p->init_flow, f_a, s.stream));
+    if (N > 0) {
+        s.bs = (BeadState*)base;
+        s.rect_f = base + kScratchBeadBytes;
+        window_size(p, s.rc, s.rect_wmax, s.rect_hmax);
+        // the state a new simulation starts from: everything zero (the earlier call's
+        // contents are not used), then the fiber as fpd_init_fiber sets it
+        HIP_TRY(launch_zero(base, need, s.stream));
+        const double ev_k = chains_of(p) > 1 ? p->ev_k : 0.0;
+        const double ev_d = p->ev_range > 0.0 ? p->ev_range : 2.0 * p->radius;
+        HIP_TRY(launch_fiber_setup(s.bs, R_in, N, ev_k, ev_d, s.stream));
+        s.fiber = true;
+        HIP_TRY(launch_bead(p->storage, make_args(&s, 0), 0, 0, s.stream));
+    }
+    for (int64_t i = 0; i < n_steps; ++i) {
+        rc = enqueue_step(&s, s.cur);
+        if (rc) return rc;
+        s.cur = 1 - s.cur;
+    }
+    if (N > 0 || health) HIP_TRY(launch_beads_out(s.bs, N, R_out, health, s.stream));
     return FPD_OK;
 }
 
