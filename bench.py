@@ -2,21 +2,33 @@
 """Throughput of the FPD fiber time step on one MI355X (arXiv:2212.14153, Sec. II.C).
 
 Default workload: the 8192 x 2048 (16.8M nodes) confined-Couette channel with a 40-bead
-fiber of radius 4 (Re_ps = 5, K = 3.3), FP32 populations, 2000 steps.  One "step" is the
-whole path: the fused pull-stream + MRT-collide lattice kernel (with phi/eta/force density
-near the fiber) and the per-bead kernel (Eq. 5 reduction, Euler update, A_i, forces).
+fiber of radius 4 (Re_ps = 5, K = 3.3), FP32 populations.  One "step" is the whole path:
+the fused pull-stream + MRT-collide lattice kernel (with phi/eta/force density near the
+fiber) and the per-bead kernel (Eq. 5 reduction, Euler update, A_i, forces).  The timed
+steps replay captured graphs (the chunk divides the timed step count; the graph is captured
+before the timing starts).
 
 Prints ONE JSON line with MLUPS (whole step, inputs resident in HBM), the lattice kernel's
-HBM roofline (algorithmic 18 * sizeof(population) bytes per node per step over its event
-time) and a CPU baseline (the FP64 oracle on a bounded sample of the same workload).
+HBM roofline (algorithmic 18 * sizeof(population) bytes per node per step over its
+dispatch-stamped duration) and a CPU baseline (the FP64 oracle on a bounded sample of the
+same workload).  Bounded runs of the other configurations are added as keys of the same
+line (skip them with --no-extras):
+  c2          the 1024 x 256 channel with the 20-bead fiber, FP32: MLUPS and effective GB/s
+              (its two 9.4 MB buffers stay in the 256 MB Infinity Cache: not an HBM figure);
+  sweep_c4    256 parameter-sweep simulations (128x64 .. 1024x512, 5-30 beads) advanced
+              together by the batch kernels with autotuned tiles, against the plain path
+              (a seeded random sample of them run one at a time, per-step launches, no
+              graph, measured);
+  serve_c5    Poisson arrivals of sweep simulations (20k steps each, FP16 deviation
+              storage) served with continuous batching, at 50 requests/s and at 0.8 of the
+              measured capacity: p50/p99 time-to-result and sims/s, against a measured
+              first-in-first-out server of single simulations on the same arrivals;
+  cpu_baseline_set  the oracle on C1 (1000 steps), C2 (1000 steps) and C3 in FP64 (20 steps).
 
 Other modes (each prints one JSON line):
-  --mode batch   256 parameter-sweep simulations (uneven lattices 128x64..1024x512, 5-30
-                 beads) advanced together by the batch kernels, against the plain
-                 path (the same simulations one at a time, per-step launches, no graph);
-  --mode serve   Poisson arrivals (50 requests/s) of sweep simulations served with
-                 continuous batching in FP16/BF16 deviation storage: p50/p99 time-to-result
-                 and simulations per second, against a single-simulation FIFO server;
+  --mode batch   the full C4 sweep (256 simulations, 20k steps each) against the plain path;
+  --mode serve   the full C5 run (1000 requests after 100 warm-up at 50/s) against a
+                 measured FIFO server of single simulations on a prefix of the arrivals;
   --mode particle  the driven-particle benchmark of Sec. III.B (periodic box, H = 10 d,
                  d = 20) swept over 64 driving forces in one batch (90k steps): C_d(Re_p), eps_v,
                  the diffuse-interface drag, and throughput;
@@ -82,29 +94,53 @@ def measured_traffic(storage, nodes, workload):
     return ent.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """The host CPU's full model name (the longer of lscpu's and /proc/cpuinfo's)."""
+    names = []
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        names += [ln.split(":", 1)[1].strip() for ln in out.splitlines()
+                  if ln.startswith("Model name")]
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            names += [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+    except OSError:
+        pass
+    names.append(platform.processor())
+    return max(names, key=len) if names else ""
+
+
 def cpu_baseline(w, steps):
-    import numpy as np  # noqa: F401
+    """The oracle, single-threaded, on `steps` FP64 steps of workload w after one untimed
+    step (page-in)."""
     import oracle
     p = oracle.OracleParams.from_mapping(w.params())
     st = oracle.make_state(p, w.init_flow, w.beads())
-    oracle.run(st, 1)                      # first step outside the timing (page-in)
+    oracle.run(st, 1)
     t0 = time.perf_counter()
     oracle.run(st, steps)
     dt = time.perf_counter() - t0
-    model = ""
-    try:
-        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
-        for line in out.splitlines():
-            if line.startswith("Model name"):
-                model = line.split(":", 1)[1].strip()
-    except Exception:
-        model = platform.processor()
     return {
-        "value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+        "value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+        "kind": "oracle",
         "sample": f"{w.nx}x{w.ny} lattice with the {w.n_beads}-bead fiber, {steps} FP64 steps "
                   f"after one untimed step, single-threaded C oracle ({dt:.1f} s)",
-        "cpu_model": model, "host_cpus": os.cpu_count(),
+        "seconds": round(dt, 2), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
     }
+
+
+def cpu_baseline_set(jobs):
+    """cpu_baseline of several (label, workload, steps) at once, one thread each (the C
+    oracle releases the interpreter lock; each run still uses one core)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    oracle.lib()
+    oracle.inverse_moments([1.0] + [0.0] * 8)   # the oracle's lazy table, before threads
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        futs = {label: ex.submit(cpu_baseline, w, n) for label, w, n in jobs}
+        return {label: f.result() for label, f in futs.items()}
 
 
 def sweep_params(_lib, ws, storage, steps_override=None):
@@ -112,7 +148,8 @@ def sweep_params(_lib, ws, storage, steps_override=None):
 
 
 def run_plain_path(_lib, ws, storage, steps, stream):
-    """The plain path: one simulation at a time, one launch per kernel, no graph."""
+    """The plain path: one simulation at a time, one launch per kernel, no graph; the time of
+    each simulation's steps (creation excluded) and its final beads."""
     times, finals = [], []
     for w in ws:
         sim = _lib.simulation_from_workload(w, storage=storage, stream=stream,
@@ -127,20 +164,19 @@ def run_plain_path(_lib, ws, storage, steps, stream):
     return times, finals
 
 
-def main_batch(args):
+def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153):
+    """C4: `sims` sweep simulations advanced together by the batch kernels (graph replay,
+    launch shape from the autotuner), against the plain path measured on a seeded random
+    sample of `plain_sims` of them.  Returns the result keys."""
     import numpy as np
-    import torch
     import workloads
     from paper_2212_14153_amd import _lib, autotune
-    torch.cuda.init()
-    stream = torch.cuda.Stream()
-    storage = args.storage
-    ws = workloads.sweep_sims(args.sims, steps=args.sweep_steps, storage=storage)
+    ws = workloads.sweep_sims(sims, seed=seed, steps=steps, storage=storage)
     params = sweep_params(_lib, ws, storage)
     nodes = sum(w.nx * w.ny for w in ws)
     budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
-    log(f"batch: {len(ws)} simulations, {nodes / 1e6:.1f}M nodes, {args.sweep_steps} steps "
-        f"each, storage {storage}, {budget / 1e9:.2f} GB")
+    log(f"sweep: {len(ws)} simulations, {nodes / 1e6:.1f}M nodes, {steps} steps each, "
+        f"storage {storage}, {budget / 1e9:.2f} GB")
 
     def make_batch():
         b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
@@ -148,104 +184,163 @@ def main_batch(args):
             b.add(p, w.beads(), 1 << 40)
         return b
 
-    cfg, table = (None, None)
-    if not args.no_autotune:
-        cfg, table = autotune.tune_batch(make_batch, storage, nodes)
+    cfg = None
+    if tune:
+        cfg, _ = autotune.tune_batch(make_batch, storage, nodes)
         log(f"autotuned launch {cfg}")
     b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
     if cfg:
         b.set_launch(dict(cfg, graph_chunk=32))
-    ids = [b.add(p, w.beads(), args.sweep_steps) for p, w in zip(params, ws)]
-    torch.cuda.synchronize()
+    ids = [b.add(p, w.beads(), steps) for p, w in zip(params, ws)]
+    stream.synchronize()
     t0 = time.perf_counter()
     finish = {}
     while len(finish) < len(ids):
-        if b.run(args.sweep_steps) == 0:
+        if b.run(steps) == 0:
             break
         t = time.perf_counter() - t0
         for sid, st in b.poll():
             finish[sid] = (t, st)
     wall = time.perf_counter() - t0
     ok = sum(1 for t, st in finish.values() if st == _lib.FPD_SIM_DONE)
-    k = min(args.plain_sims, len(ws))
-    batch_R = [b.beads(sid)[0] for sid in ids[:k]]
+    rng = np.random.default_rng(seed + 1)
+    pick = sorted(rng.choice(len(ws), size=min(plain_sims, len(ws)), replace=False).tolist())
+    batch_R = [b.beads(ids[i])[0] for i in pick]
     b.close()
-    log(f"batched: {wall:.2f} s for {len(ids)} simulations ({ok} done)")
-    plain_t, plain_R = run_plain_path(_lib, ws[:k], storage, args.sweep_steps, stream.cuda_stream)
+    log(f"batched: {wall:.2f} s for {len(ids)} simulations ({ok} done); plain path on "
+        f"{len(pick)} of them")
+    plain_t, plain_R = run_plain_path(_lib, [ws[i] for i in pick], storage, steps,
+                                      stream.cuda_stream)
     plain_per_sim = float(np.mean(plain_t))
+    # the sample's share of the sweep's work, to scale its time to all simulations
+    frac = sum(ws[i].nx * ws[i].ny for i in pick) / nodes
+    plain_all_s = float(np.sum(plain_t)) / frac
     diff = max(float(np.max(np.abs(a - c))) for a, c in zip(batch_R, plain_R))
-    lat = np.array([t for t, _ in finish.values()])
-    out = {
-        "metric": "batched sims/s", "value": round(ok / wall, 3), "unit": "sims/s",
-        "n_gpus": 1, "steps": args.sweep_steps, "warmup": 0, "ms_per_step": round(wall / args.sweep_steps * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": storage,
-        "data": "synthetic",
-        "config": {"workload": f"sweep of {len(ws)} simulations (seed 14153), {args.sweep_steps} steps each",
-                   "nodes_total": nodes, "launch": cfg, "parallelism": "single GPU"},
-        "aggregate_mlups": round(nodes * args.sweep_steps / wall / 1e6, 1),
-        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-        "plain_path": {"sims_per_s": round(1.0 / plain_per_sim, 3), "sample_sims": k,
-                       "seconds_per_sim": round(plain_per_sim, 4)},
-        "speedup_vs_plain": round((ok / wall) * plain_per_sim, 2),
+    log(f"plain path: {plain_per_sim * 1e3:.1f} ms per simulation; batch == alone: "
+        f"max bead difference {diff:.1e} lu")
+    return {
+        "workload": f"sweep of {len(ws)} simulations (seed {seed}), 128x64..1024x512, "
+                    f"{steps} steps each, {storage}",
+        "sims": len(ws), "steps": steps, "nodes_total": nodes, "launch": cfg,
+        "sims_per_s": round(ok / wall, 3), "seconds": round(wall, 3),
+        "aggregate_mlups": round(nodes * steps / wall / 1e6, 1),
+        "ms_per_batch_step": round(wall / steps * 1e3, 4),
+        "plain_path": {"sample_sims": len(pick), "sample_seed": seed + 1,
+                       "seconds_per_sim": round(plain_per_sim, 4),
+                       "sims_per_s": round(len(pick) / float(np.sum(plain_t)), 3),
+                       "all_sims_seconds_scaled_by_nodes": round(plain_all_s, 2)},
+        "speedup_vs_plain": round(plain_all_s / wall, 2),
         "max_bead_diff_vs_plain_lu": diff,
     }
+
+
+def plain_fifo(_lib, ws, arrivals, steps, storage, stream):
+    """The plain path as a server, measured: requests in arrival order, one simulation at a
+    time (created on arrival, per-step launches, no graph); time-to-result = finish -
+    arrival.  Returns the latencies, the span from the first arrival to the last finish,
+    and the final beads."""
+    import numpy as np
+    t0 = time.perf_counter()
+    lat, finals = [], []
+    for w, a in zip(ws, arrivals):
+        now = time.perf_counter() - t0
+        if now < a:
+            time.sleep(a - now)
+        sim = _lib.simulation_from_workload(w, storage=storage, stream=stream,
+                                            flags=_lib.FPD_FLAG_NO_GRAPH)
+        sim.step(steps)
+        sim.sync()
+        finals.append(sim.beads()[0])
+        sim.close()
+        lat.append(time.perf_counter() - t0 - a)
+    span = time.perf_counter() - t0 - float(arrivals[0])
+    return np.array(lat), span, finals
+
+
+def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512, chunk=200,
+              budget_gb=64, seed=50):
+    """C5 at one arrival rate: `n_req` Poisson arrivals of sweep simulations served with
+    continuous batching, and the first `n_plain` of the same arrivals through the measured
+    plain FIFO server.  Returns the result keys (p50 / p99 over the requests after
+    `warmup`, and both paths over the same first n_plain requests)."""
+    import numpy as np
+    import workloads
+    from paper_2212_14153_amd import _lib, serve
+    ws = workloads.sweep_sims(n_req, seed=seed, steps=steps, storage=storage)
+    arrivals = workloads.poisson_arrivals(n_req, rate=rate, seed=seed)
+    params = sweep_params(_lib, ws, storage)
+    reqs = [serve.Request(i, p, w.beads(), steps, float(t))
+            for i, (p, w, t) in enumerate(zip(params, ws, arrivals))]
+    log(f"serve: {n_req} requests at {rate:.1f}/s, {steps} steps each, storage {storage}")
+    srv = serve.Server(storage, hbm_budget=budget_gb << 30, max_slots=slots, chunk=chunk,
+                       stream=stream.cuda_stream, launch=dict(graph_chunk=32))
+    done = srv.serve(reqs)
+    srv.close()
+    summ = serve.summarize(done, warmup=warmup)
+    by_id = {r.rid: r for r in done}
+    head = [by_id[i] for i in range(n_plain)]
+    lat_head = np.array([r.latency for r in head])
+    log(f"served: p50 {summ['p50_s']:.2f} s, p99 {summ['p99_s']:.2f} s, "
+        f"{summ['sims_per_s']:.1f} sims/s; plain FIFO on the first {n_plain}")
+    lat_p, span_p, R_p = plain_fifo(_lib, ws[:n_plain], arrivals[:n_plain], steps, storage,
+                                    stream.cuda_stream)
+    diff = max(float(np.max(np.abs(r.beads - R)))
+               for r, R in zip(head, R_p) if r.beads is not None)
+    log(f"plain FIFO: p50 {np.percentile(lat_p, 50):.2f} s, p99 "
+        f"{np.percentile(lat_p, 99):.2f} s, {n_plain / span_p:.2f} sims/s")
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3)  # noqa: E731
+    return {
+        "rate_per_s": round(rate, 3), "requests": n_req - warmup, "warmup": warmup,
+        "completed": summ["completed"], "sims_per_s": round(summ["sims_per_s"], 3),
+        "p50_s": round(summ["p50_s"], 3), "p99_s": round(summ["p99_s"], 3),
+        "mean_s": round(summ["mean_s"], 3), "span_s": round(summ["span_s"], 2),
+        "first_requests": n_plain,
+        "served_first": {"p50_s": pct(lat_head, 50), "p99_s": pct(lat_head, 99)},
+        "plain_fifo_first": {"p50_s": pct(lat_p, 50), "p99_s": pct(lat_p, 99),
+                             "sims_per_s": round(n_plain / span_p, 3),
+                             "measured": "single simulations in arrival order, per-step "
+                                         "launches, no graph"},
+        "max_bead_diff_alone_vs_mix_lu": diff,
+    }
+
+
+def main_batch(args):
+    import torch
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    r = sweep_run(stream, args.storage, args.sims, args.sweep_steps, args.plain_sims,
+                  tune=not args.no_autotune)
+    out = {
+        "metric": "batched sims/s", "value": r["sims_per_s"], "unit": "sims/s",
+        "n_gpus": 1, "steps": args.sweep_steps, "warmup": 0,
+        "ms_per_step": r["ms_per_batch_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": r["workload"], "nodes_total": r["nodes_total"],
+                   "launch": r["launch"], "parallelism": "single GPU"},
+    }
+    out.update({k: v for k, v in r.items() if k not in ("workload", "launch")})
     print(json.dumps(out), flush=True)
 
 
 def main_serve(args):
-    import numpy as np
     import torch
-    import workloads
-    from paper_2212_14153_amd import _lib, autotune, serve
     torch.cuda.init()
     stream = torch.cuda.Stream()
     storage = args.storage if args.storage in ("f16dev", "bf16dev") else "f16dev"
-    n_req = args.requests + args.serve_warmup
-    ws = workloads.sweep_sims(n_req, seed=50, steps=args.sweep_steps, storage=storage)
-    arrivals = workloads.poisson_arrivals(n_req, rate=args.rate, seed=50)
-    params = sweep_params(_lib, ws, storage)
-    reqs = [serve.Request(i, p, w.beads(), args.sweep_steps, float(t))
-            for i, (p, w, t) in enumerate(zip(params, ws, arrivals))]
-    log(f"serve: {n_req} requests at {args.rate}/s ({args.serve_warmup} warm-up), "
-        f"{args.sweep_steps} steps each, storage {storage}")
-    srv = serve.Server(storage, hbm_budget=args.hbm_budget_gb << 30, max_slots=args.slots,
-                       chunk=args.chunk, stream=stream.cuda_stream,
-                       launch=dict(graph_chunk=32))
-    done = srv.serve(reqs)
-    srv.close()
-    summ = serve.summarize(done, warmup=args.serve_warmup)
-    log(f"served: p50 {summ['p50_s']:.2f} s, p99 {summ['p99_s']:.2f} s, "
-        f"{summ['sims_per_s']:.1f} sims/s")
-    # plain path: measured service times of a sample, a FIFO single-simulation server replayed
-    # on the same arrivals with service time linear in nodes x steps
-    k = min(args.plain_sims, len(ws))
-    pt, pR = run_plain_path(_lib, ws[:k], storage, args.sweep_steps, stream.cuda_stream)
-    sizes = np.array([w.nx * w.ny for w in ws[:k]], dtype=float)
-    A = np.stack([np.ones(k), sizes], axis=1)
-    coef, *_ = np.linalg.lstsq(A, np.array(pt), rcond=None)
-    svc = coef[0] + coef[1] * np.array([w.nx * w.ny for w in ws], dtype=float)
-    lat_plain = serve.fifo_replay(arrivals, svc)[args.serve_warmup:]
-    # alone vs in the mix: the served results of the sampled requests equal the plain runs
-    by_id = {r.rid: r for r in done}
-    diff = max(float(np.max(np.abs(by_id[i].beads - pR[i]))) for i in range(k))
+    r = serve_run(stream, storage, args.requests + args.serve_warmup, args.sweep_steps,
+                  args.rate, args.plain_requests, warmup=args.serve_warmup, slots=args.slots,
+                  chunk=args.chunk, budget_gb=args.hbm_budget_gb)
     out = {
-        "metric": "served sims/s at p50/p99 time-to-result", "value": round(summ["sims_per_s"], 3),
+        "metric": "served sims/s at p50/p99 time-to-result", "value": r["sims_per_s"],
         "unit": "sims/s", "n_gpus": 1, "steps": args.sweep_steps, "warmup": args.serve_warmup,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": storage, "data": "synthetic",
-        "config": {"workload": f"Poisson {args.rate}/s sweep requests (seed 50), {args.sweep_steps} steps",
-                   "requests": args.requests, "chunk": args.chunk, "slots": args.slots,
+        "config": {"workload": f"Poisson {args.rate}/s sweep requests (seed 50), "
+                               f"{args.sweep_steps} steps", "requests": args.requests,
+                   "chunk": args.chunk, "slots": args.slots,
                    "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
-        "p50_s": round(summ["p50_s"], 3), "p99_s": round(summ["p99_s"], 3),
-        "mean_s": round(summ["mean_s"], 3), "span_s": round(summ["span_s"], 2),
-        "completed": summ["completed"],
-        "plain_path": {"p50_s": round(float(np.percentile(lat_plain, 50)), 3),
-                       "p99_s": round(float(np.percentile(lat_plain, 99)), 3),
-                       "sims_per_s": round(1.0 / float(np.mean(svc)), 3),
-                       "service_model": "FIFO replay, service time fitted on "
-                                        f"{k} measured single-simulation runs"},
-        "max_bead_diff_alone_vs_mix_lu": diff,
     }
+    out.update(r)
     print(json.dumps(out), flush=True)
 
 
@@ -519,15 +614,96 @@ def main_shapes(args):
     print(json.dumps(out), flush=True)
 
 
+def choose_chunk(steps: int):
+    """Graph chunk for `steps` timed steps: the largest even c <= 64 that divides steps (then
+    every timed step runs in a replayed graph); for odd steps the largest even c <= 64 below
+    steps (the last step then runs as direct launches); None below two steps."""
+    for c in range(min(64, steps), 1, -1):
+        if c % 2 == 0 and steps % c == 0:
+            return c
+    c = min(64, steps - steps % 2)
+    return c if c >= 2 else None
+
+
+def timed_path(steps: int, chunk):
+    """What fpd_step does with `steps` steps and graph chunk `chunk`."""
+    replays = steps // chunk if chunk and steps >= chunk else 0
+    direct = steps - replays * (chunk or 0)
+    return {"graph_chunk": chunk, "graph_replays": replays, "direct_steps": direct}
+
+
+def time_steps(sim, stream, steps, warmup):
+    """Warm-up, capture of the graph the timed steps replay, then `steps` timed steps
+    (events on the simulation's stream); returns ms per step and the timed path."""
+    import torch
+    chunk = choose_chunk(steps)
+    if chunk:
+        sim.set_launch(dict(graph_chunk=chunk))
+    sim.step(warmup)
+    sim.sync()
+    sim.capture(steps)          # outside the timed region
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    sim.sync()
+    return e0.elapsed_time(e1) / steps, timed_path(steps, chunk)
+
+
+def kernel_pass(sim, steps):
+    """The same steps again with every lattice and bead launch stamped by its own dispatch
+    (FPD_FLAG_TIME_KERNELS): average lattice and bead kernel durations in ms."""
+    from paper_2212_14153_amd import _lib
+    sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
+    sim.reset_kernel_times()
+    sim.step(steps)
+    sim.sync()
+    ms_lat, n_lat, ms_bead, n_bead = sim.kernel_times()
+    sim.set_flags(0)
+    return ms_lat / max(n_lat, 1), (ms_bead / n_bead if n_bead else 0.0)
+
+
+def c2_run(stream, steps=200, warmup=50):
+    """C2 (1024 x 256, 20 beads, FP32): MLUPS and the lattice kernel's effective GB/s.  Both
+    population buffers (2 x 9.4 MB) fit the 256 MB Infinity Cache, so the rate measures the
+    kernel on cache-resident data, not HBM."""
+    from paper_2212_14153_amd import _lib
+    w = workload("c2", "f32")
+    nodes = w.nx * w.ny
+    sim = _lib.simulation_from_workload(w, storage="f32", stream=stream.cuda_stream)
+    ms_step, path = time_steps(sim, stream, steps, warmup)
+    lat_ms, bead_ms = kernel_pass(sim, steps)
+    flags, _ = sim.health()
+    sim.close()
+    eff = 18 * 4 * nodes / (lat_ms * 1e-3) / 1e9
+    log(f"c2: {ms_step * 1e3:.1f} us/step, {nodes / (ms_step * 1e3):.0f} MLUPS, lattice "
+        f"kernel {lat_ms * 1e3:.1f} us = {eff:.0f} GB/s effective (MALL-resident)")
+    return {"workload": w.name, "nx": w.nx, "ny": w.ny, "nodes": nodes, "steps": steps,
+            "warmup": warmup, "dtype": "f32", "timed_path": path,
+            "mlups": round(nodes / (ms_step * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms_step, 5), "lattice_kernel_ms": round(lat_ms, 5),
+            "bead_kernel_ms": round(bead_ms, 5),
+            "effective_gbps": round(eff, 1),
+            "effective_gbps_note": "18 x 4 B per node over the lattice kernel's duration; "
+                                   "the 19 MB working set stays in the 256 MB Infinity "
+                                   "Cache (MALL), so this is not an HBM rate",
+            "health_flags": flags}
+
+
 def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[1])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_VALUE))
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "suspension"])
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no c2, sweep_c4, serve_c5 keys)")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
     ap.add_argument("--mode", default="plain",
                     choices=["plain", "batch", "serve", "particle", "sandwich", "shapes"])
@@ -539,14 +715,22 @@ def main():
     ap.add_argument("--f-max", type=float, default=1e-1)
     ap.add_argument("--sims", type=int, default=256)
     ap.add_argument("--sweep-steps", type=int, default=20000)
-    ap.add_argument("--plain-sims", type=int, default=8)
+    ap.add_argument("--plain-sims", type=int, default=32)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--plain-requests", type=int, default=40)
     ap.add_argument("--slots", type=int, default=512)
     ap.add_argument("--chunk", type=int, default=200)
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
+    # sizes of the bounded runs added to the default line
+    ap.add_argument("--x-sweep-sims", type=int, default=256)
+    ap.add_argument("--x-sweep-steps", type=int, default=2000)
+    ap.add_argument("--x-sweep-plain", type=int, default=64)
+    ap.add_argument("--x-serve-requests", type=int, default=60)
+    ap.add_argument("--x-serve-steps", type=int, default=20000)
+    ap.add_argument("--x-serve-plain", type=int, default=24)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -569,6 +753,7 @@ def main():
     import torch
     from paper_2212_14153_amd import _lib
 
+    t_start = time.perf_counter()
     w = workload(args.workload, args.storage)
     nodes = w.nx * w.ny
     torch.cuda.init()
@@ -578,50 +763,22 @@ def main():
     if args.launch:
         bx, by, spt, xr = (int(v) for v in args.launch.split(","))
         sim.set_launch(dict(block_x=bx, block_y=by, rows_per_thread=spt, xcd_remap=xr))
-    cfg = sim.get_launch()
 
     copy_gbps = _lib.fpd_copy_probe(stream.cuda_stream, 1 << 30, 20)
     log(f"copy probe: {copy_gbps:.0f} GB/s (read + write)")
 
-    # warm-up (also captures the replay graphs)
-    sim.step(args.warmup)
-    sim.sync()
-    torch.cuda.synchronize()
-
-    # timed region: production path (graph replay), whole step
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    e1.synchronize()
-    sim.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
+    # timed region: the production path (captured graphs replayed), whole step
+    ms_step, path = time_steps(sim, stream, args.steps, args.warmup)
+    cfg = sim.get_launch()
     mlups = nodes / (ms_step * 1e-3) / 1e6
-    log(f"graph replay: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS (wall {wall:.2f} s)")
+    how = (f"{path['graph_replays']} graph replays of {path['graph_chunk']} steps"
+           if path["graph_replays"] else "direct launches")
+    if path["graph_replays"] and path["direct_steps"]:
+        how += f" + {path['direct_steps']} direct steps"
+    log(f"{how}: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS")
 
-    # same simulation, the lattice and bead kernels launched one by one with start and
-    # stop events stamped by each dispatch on the simulation's stream
-    sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
-    sim.reset_kernel_times()
-    e2 = torch.cuda.Event(enable_timing=True)
-    e3 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e2.record(stream)
-    sim.step(args.steps)
-    e3.record(stream)
-    e3.synchronize()
-    sim.sync()
-    ms_lat, n_lat, ms_bead, n_bead = sim.kernel_times()
-    sim.set_flags(0)
-    ms_timed_step = e2.elapsed_time(e3) / args.steps
-    lat_ms = ms_lat / max(n_lat, 1)
-    bead_ms = ms_bead / max(n_bead, 1) if n_bead else 0.0
+    # the same simulation, every lattice and bead launch stamped by its own dispatch
+    lat_ms, bead_ms = kernel_pass(sim, args.steps)
     bytes_alg = 18 * BYTES_PER_VALUE[args.storage] * nodes
     achieved = bytes_alg / (lat_ms * 1e-3) / 1e9
     log(f"lattice kernel {lat_ms * 1e3:.1f} us ({achieved:.0f} GB/s), bead kernel "
@@ -638,22 +795,42 @@ def main():
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "nodes": nodes,
                    "n_beads": w.n_beads, "radius": w.radius, "re_ps": w.re_ps,
                    "kappa": w.kappa, "storage": args.storage, "parallelism": "single GPU",
-                   "launch": cfg.__dict__},
+                   "launch": cfg.__dict__, "timed_path": path},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "kernel": "step_kernel",
                      "bytes_per_launch_alg": bytes_alg, "avg_launch_ms": round(lat_ms, 5)},
         "bead_kernel_ms": round(bead_ms, 5),
-        "ms_per_step_instrumented": round(ms_timed_step, 5),
         "copy_probe_gbps": round(copy_gbps, 1),
         "frac_of_copy_probe": round(achieved / copy_gbps, 4),
         "health_flags": flags, "max_bond_strain": strain,
     }
+    if not args.no_extras and args.workload == "c3":
+        out["c2"] = c2_run(stream)
+        out["sweep_c4"] = sweep_run(stream, "f32", args.x_sweep_sims, args.x_sweep_steps,
+                                    args.x_sweep_plain)
+        at50 = serve_run(stream, "f16dev", args.x_serve_requests, args.x_serve_steps, 50.0,
+                         args.x_serve_plain)
+        cap = at50["sims_per_s"]
+        at08 = serve_run(stream, "f16dev", args.x_serve_requests, args.x_serve_steps,
+                         0.8 * cap, args.x_serve_plain)
+        out["serve_c5"] = {"storage": "f16dev", "steps": args.x_serve_steps,
+                           "capacity_sims_per_s": cap, "at_50_per_s": at50,
+                           "at_0.8_capacity": at08}
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle, {args.cpu_steps} steps of {w.name} in FP64")
-        out["cpu_baseline"] = cpu_baseline(w.with_(storage="f64"), args.cpu_steps)
+        head = f"{args.workload}_f64"
+        jobs = [(head, w.with_(storage="f64"), args.cpu_steps)]
+        if not args.no_extras and args.workload == "c3":
+            jobs += [("c1_f64", workload("c1", "f64"), 1000),
+                     ("c2_f64", workload("c2", "f64"), 1000)]
+        log("cpu baseline: the oracle on " + ", ".join(f"{n} ({k} steps)" for n, _, k in jobs))
+        res = cpu_baseline_set(jobs)
+        out["cpu_baseline"] = res[head]
+        if len(jobs) > 1:
+            out["cpu_baseline_set"] = res
     else:
         out["cpu_baseline"] = None
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

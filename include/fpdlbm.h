@@ -174,6 +174,13 @@ int fpd_init_fiber_line(fpd_sim *s, double cx, double cy, double theta);
 /* Enqueue n_steps >= 0 time steps on the simulation's stream (asynchronous). */
 int fpd_step(fpd_sim *s, int64_t n_steps);
 
+/* Capture now, without running any step, the graph that fpd_step(s, n_steps) replays
+ * (steps are replayed in captured chunks of graph_chunk steps when n_steps >= graph_chunk
+ * and neither FPD_FLAG_NO_GRAPH nor FPD_FLAG_TIME_KERNELS is set; otherwise there is
+ * nothing to capture and the call does nothing), so that the capture cost stays out of a
+ * timed fpd_step.  Synchronous with respect to the host; enqueues no work. */
+int fpd_capture(fpd_sim *s, int64_t n_steps);
+
 /* Wait for the stream; FPD_EUNSTABLE if a health bit is set. */
 int fpd_sync(fpd_sim *s);
 

@@ -75,6 +75,7 @@ SIGNATURES = [
     ("fpd_init_fiber", ctypes.c_int, [_SIM, _D]),
     ("fpd_init_fiber_line", ctypes.c_int, [_SIM, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     ("fpd_step", ctypes.c_int, [_SIM, ctypes.c_int64]),
+    ("fpd_capture", ctypes.c_int, [_SIM, ctypes.c_int64]),
     ("fpd_sync", ctypes.c_int, [_SIM]),
     ("fpd_health", ctypes.c_int, [_SIM, ctypes.POINTER(ctypes.c_uint32), _D]),
     ("fpd_clear_health", ctypes.c_int, [_SIM]),
@@ -315,6 +316,10 @@ class Simulation:
 
     def step(self, n: int):
         check(lib().fpd_step(self.h, int(n)))
+
+    def capture(self, n: int):
+        """Capture the graph that step(n) replays, without running a step."""
+        check(lib().fpd_capture(self.h, int(n)))
 
     def sync(self):
         check(lib().fpd_sync(self.h))

@@ -309,6 +309,16 @@ __device__ inline GroupRaw<G> group_load(const uint16_t* __restrict__ row, int x
     return r;
 }
 
+// Whole-wave moves by one lane (DPP wave_shr:1 / wave_shl:1 of the gfx9 family: one VALU
+// move each, no LDS permute): lane i receives lane i - 1's value (shr) or lane i + 1's
+// (shl); the lane with no source (0, resp. 63) receives 0 and takes its value from memory.
+__device__ inline uint32_t wave_shr1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ inline uint32_t wave_shl1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+
 template <class Cd, int G, int SX>
 __device__ inline void group_finish(const GroupRaw<G>& r, int x0, int nx, bool first,
                                     bool last, typename Cd::T v[G]) {
@@ -317,13 +327,13 @@ __device__ inline void group_finish(const GroupRaw<G>& r, int x0, int nx, bool f
 #pragma unroll
         for (int i = 0; i < G; ++i) v[i] = Cd::from_bits(r.elem(i));
     } else if (SX == 1) {
-        uint32_t l = (uint32_t)__shfl_up((int)r.elem(G - 1), 1);  // x0 - 1: left lane's last
+        uint32_t l = wave_shr1(r.elem(G - 1));  // x0 - 1: left lane's last
         if (in && (first || x0 == 0)) l = r.e;
         v[0] = Cd::from_bits(l);
 #pragma unroll
         for (int i = 1; i < G; ++i) v[i] = Cd::from_bits(r.elem(i - 1));
     } else {
-        uint32_t rr = (uint32_t)__shfl_down((int)r.elem(0), 1);  // x0 + G: right lane's first
+        uint32_t rr = wave_shl1(r.elem(0));  // x0 + G: right lane's first
         if (in && x0 + G - 1 < nx && (last || x0 + G >= nx)) rr = r.e;
 #pragma unroll
         for (int i = 0; i < G - 1; ++i)

@@ -83,11 +83,11 @@ void window_size(const fpd_params* p, double rc, int& w, int& h) {
 }
 
 // Launch shapes measured best on MI355X at 8192 x 2048 (default block order, no XCD remap):
-// 128 x 2 for float64, 256 x 1 for float32, 64 x 4 with two rows per thread for the
-// two-byte formats (whose lanes update two nodes each).
+// 128 x 2 for float64, 256 x 1 for float32, 256 x 1 with two rows per thread for the
+// two-byte formats (whose lanes update two nodes each: 512-node tiles).
 fpd_launch default_launch(int storage, int graph_chunk) {
     if (storage == FPD_F64) return fpd_launch{128, 2, 1, 2, graph_chunk};
-    if (nodes_per_lane(storage) > 1) return fpd_launch{64, 4, 2, 2, graph_chunk};
+    if (nodes_per_lane(storage) > 1) return fpd_launch{256, 1, 2, 2, graph_chunk};
     return fpd_launch{256, 1, 1, 2, graph_chunk};
 }
 
@@ -578,6 +578,37 @@ int fpd_init_fiber_line(fpd_sim* s, double cx, double cy, double theta) {
     return fpd_init_fiber(s, R.data());
 }
 
+}  // extern "C"
+
+namespace {
+
+// Whether fpd_step(n) replays graphs, and the graph it replays captured (nothing runs).
+int ensure_graph(fpd_sim* s, int64_t n, bool* replay) {
+    const int chunk = s->launch.graph_chunk;
+    *replay = !(s->p.flags & (FPD_FLAG_NO_GRAPH | FPD_FLAG_TIME_KERNELS)) && chunk >= 2 &&
+              n >= chunk;
+    if (!*replay) return FPD_OK;
+    if (s->graph_chunk != chunk) {
+        drop_graphs(s);
+        s->graph_chunk = chunk;
+    }
+    if (!s->graph[s->cur]) return build_graph(s, s->cur, chunk, &s->graph[s->cur]);
+    return FPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fpd_capture(fpd_sim* s, int64_t n) {
+    if (!s) return fail(FPD_EINVAL, "NULL simulation");
+    if (n < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
+    if (s->p.n_beads > 0 && !s->fiber)
+        return fail(FPD_ESTATE, "fpd_init_fiber must come before fpd_capture");
+    bool replay = false;
+    return ensure_graph(s, n, &replay);
+}
+
 int fpd_step(fpd_sim* s, int64_t n) {
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     if (n < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
@@ -593,15 +624,10 @@ int fpd_step(fpd_sim* s, int64_t n) {
     }
     int64_t left = n;
     const int chunk = s->launch.graph_chunk;
-    if (!(fl & FPD_FLAG_NO_GRAPH) && chunk >= 2 && left >= chunk) {
-        if (s->graph_chunk != chunk) {
-            drop_graphs(s);
-            s->graph_chunk = chunk;
-        }
-        if (!s->graph[s->cur]) {
-            int rc = build_graph(s, s->cur, chunk, &s->graph[s->cur]);
-            if (rc) return rc;
-        }
+    bool replay = false;
+    int rg = ensure_graph(s, n, &replay);
+    if (rg) return rg;
+    if (replay) {
         while (left >= chunk) {
             HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
             left -= chunk;  // chunk is even: the state returns to the same buffer

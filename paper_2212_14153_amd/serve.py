@@ -29,6 +29,7 @@ class Request:
     finished: float = float("nan")
     status: int = -1
     beads: np.ndarray = field(default=None)   # final R
+    populations: np.ndarray = field(default=None)   # final f[9, ny, nx] (if asked for)
     sim_id: int = 0
 
     @property
@@ -40,14 +41,18 @@ class Server:
     """Admission by slots and HBM footprint; chunked execution; read-back on completion."""
 
     def __init__(self, storage: str, hbm_budget: int, max_slots: int, chunk: int = 200,
-                 stream=None, launch=None, clock=time.perf_counter, batch=None):
+                 stream=None, launch=None, clock=time.perf_counter, batch=None,
+                 read_populations: bool = False):
         # `batch` may be any object with the Batch methods used below (try_add, run, poll,
-        # beads, release, set_launch, close); by default the device batch of the C ABI
+        # beads, release, set_launch, close; populations if read_populations); by default
+        # the device batch of the C ABI.  read_populations: read every finished
+        # simulation's populations back too (Request.populations).
         self.batch = batch if batch is not None else _lib.Batch(hbm_budget, max_slots,
                                                                  storage=storage, stream=stream)
         if launch:
             self.batch.set_launch(launch)
         self.chunk = int(chunk)
+        self.read_populations = bool(read_populations)
         self.clock = clock
         self.t0 = None
         self.waiting = collections.deque()
@@ -79,6 +84,8 @@ class Server:
             req.status = status
             if status == _lib.FPD_SIM_DONE:
                 req.beads = self.batch.beads(sid)[0]
+                if self.read_populations:
+                    req.populations = self.batch.populations(sid)
             req.finished = self.now()
             self.batch.release(sid)
             self.done.append(req)

@@ -3,7 +3,8 @@ benchmark times (the default launch shape, steps replayed from a captured graph)
 
   * 8192 x 2048 channel with the 40-bead fiber (16.8M nodes), FP64 and FP32 storage: every
     population and every bead after two coupled steps against the FP64 oracle on the same
-    lattice (the oracle needs about 2.5 s per step here);
+    lattice (the oracle needs about 2.5 s per step here); FP16 / BF16 deviation storage
+    against the same oracle state within the storage rounding;
   * 1024 x 256 channel with the 20-bead fiber: every population after 100 steps;
   * properties that hold at any size, over the benchmark's 2000 steps at 8192 x 2048: total
     mass is conserved (tangential walls, mass-preserving collision), and the fiber centred
@@ -22,6 +23,8 @@ from paper_2212_14153_amd import _lib
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-5}
+# two-byte deviation storage: significant bits of binary16 / bfloat16
+BITS = {"f16dev": 11, "bf16dev": 8}
 
 
 def rel_err(a, b):
@@ -51,6 +54,34 @@ def test_c3_full_size_two_steps_match_oracle(c3_oracle, storage):
     tol_r = 1e-12 if storage == "f64" else 1e-6
     assert np.max(np.abs(R - c3_oracle.R)) <= tol_r
     assert np.max(np.abs(V - c3_oracle.V)) <= tol_r
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_c3_full_size_two_steps_two_byte_storage(c3_oracle, storage):
+    """The two-byte formats at full size in the benchmark's launch shape: every population
+    within the storage rounding of the oracle's, as for the small lattices (11 / 8
+    significant bits, two roundings per step: the written state and each stored result,
+    a factor 2 of slack), and the beads within the rounding that reaches Eq. (5): a
+    momentum component sums six populations, each off by at most that bound."""
+    w = workloads.c3_large(storage)
+    print(f"[case] c3 full size {w.nx}x{w.ny} N={w.n_beads} storage={storage}", flush=True)
+    p = oracle.OracleParams.from_mapping(w.params())
+    steps = 2
+    # largest deviation |f - w| of the state (the rest state is f = w), with 50 % margin
+    gmax = 1.5 * float(np.abs(c3_oracle.f - oracle.init(p, 0)).max())
+    with _lib.simulation_from_workload(w, storage=storage) as sim:
+        sim.set_launch(dict(graph_chunk=2))
+        sim.step(steps)
+        sim.sync()
+        f = sim.populations()
+        R, V, _ = sim.beads()
+    tol = 2.0 * (steps + 1) * gmax * 2.0 ** -BITS[storage]
+    err = float(np.max(np.abs(f - c3_oracle.f)))
+    print(f"[c3 {storage}] population err {err:.3e} (bound {tol:.3e})", flush=True)
+    assert err <= tol
+    tol_v = 6.0 * tol
+    assert np.max(np.abs(V - c3_oracle.V)) <= tol_v
+    assert np.max(np.abs(R - c3_oracle.R)) <= steps * tol_v
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])

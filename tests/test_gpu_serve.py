@@ -1,5 +1,6 @@
 """Continuous batching on the GPU: requests arriving while others run are admitted as
-slots free up, and each result equals the same simulation run alone, bitwise."""
+slots free up, and each result (bead positions and every population) equals the same
+simulation run alone, bitwise."""
 import numpy as np
 import pytest
 
@@ -18,7 +19,7 @@ def test_served_results_equal_alone(storage):
                           300 if i % 3 else 150, float(t))
             for i, (w, t) in enumerate(zip(ws, arrivals))]
     srv = serve.Server(storage, hbm_budget=1 << 34, max_slots=4, chunk=40,
-                       launch=dict(graph_chunk=8))
+                       launch=dict(graph_chunk=8), read_populations=True)
     done = srv.serve(reqs)
     srv.close()
     assert len(done) == len(reqs)
@@ -29,3 +30,4 @@ def test_served_results_equal_alone(storage):
         with _lib.simulation_from_workload(ws[r.rid], storage=storage) as sim:
             sim.step(r.steps)
             assert np.array_equal(sim.beads()[0], r.beads)
+            assert np.array_equal(sim.populations(), r.populations)   # the whole fluid too

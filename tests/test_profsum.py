@@ -89,3 +89,19 @@ def test_bench_refuses_more_than_one_gpu():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=60, cwd=ROOT)
     assert out.returncode == 2 and "one GPU only" in out.stderr and out.stdout == ""
+
+
+def test_graph_chunk_covers_the_timed_steps():
+    """The timed steps replay captured graphs: the chunk is even, at most 64 and divides the
+    step count when an even divisor exists; odd counts leave their last step direct."""
+    bench = load_bench()
+    assert bench.choose_chunk(20) == 20 and bench.choose_chunk(2000) == 50
+    assert bench.choose_chunk(128) == 64 and bench.choose_chunk(6) == 6
+    assert bench.choose_chunk(1) is None
+    assert bench.timed_path(20, 20) == {"graph_chunk": 20, "graph_replays": 1, "direct_steps": 0}
+    assert bench.timed_path(2000, 50)["graph_replays"] == 40
+    c = bench.choose_chunk(25)
+    assert c == 24 and bench.timed_path(25, c) == {"graph_chunk": 24, "graph_replays": 1,
+                                                   "direct_steps": 1}
+    assert bench.timed_path(1, None) == {"graph_chunk": None, "graph_replays": 0,
+                                         "direct_steps": 1}

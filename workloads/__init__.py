@@ -173,6 +173,26 @@ def sweep_sims(count: int = 256, seed: int = 14153, steps: int = 20000,
     return out
 
 
+def sweep_sim_at_height(ny: int, seed: int, steps: int = 20000,
+                        storage: str = "f32") -> Workload:
+    """One simulation of the parameter sweep (sweep_sims) at a given channel height: N, C,
+    Re_ps and K drawn from the sweep's distributions (tuples with a < 2 drawn again),
+    N_x = 2 N_y, the same mapping to lattice units."""
+    rng = np.random.default_rng(seed)
+    while True:
+        n = int(rng.integers(5, 31))
+        conf = float(rng.uniform(0.2, 0.8))
+        re = float(rng.uniform(1.0, 10.0))
+        kappa = float(10.0 ** rng.uniform(-3.0, 1.0))
+        l0 = conf * ny / n
+        if l0 / 2.0 >= 2.0:
+            break
+    u = min(max(re / (15.0 * conf * conf * ny), 1e-3), 0.05)
+    return _make(f"sweep_{2 * ny}x{ny}_s{seed}", nx=2 * ny, ny=ny, n_beads=n, radius=l0 / 2.0,
+                 l0=l0, u_wall=u, re_ps=re, kappa=kappa, theta0=math.pi / 4, steps=steps,
+                 storage=storage)
+
+
 def flexible_fiber(kappa: float, confinement: float, re_ps: float, n_beads: int = 10,
                    diameter: float = 8.0, gamma: float = 1.5e-4, eta_ratio: float = 100.0,
                    xi: float = 1.0, theta0: float = 0.0, storage: str = "f32",
