@@ -209,6 +209,16 @@ def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153):
     b.close()
     log(f"batched: {wall:.2f} s for {len(ids)} simulations ({ok} done); plain path on "
         f"{len(pick)} of them")
+    out = {
+        "workload": f"sweep of {len(ws)} simulations (seed {seed}), 128x64..1024x512, "
+                    f"{steps} steps each, {storage}",
+        "sims": len(ws), "steps": steps, "nodes_total": nodes, "launch": cfg,
+        "sims_per_s": round(ok / wall, 3), "seconds": round(wall, 3),
+        "aggregate_mlups": round(nodes * steps / wall / 1e6, 1),
+        "ms_per_batch_step": round(wall / steps * 1e3, 4),
+    }
+    if not pick:
+        return out
     plain_t, plain_R = run_plain_path(_lib, [ws[i] for i in pick], storage, steps,
                                       stream.cuda_stream)
     plain_per_sim = float(np.mean(plain_t))
@@ -218,20 +228,15 @@ def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153):
     diff = max(float(np.max(np.abs(a - c))) for a, c in zip(batch_R, plain_R))
     log(f"plain path: {plain_per_sim * 1e3:.1f} ms per simulation; batch == alone: "
         f"max bead difference {diff:.1e} lu")
-    return {
-        "workload": f"sweep of {len(ws)} simulations (seed {seed}), 128x64..1024x512, "
-                    f"{steps} steps each, {storage}",
-        "sims": len(ws), "steps": steps, "nodes_total": nodes, "launch": cfg,
-        "sims_per_s": round(ok / wall, 3), "seconds": round(wall, 3),
-        "aggregate_mlups": round(nodes * steps / wall / 1e6, 1),
-        "ms_per_batch_step": round(wall / steps * 1e3, 4),
+    out.update({
         "plain_path": {"sample_sims": len(pick), "sample_seed": seed + 1,
                        "seconds_per_sim": round(plain_per_sim, 4),
                        "sims_per_s": round(len(pick) / float(np.sum(plain_t)), 3),
                        "all_sims_seconds_scaled_by_nodes": round(plain_all_s, 2)},
         "speedup_vs_plain": round(plain_all_s / wall, 2),
         "max_bead_diff_vs_plain_lu": diff,
-    }
+    })
+    return out
 
 
 def plain_fifo(_lib, ws, arrivals, steps, storage, stream):

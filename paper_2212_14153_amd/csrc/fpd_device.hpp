@@ -27,6 +27,7 @@ template <> struct Codec<FPD_F64> {
     using store_t = double;
     using T = double;
     __device__ static inline T load(const store_t* p) { return *p; }
+    __device__ static inline T load_nt(const store_t* p) { return __builtin_nontemporal_load(p); }
     __device__ static inline void store(store_t* p, T v) { __builtin_nontemporal_store(v, p); }
     __device__ static inline double to_f64(store_t v) { return v; }
     __device__ static inline store_t from_f64(double v) { return v; }
@@ -36,6 +37,7 @@ template <> struct Codec<FPD_F32> {
     using store_t = float;
     using T = float;
     __device__ static inline T load(const store_t* p) { return *p; }
+    __device__ static inline T load_nt(const store_t* p) { return __builtin_nontemporal_load(p); }
     __device__ static inline void store(store_t* p, T v) { __builtin_nontemporal_store(v, p); }
     __device__ static inline double to_f64(store_t v) { return (double)v; }
     __device__ static inline store_t from_f64(double v) { return (float)v; }
@@ -49,6 +51,9 @@ template <> struct Codec<FPD_F16DEV> {
     static constexpr float kScale = 16384.0f;
     static constexpr float kInv = 1.0f / 16384.0f;
     __device__ static inline T load(const store_t* p) { return (float)(*p) * kInv; }
+    __device__ static inline T load_nt(const store_t* p) {
+        return (float)__builtin_nontemporal_load(p) * kInv;
+    }
     __device__ static inline void store(store_t* p, T v) {
         __builtin_nontemporal_store((_Float16)(v * kScale), p);
     }
@@ -75,6 +80,9 @@ template <> struct Codec<FPD_BF16DEV> {
     using store_t = uint16_t;
     using T = float;
     __device__ static inline T load(const store_t* p) { return bf16_to_f32(*p); }
+    __device__ static inline T load_nt(const store_t* p) {
+        return bf16_to_f32(__builtin_nontemporal_load(p));
+    }
     __device__ static inline void store(store_t* p, T v) {
         __builtin_nontemporal_store(f32_to_bf16(v), p);
     }
@@ -235,12 +243,12 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
     const S* p7 = src + 7 * plane;
     const S* p8 = src + 8 * plane;
     const int r0 = y * stride;
-    g[0] = Cd::load(p0 + r0 + x);
+    g[0] = Cd::load_nt(p0 + r0 + x);
     g[1] = Cd::load(p1 + r0 + xm);
     g[3] = Cd::load(p3 + r0 + xp);
     if (y > 0 || per) {
         const int rm = y > 0 ? r0 - stride : (ny - 1) * stride;
-        g[2] = Cd::load(p2 + rm + x);
+        g[2] = Cd::load_nt(p2 + rm + x);
         g[5] = Cd::load(p5 + rm + xm);
         g[6] = Cd::load(p6 + rm + xp);
     } else {
@@ -250,7 +258,7 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
     }
     if (y < ny - 1 || per) {
         const int rp = y < ny - 1 ? r0 + stride : 0;
-        g[4] = Cd::load(p4 + rp + x);
+        g[4] = Cd::load_nt(p4 + rp + x);
         g[7] = Cd::load(p7 + rp + xp);
         g[8] = Cd::load(p8 + rp + xm);
     } else {
@@ -291,11 +299,15 @@ __device__ inline GroupRaw<G> group_load(const uint16_t* __restrict__ row, int x
     r.e = 0u;
     r.c = 0u;
     if (in) {
+        // rows read without an x shift share no cache line with a neighbouring tile:
+        // non-temporal
         if constexpr (G == 2) {
-            r.w[0] = *(const uint32_t*)(row + x0);
+            const uint32_t* q = (const uint32_t*)(row + x0);
+            r.w[0] = SX == 0 ? __builtin_nontemporal_load(q) : *q;
         } else {
             typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-            const u32x2 v = *(const u32x2*)(row + x0);
+            const u32x2* q = (const u32x2*)(row + x0);
+            const u32x2 v = SX == 0 ? __builtin_nontemporal_load(q) : *q;
             r.w[0] = v.x;
             r.w[1] = v.y;
         }
