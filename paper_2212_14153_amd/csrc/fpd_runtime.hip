@@ -83,10 +83,10 @@ void window_size(const fpd_params* p, double rc, int& w, int& h) {
 }
 
 // Launch shapes measured best on MI355X at 8192 x 2048 (default block order, no XCD remap):
-// 128 x 2 for float64, 256 x 1 for float32, 256 x 1 with two rows per thread for the
+// 128 x 1 for float64, 256 x 1 for float32, 256 x 1 with two rows per thread for the
 // two-byte formats (whose lanes update two nodes each: 512-node tiles).
 fpd_launch default_launch(int storage, int graph_chunk) {
-    if (storage == FPD_F64) return fpd_launch{128, 2, 1, 2, graph_chunk};
+    if (storage == FPD_F64) return fpd_launch{128, 1, 1, 2, graph_chunk};
     if (nodes_per_lane(storage) > 1) return fpd_launch{256, 1, 2, 2, graph_chunk};
     return fpd_launch{256, 1, 1, 2, graph_chunk};
 }
