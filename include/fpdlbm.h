@@ -150,7 +150,8 @@ size_t fpd_population_bytes(const fpd_params *p);
 
 /* ------------------------------------------------------------- lifecycle ----- */
 
-/* Validate p (tau_f > 1/2, |U| < 0.1, N <= FPD_MAX_BEADS, sizes >= 1, rates in (0,2)),
+/* Validate p (tau_f > 1/2, |U| < 0.1, N <= FPD_MAX_BEADS, 1 <= nx < 2^31 / 9,
+ * 1 <= ny <= 65535, rates in (0,2)),
  * allocate device state on the current HIP device, initialise the populations per
  * p->init_flow.  hip_stream is a hipStream_t (NULL: the library creates its own).
  * The fiber is absent until fpd_init_fiber. */

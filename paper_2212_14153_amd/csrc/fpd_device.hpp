@@ -242,12 +242,12 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
     const S* p6 = src + 6 * plane;
     const S* p7 = src + 7 * plane;
     const S* p8 = src + 8 * plane;
-    const int r0 = y * stride;
+    const long long r0 = (long long)y * stride;  // 64-bit: buffers may exceed 2^31 values
     g[0] = Cd::load_nt(p0 + r0 + x);
     g[1] = Cd::load(p1 + r0 + xm);
     g[3] = Cd::load(p3 + r0 + xp);
     if (y > 0 || per) {
-        const int rm = y > 0 ? r0 - stride : (ny - 1) * stride;
+        const long long rm = y > 0 ? r0 - stride : (long long)(ny - 1) * stride;
         g[2] = Cd::load_nt(p2 + rm + x);
         g[5] = Cd::load(p5 + rm + xm);
         g[6] = Cd::load(p6 + rm + xp);
@@ -257,7 +257,7 @@ __device__ inline void pull(const typename Cd::store_t* __restrict__ src, int nx
         g[6] = Cd::load(p8 + r0 + x) + u6;
     }
     if (y < ny - 1 || per) {
-        const int rp = y < ny - 1 ? r0 + stride : 0;
+        const long long rp = y < ny - 1 ? r0 + stride : 0;
         g[4] = Cd::load_nt(p4 + rp + x);
         g[7] = Cd::load(p7 + rp + xp);
         g[8] = Cd::load(p8 + rp + xm);

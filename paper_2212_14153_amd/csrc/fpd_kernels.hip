@@ -1338,14 +1338,16 @@ particle_stats_kernel(StepArgs a, int b, NodeBox B, const double* __restrict__ f
     }
 }
 
-// Plain copy, one 16-byte vector per thread with streaming stores: the fastest of the copy
-// shapes measured on MI355X (grid-stride loops and unrolled variants were 20-35 % slower),
-// so it stands for the bandwidth a kernel can reach; its counters also calibrate traffic.
+// Plain copy, one 16-byte vector per thread, non-temporal loads and stores in 256-thread
+// blocks: the fastest of the copy shapes measured on MI355X (1 GiB: 6.68 TB/s; streaming
+// stores alone 6.36, plain 6.26, four vectors per thread 5.63, 512- and 1024-thread blocks
+// 2-5 % slower, grid-stride loops 20-35 % slower), so it stands for the bandwidth a kernel
+// can reach; its counters also calibrate traffic.
 typedef float copy_vec __attribute__((ext_vector_type(4)));
 __global__ void copy_kernel(const copy_vec* __restrict__ src, copy_vec* __restrict__ dst,
                             size_t n) {
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (i < n) __builtin_nontemporal_store(src[i], dst + i);
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // -------------------------------------------------------------------- launchers ----

@@ -176,8 +176,12 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
 int validate(const fpd_params* p) {
     if (!p) return fail(FPD_EINVAL, "params is NULL");
     if (p->nx < 1 || p->ny < 1) return fail(FPD_EINVAL, "nx, ny must be >= 1");
-    if (9LL * p->ny * padded_stride(p->nx) > 0x7fffffffLL)
-        return fail(FPD_EINVAL, "9 * ny * padded nx must stay below 2^31 values per buffer");
+    // the row pitch (nine padded direction rows) is a 32-bit element count; offsets of rows
+    // are 64-bit, so a buffer may hold more than 2^31 values; the per-row kernels take one
+    // grid row per lattice row (at most 65535)
+    if (9LL * padded_stride(p->nx) > 0x7fffffffLL)
+        return fail(FPD_EINVAL, "nx must stay below 2^31 / 9 (row pitch)");
+    if (p->ny > 65535) return fail(FPD_EINVAL, "ny must be at most 65535");
     if (!(p->nu_f > 0.0) || !(3.0 * p->nu_f + 0.5 > 0.5))
         return fail(FPD_EINVAL, "tau_f = 3 nu_f + 1/2 must exceed 1/2 (nu_f = %g)", p->nu_f);
     if (!(fabs(p->u_wall) < 0.1)) return fail(FPD_EINVAL, "|u_wall| must be < 0.1");

@@ -105,3 +105,20 @@ def test_caller_buffer_arguments():
     assert _lib.buffer_args((4096, 8192, 123)) == (4096, 8192, 123)
     with pytest.raises(ValueError):
         _lib.buffer_args((4096, 8192))
+
+
+def test_lattice_size_limits(L):
+    """The row pitch (nine padded direction rows) must fit 32 bits and ny one grid row per
+    lattice row; the buffer itself may exceed 2^31 values."""
+    from paper_2212_14153_amd import _lib
+    h = ctypes.c_void_p()
+    p = _lib.fpd_params_default()
+    p.nx, p.ny = 16384, 16384                       # 2.4e9 values per buffer: accepted
+    assert _lib.fpd_sim_footprint(p) == 2 * 9 * 16384 * 16384 * 4 + _lib.fpd_sim_footprint(
+        _lib.fpd_params_default()) - 2 * 9 * 32 * 64 * 4
+    p.ny = 65536
+    assert L.fpd_create(ctypes.byref(p), None, ctypes.byref(h)) == _lib.FPD_EINVAL
+    assert b"ny" in L.fpd_last_error()
+    p.ny, p.nx = 8, (1 << 31) // 9
+    assert L.fpd_create(ctypes.byref(p), None, ctypes.byref(h)) == _lib.FPD_EINVAL
+    assert b"nx" in L.fpd_last_error()

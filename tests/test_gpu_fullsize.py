@@ -119,3 +119,27 @@ def test_c3_bench_run_conserves_mass_and_point_symmetry(storage, tol_mass, tol_s
     R0 = w.beads()
     d0, d1 = R0[-1] - R0[0], R[-1] - R[0]
     assert np.arctan2(d1[1], d1[0]) < np.arctan2(d0[1], d0[0])
+
+
+def test_buffer_beyond_2_31_values():
+    """Row offsets are 64-bit: a 16384 x 16384 FP16 lattice holds 2.4e9 values per buffer
+    (rows past 2^31 / (9 x 16384) = 14563 start beyond 2^31).  The flow is uniform in x (a
+    linear Couette start without a fiber), so after two steps every column equals the one
+    column of a 64 x 16384 lattice, bitwise, up to the last row."""
+    ny = 16384
+    base = workloads.c1_small_fp64().with_(n_beads=0, ny=ny, u_wall=0.05, nu_f=0.05)
+    print(f"[case] 16384x{ny} f16dev, 2 steps", flush=True)
+    with _lib.simulation_from_workload(base.with_(nx=64), storage="f16dev") as sim:
+        sim.step(2)
+        sim.sync()
+        _, ref, _, _ = sim.fields()
+    big = base.with_(nx=16384)
+    assert 9 * big.nx * (ny - 1) > 2 ** 31
+    p = _lib.params_from_mapping(big.params(), storage="f16dev")
+    with _lib.Simulation(p) as sim:
+        sim.step(2)
+        sim.sync()
+        ux = np.empty((ny, big.nx))
+        _lib.check(_lib.lib().fpd_read_fields(sim.h, None, _lib._ptr(ux), None, None))
+    assert np.array_equal(ux, np.broadcast_to(ref[:, :1], ux.shape))
+    assert abs(ux[-1, 0]) > 0.9 * 0.05                     # the top row moved with the wall
