@@ -66,6 +66,15 @@ template <> struct Codec<FPD_F16DEV> {
     __device__ static inline uint32_t to_bits(T v) {
         return __builtin_bit_cast(uint16_t, (_Float16)(v * kScale));
     }
+    // The two-node lattice path collides the stored values as they are, g * 2^14
+    // (mrt_collide_scaled): the scale leaves the nine decodes per node.
+    static constexpr bool kScaledCollide = true;
+    __device__ static inline T from_bits_scaled(uint32_t b) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+    }
+    __device__ static inline uint32_t to_bits_scaled(T v) {
+        return __builtin_bit_cast(uint16_t, (_Float16)v);
+    }
 };
 
 // bfloat16 of g, round to nearest even (deviations are finite here).
@@ -90,6 +99,9 @@ template <> struct Codec<FPD_BF16DEV> {
     __device__ static inline store_t from_f64(double v) { return f32_to_bf16((float)v); }
     __device__ static inline T from_bits(uint32_t b) { return bf16_to_f32((uint16_t)b); }
     __device__ static inline uint32_t to_bits(T v) { return f32_to_bf16(v); }
+    static constexpr bool kScaledCollide = false;   // no scale to take out
+    __device__ static inline T from_bits_scaled(uint32_t b) { return from_bits(b); }
+    __device__ static inline uint32_t to_bits_scaled(T v) { return to_bits(v); }
 };
 
 // ------------------------------------------------------------------- helpers --------
@@ -331,30 +343,33 @@ __device__ inline uint32_t wave_shl1(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
 }
 
+// Values in the collision's units: the stored values as they are for a codec that
+// collides scaled (Codec::kScaledCollide), else the deviations g.
 template <class Cd, int G, int SX>
 __device__ inline void group_finish(const GroupRaw<G>& r, int x0, int nx, bool first,
                                     bool last, typename Cd::T v[G]) {
     const bool in = x0 < nx;
     if (SX == 0) {
 #pragma unroll
-        for (int i = 0; i < G; ++i) v[i] = Cd::from_bits(r.elem(i));
+        for (int i = 0; i < G; ++i) v[i] = Cd::from_bits_scaled(r.elem(i));
     } else if (SX == 1) {
         uint32_t l = wave_shr1(r.elem(G - 1));  // x0 - 1: left lane's last
         if (in && (first || x0 == 0)) l = r.e;
-        v[0] = Cd::from_bits(l);
+        v[0] = Cd::from_bits_scaled(l);
 #pragma unroll
-        for (int i = 1; i < G; ++i) v[i] = Cd::from_bits(r.elem(i - 1));
+        for (int i = 1; i < G; ++i) v[i] = Cd::from_bits_scaled(r.elem(i - 1));
     } else {
         uint32_t rr = wave_shl1(r.elem(0));  // x0 + G: right lane's first
         if (in && x0 + G - 1 < nx && (last || x0 + G >= nx)) rr = r.e;
 #pragma unroll
         for (int i = 0; i < G - 1; ++i)
-            v[i] = Cd::from_bits(x0 + i + 1 < nx ? r.elem(i + 1) : r.c);
-        v[G - 1] = Cd::from_bits(rr);
+            v[i] = Cd::from_bits_scaled(x0 + i + 1 < nx ? r.elem(i + 1) : r.c);
+        v[G - 1] = Cd::from_bits_scaled(rr);
     }
 }
 
-// pull() for the group of nodes x0 .. x0 + G - 1 of row y; g[i] receives node x0 + i.
+// pull() for the group of nodes x0 .. x0 + G - 1 of row y; g[i] receives node x0 + i, in
+// the collision's units (group_finish; the wall term u6 comes in the same units).
 template <class Cd, int G>
 __device__ inline void pull_group(const uint16_t* __restrict__ src, int nx, int ny, int stride,
                                   long long plane, int x0, int y, bool per, bool first,
@@ -472,6 +487,72 @@ __device__ inline void mrt_collide(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s
     jy += Fy;
 
     // g = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const T a = drho * T(1.0 / 9.0);
+    const T b = me * T(1.0 / 36.0);
+    const T c = meps * T(1.0 / 36.0);
+    const T d = jx * T(1.0 / 6.0);
+    const T e = qx * T(1.0 / 12.0);
+    const T f = jy * T(1.0 / 6.0);
+    const T h = qy * T(1.0 / 12.0);
+    const T p = pxx * T(0.25);
+    const T q = pxy * T(0.25);
+    const T axis = a - b - T(2) * c;
+    const T diag = a + T(2) * b + c;
+    const T de = d + e, fh = f + h;
+    g[0] = a - T(4) * b + T(4) * c;
+    g[1] = axis + (d - T(2) * e) + p;
+    g[3] = axis - (d - T(2) * e) + p;
+    g[2] = axis + (f - T(2) * h) - p;
+    g[4] = axis - (f - T(2) * h) - p;
+    g[5] = diag + de + fh + q;
+    g[6] = diag - de + fh - q;
+    g[7] = diag - de - fh + q;
+    g[8] = diag + de - fh - q;
+}
+
+// mrt_collide on h = S g, the deviations scaled by S = 2^14 as the FP16 format stores them:
+// the moments of h are S times those of g; rho and u come from the unscaled drho and j, the
+// equilibria and force terms enter scaled by S, and the result is S g*.  The same operator
+// as mrt_collide; the scale leaves the nine decodes and encodes of each node.
+template <typename T>
+__device__ inline void mrt_collide_scaled(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s_eps) {
+    constexpr T S = T(16384), iS = T(1.0 / 16384.0);
+    const T s14 = (g[1] + g[2]) + (g[3] + g[4]);
+    const T s58 = (g[5] + g[6]) + (g[7] + g[8]);
+    const T drho = g[0] + s14 + s58;
+    const T rho = T(1) + drho * iS;
+    const T d13 = g[1] - g[3], d24 = g[2] - g[4];
+    const T a58 = (g[5] - g[7]), b68 = (g[6] - g[8]);
+    T jx = d13 + a58 - b68;
+    T jy = d24 + a58 + b68;
+    T me = T(2) * s58 - s14 - T(4) * g[0];
+    T meps = s58 - T(2) * s14 + T(4) * g[0];
+    T qx = (a58 - b68) - T(2) * d13;
+    T qy = (a58 + b68) - T(2) * d24;
+    T pxx = (g[1] + g[3]) - (g[2] + g[4]);
+    T pxy = (g[5] + g[7]) - (g[6] + g[8]);
+
+    const T Fxs = S * Fx, Fys = S * Fy;       // force density in the scaled units
+    const T inv_rho = T(1) / rho;
+    const T inv_rho_s = iS * inv_rho;
+    const T ux = (jx + T(0.5) * Fxs) * inv_rho_s;
+    const T uy = (jy + T(0.5) * Fys) * inv_rho_s;
+    const T rho_s = S * rho;
+    const T rux = rho_s * ux, ruy = rho_s * uy;   // S rho u
+    const T ru2 = rux * ux + ruy * uy;
+    const T uF = ux * Fxs + uy * Fys;
+
+    me = me - s_e * (me - (T(-2) * drho + T(3) * ru2)) + (T(1) - T(0.5) * s_e) * (T(6) * uF);
+    meps = meps - s_eps * (meps - (drho - T(3) * ru2)) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
+    const T hq = T(1) - T(0.5) * s_q;
+    qx = qx - s_q * (qx + rux) - hq * Fxs;
+    qy = qy - s_q * (qy + ruy) - hq * Fys;
+    const T hn = T(1) - T(0.5) * s_nu;
+    pxx = pxx - s_nu * (pxx - (rux * ux - ruy * uy)) + hn * T(2) * (ux * Fxs - uy * Fys);
+    pxy = pxy - s_nu * (pxy - rux * uy) + hn * (ux * Fys + uy * Fxs);
+    jx += Fxs;
+    jy += Fys;
+
     const T a = drho * T(1.0 / 9.0);
     const T b = me * T(1.0 / 36.0);
     const T c = meps * T(1.0 / 36.0);

@@ -566,7 +566,9 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
     const long long plane = a.L.plane;
     const uint16_t* __restrict__ src = (const uint16_t*)a.src;
     uint16_t* __restrict__ dst = (uint16_t*)a.dst;
-    const T u6 = (T)a.u6;
+    // the pulled values and the collision in the codec's units (scaled for FP16)
+    constexpr bool kScaled = Cd::kScaledCollide;
+    const T u6 = kScaled ? (T)(a.u6 * 16384.0) : (T)a.u6;
     const T s_e = (T)a.s_e, s_eps = (T)a.s_eps;
 
     int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
@@ -632,13 +634,20 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
         uint32_t bits[9][G / 2];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-            if (plain)  // no force anywhere on this tile: the unforced collision
-                mrt_collide<T>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
-            else
-                mrt_collide<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
+            if constexpr (kScaled) {
+                if (plain)
+                    mrt_collide_scaled<T>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+                else
+                    mrt_collide_scaled<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
+            } else {
+                if (plain)  // no force anywhere on this tile: the unforced collision
+                    mrt_collide<T>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+                else
+                    mrt_collide<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
+            }
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const uint32_t b = Cd::to_bits(g[i][k]);
+                const uint32_t b = Cd::to_bits_scaled(g[i][k]);
                 if (i & 1) bits[k][i >> 1] |= b << 16;
                 else bits[k][i >> 1] = b;
             }
