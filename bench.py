@@ -658,11 +658,14 @@ def time_steps(sim, stream, steps, warmup):
     return e0.elapsed_time(e1) / steps, timed_path(steps, chunk)
 
 
-def kernel_pass(sim, steps):
-    """The same steps again with every lattice and bead launch stamped by its own dispatch
-    (FPD_FLAG_TIME_KERNELS): average lattice and bead kernel durations in ms."""
+def kernel_pass(sim, steps, warmup=4):
+    """The same number of steps again with every lattice and bead launch stamped by its own
+    dispatch (FPD_FLAG_TIME_KERNELS), after `warmup` untimed steps in the same mode: average
+    lattice and bead kernel durations in ms."""
     from paper_2212_14153_amd import _lib
     sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
+    sim.step(warmup)
+    sim.sync()
     sim.reset_kernel_times()
     sim.step(steps)
     sim.sync()

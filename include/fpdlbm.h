@@ -150,16 +150,20 @@ size_t fpd_population_bytes(const fpd_params *p);
 
 /* ------------------------------------------------------------- lifecycle ----- */
 
-/* Validate p (tau_f > 1/2, |U| < 0.1, N <= FPD_MAX_BEADS, 1 <= nx < 2^31 / 9,
- * 1 <= ny <= 65535, rates in (0,2)),
- * allocate device state on the current HIP device, initialise the populations per
- * p->init_flow.  hip_stream is a hipStream_t (NULL: the library creates its own).
+/* The problem of Sec. IV.A (Fig. 1b): a channel of nx x ny squares between walls moving
+ * at -U and +U, fluid of viscosity eta_f, fiber beads of radius a and interface xi
+ * (Eqs. 1, 2, 9), on the lattice of Sec. II.C.  Validate p (tau_f > 1/2, |U| < 0.1,
+ * N <= FPD_MAX_BEADS, 1 <= nx < 2^31 / 9, 1 <= ny <= 65535, rates in (0,2); FPD_EINVAL
+ * otherwise), allocate device state on the current HIP device (FPD_ENOMEM when that
+ * fails), initialise the populations per p->init_flow.  hip_stream is a hipStream_t (NULL:
+ * the library creates its own).  The caller owns *out and frees it with fpd_destroy.
  * The fiber is absent until fpd_init_fiber. */
 int fpd_create(const fpd_params *p, void *hip_stream, fpd_sim **out);
 
-/* As fpd_create, but the two population buffers are caller-owned device memory of
- * bytes_each >= fpd_population_bytes(p) bytes each (e.g. torch tensors), 16-byte aligned
- * (FPD_EINVAL otherwise); they must outlive the simulation. */
+/* As fpd_create (the problem of Sec. IV.A), but the two population buffers of the pull
+ * scheme are caller-owned device memory of bytes_each >= fpd_population_bytes(p) bytes
+ * each (e.g. torch tensors), 16-byte aligned (FPD_EINVAL otherwise); the library writes
+ * the initial state into f_a and never frees them; they must outlive the simulation. */
 int fpd_create_with_buffers(const fpd_params *p, void *hip_stream, void *f_a, void *f_b,
                             size_t bytes_each, fpd_sim **out);
 
@@ -172,7 +176,12 @@ int fpd_init_fiber(fpd_sim *s, const double *R);
  * R_i = c + (i - (N + 1)/2) l_0 (cos theta, sin theta), i = 1..N. */
 int fpd_init_fiber_line(fpd_sim *s, double cx, double cy, double theta);
 
-/* Enqueue n_steps >= 0 time steps on the simulation's stream (asynchronous). */
+/* Enqueue n_steps >= 0 time steps on the simulation's stream (asynchronous): each is the
+ * three integration steps of Sec. II.C, (1) phi, F, f and eta from R^n (Eqs. 1, 2, 4,
+ * 10-12), (2) the MRT collide-and-stream update with moving-wall bounce-back, (3) V^{n+1}
+ * by Eq. (5) and R^{n+1} = R^n + V^{n+1}.  FPD_EINVAL for n_steps < 0, FPD_ESTATE before
+ * fpd_init_fiber when the simulation has beads; an unstable run is reported by health
+ * bits (fpd_sync), not here. */
 int fpd_step(fpd_sim *s, int64_t n_steps);
 
 /* Capture now, without running any step, the graph that fpd_step(s, n_steps) replays
@@ -204,8 +213,9 @@ const char *fpd_last_error(void);
  * Eq. (1).  Pressure is rho / 3. */
 int fpd_read_fields(fpd_sim *s, double *rho, double *ux, double *uy, double *eta);
 
-/* Host f[9][ny][nx]: the pre-collision (post-stream) populations of the current step,
- * decoded to float64 whatever the storage. */
+/* Host f[9][ny][nx] (caller-owned, filled here): the pre-collision (post-stream)
+ * populations f_k of the MRT-LBM scheme (Sec. II.C) at the current step, decoded to
+ * float64 whatever the storage.  Synchronises; FPD_EDEVICE on a HIP error. */
 int fpd_read_populations(fpd_sim *s, double *f);
 
 /* Replace the current pre-collision populations with host f[9][ny][nx] (encoded into the
@@ -273,8 +283,12 @@ int fpd_copy_probe(void *hip_stream, size_t bytes, int32_t iters, double *gbps);
 
 /* ------------------------------------------------------------- checkpoint ---- */
 
-/* Save / restore populations (in storage format), bead state, step count and parameters.
- * fpd_load requires a simulation created with the same parameters. */
+/* Save / restore the whole state of the time integration of Sec. II.C: populations (in
+ * storage format), bead state (R, V, F of Sec. II.B and the derived A_i, window and health),
+ * step count and parameters, to / from the file at path.  fpd_load requires a simulation
+ * created with the same parameters (FPD_EINVAL otherwise, the simulation unchanged); a
+ * file that cannot be opened or is truncated gives FPD_EINVAL, a failed write FPD_EDEVICE.
+ * Both synchronise. */
 int fpd_save(fpd_sim *s, const char *path);
 int fpd_load(fpd_sim *s, const char *path);
 
@@ -333,23 +347,28 @@ typedef struct fpd_batch fpd_batch;
  * state). */
 size_t fpd_sim_footprint(const fpd_params *p);
 
-/* hbm_budget_bytes caps the sum of footprints of held simulations; max_slots caps their
- * number (<= 4096); storage is one of FPD_F64..FPD_BF16DEV for every member. */
+/* A batch for the parameter sweeps of Sec. IV (Figs. 7-10): hbm_budget_bytes caps the sum
+ * of footprints of held simulations; max_slots caps their number (<= 4096); storage is one
+ * of FPD_F64..FPD_BF16DEV for every member (FPD_EINVAL otherwise).  hip_stream as for
+ * fpd_create.  The caller owns *out and frees it with fpd_batch_destroy. */
 int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage,
                      void *hip_stream, fpd_batch **out);
 
 /* Launch shape of the batch's lattice kernel (graph_chunk: steps per replayed graph). */
 int fpd_batch_set_launch(fpd_batch *b, const fpd_launch *cfg);
 
-/* Admit one simulation: p->storage must be the batch's; R is host [n_beads][2] (NULL when
- * n_beads = 0); it will run n_steps >= 0 steps.  FPD_ENOMEM when no slot is free or the
- * footprint would exceed the budget (nothing is allocated then).  *sim_id > 0. */
+/* Admit one simulation of the problem of Sec. IV.A (as fpd_create + fpd_init_fiber):
+ * p->storage must be the batch's; R is host [n_beads][2] (NULL when n_beads = 0); it will
+ * run n_steps >= 0 steps.  FPD_ENOMEM when no slot is free or the footprint would exceed
+ * the budget (nothing is allocated then); FPD_EINVAL for invalid parameters or beads.
+ * *sim_id > 0. */
 int fpd_batch_add(fpd_batch *b, const fpd_params *p, const double *R, int64_t n_steps,
                   int64_t *sim_id);
 
-/* Advance every active simulation by min(max_steps, smallest remaining count) steps
- * (*advanced receives it; 0 when none is active), then check health: a simulation with a
- * health bit set becomes FPD_SIM_FAILED, the others continue.  Synchronises. */
+/* Advance every active simulation by min(max_steps, smallest remaining count) steps of
+ * Sec. II.C (*advanced receives it; 0 when none is active), then check health: a
+ * simulation with a health bit set becomes FPD_SIM_FAILED, the others continue.
+ * Synchronises; FPD_EDEVICE on a HIP error. */
 int fpd_batch_run(fpd_batch *b, int64_t max_steps, int64_t *advanced);
 
 /* Simulations that became DONE or FAILED since the last poll: ids[i], status[i]

@@ -264,6 +264,9 @@ int build_graph(fpd_sim* s, int from, int chunk, hipGraphExec_t* out) {
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(FPD_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    // move the graph to the device now, so its first replay costs what the others do
+    e = hipGraphUpload(*out, s->stream);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "graph upload: %s", hipGetErrorString(e));
     return FPD_OK;
 }
 
@@ -1250,6 +1253,8 @@ int batch_build_graph(fpd_batch* b, int chunk) {
     e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(FPD_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
+    e = hipGraphUpload(b->graph, b->stream);
+    if (e != hipSuccess) return fail(FPD_EDEVICE, "batch graph upload: %s", hipGetErrorString(e));
     b->graph_chunk = chunk;
     for (int k = 0; k < 3; ++k) b->graph_counts[k] = b->h_counts[k];
     b->graph_periodic = b->any_periodic;

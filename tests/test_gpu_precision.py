@@ -51,7 +51,7 @@ def test_reduced_storage_error_against_oracle(reference, storage):
 # parameters drawn from the sweep's distributions, seed 1: 6 beads, C = 0.49, Re_ps = 9.8,
 # K = 7.0, U = 0.042) over the served 20k steps (gamma t = 26), against the oracle at 1k,
 # 5k and 20k steps.  The errors are stated, and held to the measured levels with margin.
-SWEEP_BOUNDS = {"f64": (1e-6, 1e-3), "f32": (2e-4, 1e-3), "f16dev": (5e-2, 3.0),
+SWEEP_BOUNDS = {"f64": (1e-10, 1e-10), "f32": (2e-4, 1e-3), "f16dev": (5e-2, 2.5),
                 "bf16dev": (0.15, 5.0)}
 
 
