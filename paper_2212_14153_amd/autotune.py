@@ -12,6 +12,8 @@ import itertools
 import json
 import math
 import os
+import sys
+import tempfile
 import time
 
 SHAPES = [(256, 1), (128, 2), (128, 1), (64, 4), (64, 2)]
@@ -69,15 +71,29 @@ def search(run, candidates=None, rounds: int = 3):
     return candidates[order[0]], table
 
 
+def _log_cached(key: str, cfg: dict) -> None:
+    print(f"[autotune] {key}: cached launch shape {cfg} applied (from {cache_path()})",
+          file=sys.stderr, flush=True)
+
+
 def tune_simulation(sim, storage: str, nodes: int, steps: int = 40, rounds: int = 3,
-                    use_cache: bool = True):
-    """Pick and apply the best launch shape for one simulation."""
+                    use_cache: bool = True, restore: bool = True):
+    """Pick and apply the best launch shape for one simulation.  Timing steps the
+    simulation (rounds x candidates x (steps + 2) steps); with restore (the default) its
+    state is saved to a temporary checkpoint first and loaded back afterwards, so the
+    simulation is where it was, bitwise; restore=False leaves it advanced."""
     key = f"sim|{device_key()}|{storage}|{size_class(nodes)}"
     cache = _load_cache()
     if use_cache and key in cache:
         sim.set_launch(cache[key]["cfg"])
+        _log_cached(key, cache[key]["cfg"])
         return cache[key]["cfg"], None
     saved = sim.get_launch()
+    ckpt = None
+    if restore:
+        fd, ckpt = tempfile.mkstemp(prefix="fpd_autotune_", suffix=".ckpt")
+        os.close(fd)
+        sim.save(ckpt)
 
     def run(cfg):
         sim.set_launch(cfg)
@@ -88,7 +104,12 @@ def tune_simulation(sim, storage: str, nodes: int, steps: int = 40, rounds: int 
         sim.sync()
         return time.perf_counter() - t0
 
-    best, table = search(run, rounds=rounds)
+    try:
+        best, table = search(run, rounds=rounds)
+    finally:
+        if ckpt:
+            sim.load(ckpt)
+            os.remove(ckpt)
     sim.set_launch(dict(best, graph_chunk=saved.graph_chunk))
     cache[key] = {"cfg": best, "seconds": table[0][1], "steps": steps}
     _store_cache(cache)
@@ -102,6 +123,7 @@ def tune_batch(make_batch, storage: str, nodes: int, steps: int = 16, rounds: in
     key = f"batch|{device_key()}|{storage}|{size_class(nodes)}"
     cache = _load_cache()
     if use_cache and key in cache:
+        _log_cached(key, cache[key]["cfg"])
         return cache[key]["cfg"], None
     b = make_batch()
     try:
