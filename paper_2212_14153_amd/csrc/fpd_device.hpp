@@ -194,41 +194,86 @@ __device__ inline double phi_f64(double r, double a, double xi) {
     return 1.0 / (1.0 + exp(2.0 * (r - a) / xi));
 }
 // FP32 (the FP32 and two-byte storage paths): the hardware 2^x, reciprocal and square root
-// (PhiEval), each within about one ulp, instead of the correctly rounded library forms (the
+// (BeadGeom<float>), each within about one ulp, instead of the correctly rounded library forms (the
 // fiber tiles evaluate phi for every nearby bead at every node).
 __device__ inline float phi_f32(float r, float a, float inv_xi) {
     const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * (r - a) * inv_xi);  // 2 log2(e)
     return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
-template <typename T> struct PhiEval;
-// dist2 is the one expression of the squared distance: the cutoff test and phi
-// itself always see the same value.
+// dist2 is the one expression of the FP64 squared distance: the cutoff test and phi itself
+// always see the same value.
 __device__ inline double dist2(double dx, double dy) { return dx * dx + dy * dy; }
 
-template <> struct PhiEval<double> {
-    // phi at squared distance r2 < rc2
-    __device__ static inline double of_r2(double r2, double a, double xi, double) {
+// Minimum image of an integer offset d in (-n, n): d mod n in [-(n/2), n - n/2).
+__device__ inline int wrap_offset(int d, int n) {
+    const int h = n >> 1;
+    if (d >= n - h) return d - n;
+    if (d < -h) return d + n;
+    return d;
+}
+
+// A bead as the fiber arithmetic of precision T sees it: the squared distance of a node
+// centre (x + 1/2, y + 1/2) from the bead (minimum image in x, and in y in a periodic box)
+// and the cutoff test r2 < rc^2.  The fiber tiles (Eqs. 1, 2, 4) and the bead kernel
+// (A_i, Eq. 5) evaluate phi only through this, on the same per-bead data, so whether a node
+// sees a bead, and the phi it gets, never depends on the tiling.  Every integer support box
+// (bead_box, the window, the occupancy bitmap) holds all nodes closer than rc + 1 to the
+// bead, so this test, not a box, decides which nodes are in.
+template <typename T> struct BeadGeom;
+
+template <> struct BeadGeom<double> {
+    double R[2];
+    __device__ static inline BeadGeom make(double Rx, double Ry, int, int, bool) {
+        return BeadGeom{{Rx, Ry}};
+    }
+    __device__ inline double r2(int x, int y, int nx, int ny, bool per) const {
+        const double dx = min_image((double)x + 0.5 - R[0], nx);
+        const double dy = y_image((double)y + 0.5 - R[1], ny, per);
+        return dist2(dx, dy);
+    }
+    // the node that holds the bead: floor(R), wrapped (x, and y in a periodic box)
+    __device__ inline void node(int nx, int ny, bool per, int& ox, int& oy) const {
+        ox = imod((int)floor(R[0]), nx);
+        oy = per ? imod((int)floor(R[1]), ny) : (int)floor(R[1]);
+    }
+    __device__ static inline double cut2(double rc2) { return rc2; }
+    // phi at squared distance r2 < cut2
+    __device__ static inline double phi(double r2, double a, double xi, double) {
         return phi_f64(sqrt(r2), a, xi);
     }
-    __device__ static inline double eval(double dx, double dy, double rc2, double a,
-                                         double xi, double inv_xi) {
-        const double r2 = dist2(dx, dy);
-        if (r2 >= rc2) return 0.0;
-        return of_r2(r2, a, xi, inv_xi);
-    }
 };
-// The cutoff test stays in FP64 in both variants: it is the same predicate as the
-// support boxes, so whether a node sees a bead never depends on the tiling.
-template <> struct PhiEval<float> {
-    __device__ static inline float of_r2(double r2, double a, double, double inv_xi) {
-        return phi_f32(__builtin_amdgcn_sqrtf((float)r2), (float)a, (float)inv_xi);
+
+// FP32 (the FP32 and two-byte storage paths): the node (ox, oy) holding the bead, i.e.
+// floor(R) wrapped into the lattice, and q = 1/2 - frac(R) rounded to FP32.  A node's
+// offset x + 1/2 - Rx is the integer x - ox (minimum image) plus q: one rounding of q and
+// one of the FP32 sum, at any lattice size, and no FP64 arithmetic per node and bead.
+template <> struct BeadGeom<float> {
+    int o[2];
+    float q[2];
+    __device__ static inline BeadGeom make(double Rx, double Ry, int nx, int ny, bool per) {
+        BeadGeom g{{0, 0}, {0.0f, 0.0f}};
+        if (!bead_sane(Rx, Ry)) return g;  // empty support box: never evaluated
+        const double fx = floor(Rx), fy = floor(Ry);
+        g.o[0] = imod((int)fx, nx);
+        g.o[1] = per ? imod((int)fy, ny) : (int)fy;
+        g.q[0] = (float)(0.5 - (Rx - fx));  // Rx - floor(Rx) is exact
+        g.q[1] = (float)(0.5 - (Ry - fy));
+        return g;
     }
-    __device__ static inline float eval(double dx, double dy, double rc2, double a, double xi,
-                                        double inv_xi) {
-        const double r2 = dist2(dx, dy);
-        if (r2 >= rc2) return 0.0f;
-        return of_r2(r2, a, xi, inv_xi);
+    __device__ inline float r2(int x, int y, int nx, int ny, bool per) const {
+        const int di = wrap_offset(x - o[0], nx);
+        const int dj = per ? wrap_offset(y - o[1], ny) : y - o[1];
+        const float dx = (float)di + q[0], dy = (float)dj + q[1];
+        return __builtin_fmaf(dx, dx, dy * dy);  // one fixed contraction everywhere
+    }
+    __device__ inline void node(int, int, bool, int& ox, int& oy) const {
+        ox = o[0];
+        oy = o[1];
+    }
+    __device__ static inline float cut2(double rc2) { return (float)rc2; }
+    __device__ static inline float phi(float r2, double a, double, double inv_xi) {
+        return phi_f32(__builtin_amdgcn_sqrtf(r2), (float)a, (float)inv_xi);
     }
 };
 

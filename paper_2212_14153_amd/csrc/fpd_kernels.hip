@@ -314,13 +314,20 @@ __device__ inline void own_bead(const Fiber& fib, const Bonds& B, int b, const d
 }
 
 // ------------------------------------------------- bead list for a tile (LDS) ------
+// One bead of a tile's list: its position as the fiber arithmetic of T sees it and its
+// Eq. (4) coefficients C_b = F_b / A_b rounded to T.
+template <typename T> struct TileBead {
+    BeadGeom<T> g;
+    T C[2];
+};
 // Ordered compaction of the beads whose support box meets the tile's columns
 // [cx0, cx0 + cw) and rows [ry0, ry0 + rh): bead order is kept, so per-node sums over
 // beads run in the same order as in a full loop.  Bond tangents and forces are computed
 // only when some bead is near (with several fibers most window tiles have none).
+template <typename T>
 __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, int cx0, int cw,
-                                   int ry0, int rh, double (*sR)[2], double (*sC)[2],
-                                   int* sIdx, int* s_wave, Bonds& B, bool forces_ready) {
+                                   int ry0, int rh, TileBead<T>* sB, int* sIdx, int* s_wave,
+                                   Bonds& B, bool forces_ready) {
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nthreads = blockDim.x * blockDim.y;
     const int lane = tid & 63, wave = tid >> 6, nwaves = (nthreads + 63) >> 6;
@@ -349,8 +356,7 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
             chunk += s_wave[w];
         }
         if (hit) {
-            sR[off + before][0] = Rx;
-            sR[off + before][1] = Ry;
+            sB[off + before].g = BeadGeom<T>::make(Rx, Ry, nx, ny, per);
             sIdx[off + before] = b;
         }
         total += chunk;
@@ -360,8 +366,8 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
     if (forces_ready) {
         for (int i = tid; i < total; i += nthreads) {
             const int b = sIdx[i];
-            sC[i][0] = bs->C[b][0];
-            sC[i][1] = bs->C[b][1];
+            sB[i].C[0] = (T)bs->C[b][0];
+            sB[i].C[1] = (T)bs->C[b][1];
         }
     } else {
         fill_bonds(bs, fib.n, B);
@@ -376,11 +382,10 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
             }
             const double A = bs->A[b];
             const double C0 = F[0] / A, C1 = F[1] / A;
-            sC[i][0] = C0;
-            sC[i][1] = C1;
-            const double Rx = sR[i][0], Ry = sR[i][1];
-            const int ox = imod((int)floor(Rx), nx);
-            const int oy = per ? imod((int)floor(Ry), ny) : (int)floor(Ry);
+            sB[i].C[0] = (T)C0;
+            sB[i].C[1] = (T)C1;
+            int ox, oy;
+            sB[i].g.node(nx, ny, per, ox, oy);
             if (ox >= cx0 && ox < cx0 + cw && oy >= ry0 && oy < ry0 + rh)
                 own_bead(fib, B, b, F, C0, C1);
         }
@@ -391,10 +396,10 @@ __device__ inline int gather_beads(const Fiber& fib, int nx, int ny, bool per, i
 
 // ------------------------------------------------------------- fused lattice step ---
 
-// LDS of a lattice tile: the beads near it and their Eq. (4) coefficients.
+// LDS of a lattice tile: the beads near it (TileBead records of the tile's precision) and
+// their Eq. (4) coefficients.
 struct TileLds {
-    double R[kMaxBeads][2];
-    double C[kMaxBeads][2];
+    alignas(16) unsigned char beads[kMaxBeads * sizeof(TileBead<double>)];
     Bonds bonds;
     int idx[kMaxBeads];
     int wave[16];
@@ -413,19 +418,20 @@ __device__ inline Window tile_window(const StepArgs& a) {
 // uniform body force), recorded in the force window.  Fx, Fy are overwritten; s_nu and
 // s_q keep the fluid values where sum phi = 0.
 template <typename T>
-__device__ inline void fiber_node(const StepArgs& a, bool per, const double (*sR)[2],
-                                  const double (*sC)[2], int nb, int x, int y, int wx0,
-                                  int wy0, int ww, int wh, T& Fx, T& Fy, T& s_nu, T& s_q) {
+__device__ inline void fiber_node(const StepArgs& a, bool per, const TileBead<T>* sB, int nb,
+                                  int x, int y, int wx0, int wy0, int ww, int wh, T& Fx, T& Fy,
+                                  T& s_nu, T& s_q) {
+    using G = BeadGeom<T>;
     const int nx = a.L.nx, ny = a.L.ny;
-    const double xc = (double)x + 0.5, yc = (double)y + 0.5;
+    const T rc2 = G::cut2(a.fib.rc2);
     T sphi = T(0), fx = T(0), fy = T(0);
     for (int i = 0; i < nb; ++i) {
-        const double dx = min_image(xc - sR[i][0], nx);
-        const double dy = y_image(yc - sR[i][1], ny, per);
-        const T ph = PhiEval<T>::eval(dx, dy, a.fib.rc2, a.fib.a, a.fib.xi, a.fib.inv_xi);
+        const T r2 = sB[i].g.r2(x, y, nx, ny, per);
+        if (!(r2 < rc2)) continue;
+        const T ph = G::phi(r2, a.fib.a, a.fib.xi, a.fib.inv_xi);
         sphi += ph;
-        fx += ph * (T)sC[i][0];
-        fy += ph * (T)sC[i][1];
+        fx += ph * sB[i].C[0];
+        fy += ph * sB[i].C[1];
     }
     Fx = fx + (T)a.gx;
     Fy = fy + (T)a.gy;
@@ -465,8 +471,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     const bool per = periodic_of(BC, a);
     using T = typename Cd::T;
     using S = typename Cd::store_t;
-    double (*sR)[2] = lds.R;
-    double (*sC)[2] = lds.C;
+    TileBead<T>* sB = (TileBead<T>*)lds.beads;
     int* s_wave = lds.wave;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int bx = blockDim.x;
@@ -511,9 +516,8 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
         fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx) &&
                      occ_hit(a.fib, a.parity, xtile, tw, ytile, a.rows_per_block, nx, ny);
         if (fiber_tile)
-            nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
-                              a.rows_per_block, sR, sC, lds.idx, s_wave, lds.bonds,
-                              FR);
+            nb = gather_beads<T>(a.fib, nx, ny, per, xtile, tw, ytile, a.rows_per_block, sB,
+                                 lds.idx, s_wave, lds.bonds, FR);
     }
 
     // a tile inside the window that no bead's support reaches is fluid only: no node of
@@ -530,7 +534,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
         // the fiber terms first: the populations are not live during the bead loop
         T Fx = (T)a.gx, Fy = (T)a.gy, s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
         if (fiber_tile)
-            fiber_node<T>(a, per, sR, sC, nb, x, y, wx0, wy0, ww, wh, Fx, Fy, s_nu, s_q);
+            fiber_node<T>(a, per, sB, nb, x, y, wx0, wy0, ww, wh, Fx, Fy, s_nu, s_q);
         T g[9];
         pull<Cd>(src, nx, ny, stride, plane, x, y, per, u6, g);
         if (plain)  // no force anywhere on this tile: the unforced collision
@@ -599,9 +603,8 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
         fiber_tile = ww > 0 && wh > 0 && rows_hit && cols_overlap(xtile, tw, wx0, ww, nx) &&
                      occ_hit(a.fib, a.parity, xtile, tw, ytile, a.rows_per_block, nx, ny);
         if (fiber_tile)
-            nb = gather_beads(a.fib, nx, ny, per, xtile, tw, ytile,
-                              a.rows_per_block, lds.R, lds.C, lds.idx, lds.wave, lds.bonds,
-                              FR);
+            nb = gather_beads<T>(a.fib, nx, ny, per, xtile, tw, ytile, a.rows_per_block,
+                                 (TileBead<T>*)lds.beads, lds.idx, lds.wave, lds.bonds, FR);
     }
 
     // a tile inside the window that no bead's support reaches is fluid only: no node of
@@ -624,8 +627,8 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
             s_nu[i] = (T)a.s_nu_f;
             s_q[i] = (T)a.s_q_f;
             if (fiber_tile && x0 + i < nx)
-                fiber_node<T>(a, per, lds.R, lds.C, nb, x0 + i, y, wx0, wy0, ww, wh, Fx[i], Fy[i],
-                              s_nu[i], s_q[i]);
+                fiber_node<T>(a, per, (const TileBead<T>*)lds.beads, nb, x0 + i, y, wx0, wy0,
+                              ww, wh, Fx[i], Fy[i], s_nu[i], s_q[i]);
         }
         T g[G][9];
         pull_group<Cd, G>(src, nx, ny, stride, plane, x0, y, per, first, last, u6,
@@ -757,33 +760,32 @@ __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
 
 // ----------------------------------------------------------------- bead kernel -----
 
-// phi of one bead in the arithmetic of the storage (FP64 for FPD_F64, FP32 otherwise) at
-// squared distance r2 = dist2(dx, dy) < rc2 (the FP64 cutoff test of PhiEval, shared with
-// the support boxes).
+// Node t of a bead's support box (columns i0 .. i0 + w - 1, rows from j0, both wrapped),
+// its squared distance from the bead in the fiber arithmetic T of the storage (FP64 for
+// FPD_F64, FP32 otherwise) and whether it passes the cutoff test: BeadGeom<T>, the same
+// evaluation as in the lattice tiles.  t >= total: out.
 template <typename T>
-__device__ inline double bead_phi_r2(const Fiber& fib, double r2) {
-    return (double)PhiEval<T>::of_r2(r2, fib.a, fib.xi, fib.inv_xi);
-}
-
-// Squared distance of node t of a bead's support box (columns i0 .. i0 + w - 1, rows from
-// j0, both wrapped) from (Rx, Ry), and whether it is inside the cutoff; t >= total: out.
-__device__ inline void box_node(const Fiber& fib, int t, int total, int i0, int w, int j0,
-                                int nx, int ny, bool per, double Rx, double Ry, int& x,
-                                int& y, double& r2, bool& in) {
+__device__ inline void box_node(const Fiber& fib, const BeadGeom<T>& geo, int t, int total,
+                                int i0, int w, int j0, int nx, int ny, bool per, int& x, int& y,
+                                T& r2, bool& in) {
     x = i0;
     y = j0;
-    r2 = 0.0;
+    r2 = T(0);
     in = false;
     if (t < total) {
         y = j0 + t / w;
         if (y >= ny) y -= ny;  // periodic box: rows wrap
         x = i0 + t % w;
         if (x >= nx) x -= nx;
-        const double dx = min_image((double)x + 0.5 - Rx, nx);
-        const double dy = y_image((double)y + 0.5 - Ry, ny, per);
-        r2 = dist2(dx, dy);
-        in = r2 < fib.rc2;  // the cutoff test of PhiEval
+        r2 = geo.r2(x, y, nx, ny, per);
+        in = r2 < BeadGeom<T>::cut2(fib.rc2);
     }
+}
+
+// phi of one bead at a node that passed the cutoff test (squared distance r2)
+template <typename T>
+__device__ inline double bead_phi(const Fiber& fib, T r2) {
+    return (double)BeadGeom<T>::phi(r2, fib.a, fib.xi, fib.inv_xi);
 }
 
 // This bead's share of the next support window and of the occupancy bitmap (slot
@@ -835,6 +837,7 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
     if (do_velocity) {
         int i0, w, j0, j1;
         bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
+        const BeadGeom<T> geo = BeadGeom<T>::make(Rx, Ry, nx, ny, per);
         const int rows = j1 - j0 + 1;
         const int total = (rows > 0 && w > 0) ? rows * w : 0;
         const Window win = decode_window(wraw, nx, ny, per, fib.rect_wmax, fib.rect_hmax);
@@ -847,15 +850,16 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
             sx[r] = 0.0;
             sy[r] = 0.0;
             for (int t0 = tid + r * NT; t0 < total; t0 += VB * kBeadLanes) {
-                double ph[VB], r2[VB];
+                double ph[VB];
+                T r2[VB];
                 bool in[VB];
                 int ii[VB], jj[VB];
                 T g[VB][9];
                 T fw[VB][2];
 #pragma unroll
                 for (int u = 0; u < VB; ++u)
-                    box_node(fib, t0 + u * kBeadLanes, total, i0, w, j0, nx, ny, per, Rx, Ry,
-                             ii[u], jj[u], r2[u], in[u]);
+                    box_node<T>(fib, geo, t0 + u * kBeadLanes, total, i0, w, j0, nx, ny, per,
+                                ii[u], jj[u], r2[u], in[u]);
 #pragma unroll
                 for (int u = 0; u < VB; ++u) {
                     fw[u][0] = (T)a.gx;  // outside the window f^n is the body force alone
@@ -877,7 +881,7 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
                 }
 #pragma unroll
                 for (int u = 0; u < VB; ++u)
-                    ph[u] = in[u] ? bead_phi_r2<T>(fib, r2[u]) : 0.0;
+                    ph[u] = in[u] ? bead_phi<T>(fib, r2[u]) : 0.0;
 #pragma unroll
                 for (int u = 0; u < VB; ++u) {
                     if (ph[u] == 0.0) continue;
@@ -917,6 +921,7 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
 
     int i0, w, j0, j1;
     bead_box(Rx, Ry, fib.rc, nx, ny, per, i0, w, j0, j1);
+    const BeadGeom<T> geo = BeadGeom<T>::make(Rx, Ry, nx, ny, per);
     const int rows = j1 - j0 + 1;
     const int total = (rows > 0 && w > 0) ? rows * w : 0;
     double sa[R];
@@ -925,10 +930,10 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
         sa[r] = 0.0;
         for (int t = tid + r * NT; t < total; t += kBeadLanes) {
             int x, y;
-            double r2;
+            T r2;
             bool in;
-            box_node(fib, t, total, i0, w, j0, nx, ny, per, Rx, Ry, x, y, r2, in);
-            if (in) sa[r] += bead_phi_r2<T>(fib, r2);
+            box_node<T>(fib, geo, t, total, i0, w, j0, nx, ny, per, x, y, r2, in);
+            if (in) sa[r] += bead_phi<T>(fib, r2);
         }
     }
     const double A_new = lanes_sum<R>(sa, scratch);
