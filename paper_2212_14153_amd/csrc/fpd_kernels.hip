@@ -487,6 +487,11 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     const T u6 = (T)a.u6;
     const T s_e = (T)a.s_e, s_eps = (T)a.s_eps;
 
+    // the first row's populations are requested before the fiber checks below, so their
+    // latency overlaps the reads of the window, the occupancy bitmap and the bead list
+    T g0[9];
+    if (x < nx && ybase < ny) pull<Cd>(src, nx, ny, stride, plane, x, ybase, per, u6, g0);
+
     // Block-uniform: does this tile meet the fiber's support window?
     int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
     bool fiber_tile = false;
@@ -531,12 +536,18 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     for (int r = 0; r < SPT; ++r) {
         const int y = ybase + r;
         if (x >= nx || y >= ny) continue;
-        // the fiber terms first: the populations are not live during the bead loop
+        // the fiber terms first: the populations of later rows are not live during the
+        // bead loop
         T Fx = (T)a.gx, Fy = (T)a.gy, s_nu = (T)a.s_nu_f, s_q = (T)a.s_q_f;
         if (fiber_tile)
             fiber_node<T>(a, per, sB, nb, x, y, wx0, wy0, ww, wh, Fx, Fy, s_nu, s_q);
         T g[9];
-        pull<Cd>(src, nx, ny, stride, plane, x, y, per, u6, g);
+        if (r == 0) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) g[k] = g0[k];
+        } else {
+            pull<Cd>(src, nx, ny, stride, plane, x, y, per, u6, g);
+        }
         if (plain)  // no force anywhere on this tile: the unforced collision
             mrt_collide<T>(g, T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
         else
@@ -631,8 +642,7 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
                               ww, wh, Fx[i], Fy[i], s_nu[i], s_q[i]);
         }
         T g[G][9];
-        pull_group<Cd, G>(src, nx, ny, stride, plane, x0, y, per, first, last, u6,
-                          g);
+        pull_group<Cd, G>(src, nx, ny, stride, plane, x0, y, per, first, last, u6, g);
         if (x0 >= nx) continue;
         uint32_t bits[9][G / 2];
 #pragma unroll
