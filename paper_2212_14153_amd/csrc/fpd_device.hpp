@@ -492,6 +492,15 @@ __device__ inline void pull_group(const uint16_t* __restrict__ src, int nx, int 
 // basis (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy), with Guo's forcing: the velocity is
 // (j + F/2)/rho and the source (I - S/2) applied to the force moments
 //   (0, 6 u.F, -6 u.F, F_x, -F_x, F_y, -F_y, 2(u_x F_x - u_y F_y), u_x F_y + u_y F_x).
+// 1/x in the arithmetic of T: FP64 divides; FP32 (the FP32 and two-byte paths) takes the
+// hardware reciprocal, within about one ulp, instead of the correctly rounded division
+// sequence (ten instructions per node in the collision).
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+// a / b in the same sense (FP64: the division itself)
+__device__ inline double quot(double a, double b) { return a / b; }
+__device__ inline float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // The moment matrix has entries in {0, +-1, +-2, +-4} and is applied as adds in registers;
 // moments of w are (1, -2, 1, 0, ...), so e and eps are carried as deviations too and no
 // O(1) cancellation enters |m - m_eq|.
@@ -512,7 +521,7 @@ __device__ inline void mrt_collide(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s
     T pxx = (g[1] + g[3]) - (g[2] + g[4]);
     T pxy = (g[5] + g[7]) - (g[6] + g[8]);
 
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = recip(rho);
     const T ux = (jx + T(0.5) * Fx) * inv_rho;
     const T uy = (jy + T(0.5) * Fy) * inv_rho;
     const T rux = rho * ux, ruy = rho * uy;
@@ -578,7 +587,7 @@ __device__ inline void mrt_collide_scaled(T g[9], T Fx, T Fy, T s_nu, T s_q, T s
     T pxy = (g[5] + g[7]) - (g[6] + g[8]);
 
     const T Fxs = S * Fx, Fys = S * Fy;       // force density in the scaled units
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = recip(rho);
     const T inv_rho_s = iS * inv_rho;
     const T ux = (jx + T(0.5) * Fxs) * inv_rho_s;
     const T uy = (jy + T(0.5) * Fys) * inv_rho_s;

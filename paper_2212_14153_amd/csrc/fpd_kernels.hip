@@ -440,8 +440,9 @@ __device__ inline void fiber_node(const StepArgs& a, bool per, const TileBead<T>
     if (sphi > T(0)) {  // else the fluid rates, exactly as on the other tiles
         const T nu_f = (T)a.fib.nu_f;
         const T eta = nu_f + ((T)a.fib.nu_s - nu_f) * sphi;
-        s_nu = T(1) / (T(3) * eta + T(0.5));
-        s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed : T(8) * (T(2) - s_nu) / (T(8) - s_nu);
+        s_nu = recip(T(3) * eta + T(0.5));
+        s_q = a.fib.s_q_fixed > 0.0 ? (T)a.fib.s_q_fixed
+                                    : quot(T(8) * (T(2) - s_nu), T(8) - s_nu);
     }
     const int wi = imod(x - wx0, nx), wj = per ? imod(y - wy0, ny) : y - wy0;
     if (wi < ww && wj >= 0 && wj < wh) {
