@@ -504,7 +504,11 @@ __device__ inline float quot(float a, float b) { return a * __builtin_amdgcn_rcp
 // The moment matrix has entries in {0, +-1, +-2, +-4} and is applied as adds in registers;
 // moments of w are (1, -2, 1, 0, ...), so e and eps are carried as deviations too and no
 // O(1) cancellation enters |m - m_eq|.
-template <typename T>
+// kForce = false: the collision without a force term (F = 0), as a separate instance
+// rather than F = 0 at run time, whose products with zero the compiler must keep.  With
+// F = +0 the forced instance gives the same bits (every force term is then +0 or -0
+// added to a sum, so only the sign of an exact zero could differ).
+template <typename T, bool kForce = true>
 __device__ inline void mrt_collide(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s_eps) {
     const T s14 = (g[1] + g[2]) + (g[3] + g[4]);
     const T s58 = (g[5] + g[6]) + (g[7] + g[8]);
@@ -522,23 +526,31 @@ __device__ inline void mrt_collide(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s
     T pxy = (g[5] + g[7]) - (g[6] + g[8]);
 
     const T inv_rho = recip(rho);
-    const T ux = (jx + T(0.5) * Fx) * inv_rho;
-    const T uy = (jy + T(0.5) * Fy) * inv_rho;
-    const T rux = rho * ux, ruy = rho * uy;
+    // rho u = j + F/2 (Guo), u = rho u / rho
+    const T rux = kForce ? jx + T(0.5) * Fx : jx, ruy = kForce ? jy + T(0.5) * Fy : jy;
+    const T ux = rux * inv_rho, uy = ruy * inv_rho;
     const T ru2 = rux * ux + ruy * uy;
-    const T uF = ux * Fx + uy * Fy;
 
     // m* = m - s (m - m_eq) + (1 - s/2) F_m, moment by moment
-    me = me - s_e * (me - (T(-2) * drho + T(3) * ru2)) + (T(1) - T(0.5) * s_e) * (T(6) * uF);
-    meps = meps - s_eps * (meps - (drho - T(3) * ru2)) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
-    const T hq = T(1) - T(0.5) * s_q;
-    qx = qx - s_q * (qx + rux) - hq * Fx;
-    qy = qy - s_q * (qy + ruy) - hq * Fy;
-    const T hn = T(1) - T(0.5) * s_nu;
-    pxx = pxx - s_nu * (pxx - (rux * ux - ruy * uy)) + hn * T(2) * (ux * Fx - uy * Fy);
-    pxy = pxy - s_nu * (pxy - rux * uy) + hn * (ux * Fy + uy * Fx);
-    jx += Fx;
-    jy += Fy;
+    me = me - s_e * (me - (T(-2) * drho + T(3) * ru2));
+    meps = meps - s_eps * (meps - (drho - T(3) * ru2));
+    qx = qx - s_q * (qx + rux);
+    qy = qy - s_q * (qy + ruy);
+    pxx = pxx - s_nu * (pxx - (rux * ux - ruy * uy));
+    pxy = pxy - s_nu * (pxy - rux * uy);
+    if constexpr (kForce) {
+        const T uF = ux * Fx + uy * Fy;
+        me += (T(1) - T(0.5) * s_e) * (T(6) * uF);
+        meps += (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
+        const T hq = T(1) - T(0.5) * s_q;
+        qx -= hq * Fx;
+        qy -= hq * Fy;
+        const T hn = T(1) - T(0.5) * s_nu;
+        pxx += hn * T(2) * (ux * Fx - uy * Fy);
+        pxy += hn * (ux * Fy + uy * Fx);
+        jx += Fx;
+        jy += Fy;
+    }
 
     // g = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
     const T a = drho * T(1.0 / 9.0);
@@ -568,7 +580,7 @@ __device__ inline void mrt_collide(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s
 // the moments of h are S times those of g; rho and u come from the unscaled drho and j, the
 // equilibria and force terms enter scaled by S, and the result is S g*.  The same operator
 // as mrt_collide; the scale leaves the nine decodes and encodes of each node.
-template <typename T>
+template <typename T, bool kForce = true>
 __device__ inline void mrt_collide_scaled(T g[9], T Fx, T Fy, T s_nu, T s_q, T s_e, T s_eps) {
     constexpr T S = T(16384), iS = T(1.0 / 16384.0);
     const T s14 = (g[1] + g[2]) + (g[3] + g[4]);
@@ -587,25 +599,31 @@ __device__ inline void mrt_collide_scaled(T g[9], T Fx, T Fy, T s_nu, T s_q, T s
     T pxy = (g[5] + g[7]) - (g[6] + g[8]);
 
     const T Fxs = S * Fx, Fys = S * Fy;       // force density in the scaled units
-    const T inv_rho = recip(rho);
-    const T inv_rho_s = iS * inv_rho;
-    const T ux = (jx + T(0.5) * Fxs) * inv_rho_s;
-    const T uy = (jy + T(0.5) * Fys) * inv_rho_s;
-    const T rho_s = S * rho;
-    const T rux = rho_s * ux, ruy = rho_s * uy;   // S rho u
+    const T inv_rho_s = iS * recip(rho);
+    // S rho u = S (j + F/2), u = S rho u / (S rho)
+    const T rux = kForce ? jx + T(0.5) * Fxs : jx, ruy = kForce ? jy + T(0.5) * Fys : jy;
+    const T ux = rux * inv_rho_s, uy = ruy * inv_rho_s;
     const T ru2 = rux * ux + ruy * uy;
-    const T uF = ux * Fxs + uy * Fys;
 
-    me = me - s_e * (me - (T(-2) * drho + T(3) * ru2)) + (T(1) - T(0.5) * s_e) * (T(6) * uF);
-    meps = meps - s_eps * (meps - (drho - T(3) * ru2)) + (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
-    const T hq = T(1) - T(0.5) * s_q;
-    qx = qx - s_q * (qx + rux) - hq * Fxs;
-    qy = qy - s_q * (qy + ruy) - hq * Fys;
-    const T hn = T(1) - T(0.5) * s_nu;
-    pxx = pxx - s_nu * (pxx - (rux * ux - ruy * uy)) + hn * T(2) * (ux * Fxs - uy * Fys);
-    pxy = pxy - s_nu * (pxy - rux * uy) + hn * (ux * Fys + uy * Fxs);
-    jx += Fxs;
-    jy += Fys;
+    me = me - s_e * (me - (T(-2) * drho + T(3) * ru2));
+    meps = meps - s_eps * (meps - (drho - T(3) * ru2));
+    qx = qx - s_q * (qx + rux);
+    qy = qy - s_q * (qy + ruy);
+    pxx = pxx - s_nu * (pxx - (rux * ux - ruy * uy));
+    pxy = pxy - s_nu * (pxy - rux * uy);
+    if constexpr (kForce) {
+        const T uF = ux * Fxs + uy * Fys;
+        me += (T(1) - T(0.5) * s_e) * (T(6) * uF);
+        meps += (T(1) - T(0.5) * s_eps) * (T(-6) * uF);
+        const T hq = T(1) - T(0.5) * s_q;
+        qx -= hq * Fxs;
+        qy -= hq * Fys;
+        const T hn = T(1) - T(0.5) * s_nu;
+        pxx += hn * T(2) * (ux * Fxs - uy * Fys);
+        pxy += hn * (ux * Fys + uy * Fxs);
+        jx += Fxs;
+        jy += Fys;
+    }
 
     const T a = drho * T(1.0 / 9.0);
     const T b = me * T(1.0 / 36.0);

@@ -550,7 +550,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
             pull<Cd>(src, nx, ny, stride, plane, x, y, per, u6, g);
         }
         if (plain)  // no force anywhere on this tile: the unforced collision
-            mrt_collide<T>(g, T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+            mrt_collide<T, false>(g, T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
         else
             mrt_collide<T>(g, Fx, Fy, s_nu, s_q, s_e, s_eps);
         S* o = dst + (long long)y * stride + x;
@@ -650,12 +650,14 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
         for (int i = 0; i < G; ++i) {
             if constexpr (kScaled) {
                 if (plain)
-                    mrt_collide_scaled<T>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+                    mrt_collide_scaled<T, false>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f,
+                                                 s_e, s_eps);
                 else
                     mrt_collide_scaled<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
             } else {
                 if (plain)  // no force anywhere on this tile: the unforced collision
-                    mrt_collide<T>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e, s_eps);
+                    mrt_collide<T, false>(g[i], T(0), T(0), (T)a.s_nu_f, (T)a.s_q_f, s_e,
+                                          s_eps);
                 else
                     mrt_collide<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
             }
