@@ -15,7 +15,8 @@ from paper_2212_14153_amd import _lib
 pytestmark = pytest.mark.gpu
 
 # storage: (max |u - u_oracle| / U, max |R - R_oracle| in lu) after 1000 steps.  Measured on
-# MI355X: f32 1.7e-5 U / 9.6e-6 lu; over six starts shifted by 0 .. 5e-7 lu, f16dev
+# MI355X: f32 1.7e-5 U / 9.6e-6 lu, f16dev 1.0e-3 U / 1.8e-4 lu, bf16dev 1.2e-2 U /
+# 1.6e-3 lu; over six starts shifted by 0 .. 5e-7 lu (an earlier build) f16dev
 # 0.9-1.2e-3 U / 0.9-3.7e-4 lu and bf16dev 1.0-1.5e-2 U / 1.4-2.5e-3 lu (the two-byte
 # rounding makes the bead error of one start vary by an order of magnitude).
 BOUNDS = {"f32": (5e-5, 1e-4), "f16dev": (5e-3, 2e-3), "bf16dev": (5e-2, 5e-3)}
@@ -53,8 +54,8 @@ def test_reduced_storage_error_against_oracle(reference, storage):
 # 5k and 20k steps.  Up to 5k steps the errors are stable and held to the measured levels
 # with margin.  At 20k steps the fiber is flipping, and the two-byte storages' bead error
 # is set by the phase of the flip: over starts shifted by 0 .. 5e-7 lu it spans
-# 0.17 - 12 lu (FP16) and 0.1 - 3 lu (BF16), so there it is held as a distribution over six
-# such starts (each against the FP64 path from the same start, which the oracle pins at
+# 1.3 - 8.7 lu (FP16) and 0.13 - 1.9 lu (BF16), and 0.17 - 12 lu in a build that differs
+# only in rounding, so there it is held as a distribution over six such starts (each against the FP64 path from the same start, which the oracle pins at
 # the first one) by its median and its maximum.
 SWEEP_BOUNDS = {"f64": (1e-10, 1e-10), "f32": (2e-4, 1e-3), "f16dev": (2e-2, 0.15),
                 "bf16dev": (6e-2, 1.0)}
