@@ -924,12 +924,14 @@ __device__ inline void bead_block(const StepArgs& a, int b, int do_velocity, int
             s_R[1] = Ry + Vy;
             bs->R[b][0] = s_R[0];
             bs->R[b][1] = s_R[1];
-            // issued now, its atomics complete while the block sums A_i
-            publish_support(fib, win_out, s_R[0], s_R[1], nx, ny, per);
         }
         __syncthreads();
         Rx = s_R[0];
         Ry = s_R[1];
+        // the next support window and occupancy cells from the new position, by the
+        // block's last thread (its wave has the fewest nodes in the A_i sum below); the
+        // atomics complete while the block sums A_i
+        if (tid == NT - 1) publish_support(fib, win_out, Rx, Ry, nx, ny, per);
     }
 
     int i0, w, j0, j1;
