@@ -120,18 +120,22 @@ struct RecordBuf {
     double data[1];            // [cap][1 + 4 * fibers]
 };
 
-// A batch step: per simulation two StepArgs (the step parities of a chunk), prefix sums of
-// lattice tiles and of beads, item -> simulation tables and counts {simulations, tiles,
-// beads}; all in device memory, so a captured graph stays valid while the tables are
-// rewritten with the same counts (the grids are sized from the counts at launch).
+// A work item of a batch kernel: its simulation's row in the tables and its index within
+// that simulation (tile or bead); one 8-byte entry, so a block finds both in one load.
+struct ItemRef {
+    int sim, local;
+};
+
+// A batch step: per simulation two StepArgs (the step parities of a chunk), item tables
+// and counts {simulations, tiles, beads}; all in device memory, so a captured graph stays
+// valid while the tables are rewritten with the same counts (the grids are sized from the
+// counts at launch).
 struct BatchArgs {
-    const StepArgs* args;     // [2 * n]
-    const int* tile_off;      // [n + 1]
-    const int* bead_off;      // [n + 1]
-    const int* tile_sim;      // [tiles]: simulation of each lattice item
-    const int* bead_sim;      // [beads]: simulation of each bead item
-    const int* counts;        // [3]
-    int gpar;                 // parity of this step within the chunk
+    const StepArgs* args;       // [2 * n]
+    const ItemRef* tile_items;  // [tiles]: simulation and tile of each lattice item
+    const ItemRef* bead_items;  // [beads]: simulation and bead of each bead item
+    const int* counts;          // [3]
+    int gpar;                   // parity of this step within the chunk
 };
 
 // A box of nodes: columns cx0 + [0, cw) and rows cy0 + [0, ch), modulo the lattice along

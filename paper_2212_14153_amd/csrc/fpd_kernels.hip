@@ -752,9 +752,10 @@ __device__ inline StepArgs load_args(const StepArgs* table, int i) {
 
 typedef const int __attribute__((address_space(4))) ConstInt;
 
-// Simulation index of a work item from the lookup table (uniform: a scalar load).
-__device__ inline int item_sim(const int* table, int item) {
-    return ((const ConstInt*)table)[item];
+// A work item's simulation and index from its table (uniform: one scalar load of both).
+__device__ inline ItemRef item_ref(const ItemRef* table, int item) {
+    const ConstInt* e = (const ConstInt*)(table + item);
+    return ItemRef{e[0], e[1]};
 }
 
 // Lattice kernel over a batch of simulations of different sizes: one block per (simulation,
@@ -765,10 +766,9 @@ __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     __shared__ TileLds lds;
     const int item = blockIdx.x;
     if (item >= b.counts[1]) return;
-    const int s = item_sim(b.tile_sim, item);
-    const int s_off = ((const ConstInt*)b.tile_off)[s];
-    const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    tile_any<ST, SPT, BC, true>(a, tile_window(a), item - s_off, lds);
+    const ItemRef e = item_ref(b.tile_items, item);
+    const StepArgs a = load_args(b.args, 2 * e.sim + b.gpar);
+    tile_any<ST, SPT, BC, true>(a, tile_window(a), e.local, lds);
 }
 
 // ----------------------------------------------------------------- bead kernel -----
@@ -987,10 +987,9 @@ __global__ void __launch_bounds__(kBatchBeadBlock) batch_bead_kernel(BatchArgs b
     __shared__ double s_R[2];
     const int item = blockIdx.x;
     if (item >= b.counts[2]) return;
-    const int s = item_sim(b.bead_sim, item);
-    const int s_off = ((const ConstInt*)b.bead_off)[s];
-    const StepArgs a = load_args(b.args, 2 * s + b.gpar);
-    bead_block<ST, kBatchBeadVelBatch, kBatchBeadBlock>(a, item - s_off, 1, 1 - a.parity,
+    const ItemRef e = item_ref(b.bead_items, item);
+    const StepArgs a = load_args(b.args, 2 * e.sim + b.gpar);
+    bead_block<ST, kBatchBeadVelBatch, kBatchBeadBlock>(a, e.local, 1, 1 - a.parity,
                                                         scratch, s_R);
 }
 

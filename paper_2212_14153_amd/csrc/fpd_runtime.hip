@@ -1102,8 +1102,6 @@ struct fpd_batch {
     int64_t next_id = 1;
     // device work tables and their pinned host mirrors
     StepArgs* d_args = nullptr;
-    int* d_tile_off = nullptr;
-    int* d_bead_off = nullptr;
     int* d_counts = nullptr;
     BeadState** d_states = nullptr;
     unsigned* d_health = nullptr;
@@ -1113,10 +1111,10 @@ struct fpd_batch {
     int* h_counts = nullptr;
     BeadState** h_states = nullptr;
     unsigned* h_health = nullptr;
-    int* d_tile_sim = nullptr;   // item -> simulation row lookup tables (device, pinned host)
-    int* d_bead_sim = nullptr;
-    int* h_tile_sim = nullptr;
-    int* h_bead_sim = nullptr;
+    ItemRef* d_tile_items = nullptr;   // item tables (device, pinned host)
+    ItemRef* d_bead_items = nullptr;
+    ItemRef* h_tile_items = nullptr;
+    ItemRef* h_bead_items = nullptr;
     int cap_tiles = 0, cap_beads = 0;
     std::vector<int> table;  // entry index of table row r
     bool dirty = true;
@@ -1184,8 +1182,8 @@ int batch_rebuild(fpd_batch* b) {
     if (b->graph && (b->graph_counts[0] != r || b->graph_counts[1] != tiles ||
                      b->graph_counts[2] != beads || b->graph_periodic != b->any_periodic))
         batch_drop_graph(b);  // its grids or kernel variant no longer match the tables
-    // item -> simulation lookup tables (grown geometrically; a new pointer drops the graph)
-    auto grow = [&](int need, int& cap, int*& d, int*& h) -> int {
+    // item tables (grown geometrically; a new pointer drops the graph)
+    auto grow = [&](int need, int& cap, ItemRef*& d, ItemRef*& h) -> int {
         if (need <= cap) return FPD_OK;
         int ncap = cap > 0 ? cap : 1024;
         while (ncap < need) ncap *= 2;
@@ -1194,32 +1192,30 @@ int batch_rebuild(fpd_batch* b) {
         d = nullptr;
         h = nullptr;
         cap = 0;
-        if (hipMalloc((void**)&d, sizeof(int) * ncap) != hipSuccess ||
-            hipHostMalloc((void**)&h, sizeof(int) * ncap, 0) != hipSuccess)
+        if (hipMalloc((void**)&d, sizeof(ItemRef) * ncap) != hipSuccess ||
+            hipHostMalloc((void**)&h, sizeof(ItemRef) * ncap, 0) != hipSuccess)
             return fail(FPD_ENOMEM, "batch item table allocation failed");
         cap = ncap;
         batch_drop_graph(b);
         return FPD_OK;
     };
-    int rc = grow(tiles, b->cap_tiles, b->d_tile_sim, b->h_tile_sim);
-    if (rc == FPD_OK) rc = grow(beads, b->cap_beads, b->d_bead_sim, b->h_bead_sim);
+    int rc = grow(tiles, b->cap_tiles, b->d_tile_items, b->h_tile_items);
+    if (rc == FPD_OK) rc = grow(beads, b->cap_beads, b->d_bead_items, b->h_bead_items);
     if (rc) return rc;
     for (int q = 0; q < r; ++q) {
-        for (int t = b->h_tile_off[q]; t < b->h_tile_off[q + 1]; ++t) b->h_tile_sim[t] = q;
-        for (int t = b->h_bead_off[q]; t < b->h_bead_off[q + 1]; ++t) b->h_bead_sim[t] = q;
+        for (int t = b->h_tile_off[q]; t < b->h_tile_off[q + 1]; ++t)
+            b->h_tile_items[t] = ItemRef{q, t - b->h_tile_off[q]};
+        for (int t = b->h_bead_off[q]; t < b->h_bead_off[q + 1]; ++t)
+            b->h_bead_items[t] = ItemRef{q, t - b->h_bead_off[q]};
     }
     if (tiles > 0)
-        HIP_TRY(hipMemcpyAsync(b->d_tile_sim, b->h_tile_sim, sizeof(int) * tiles,
+        HIP_TRY(hipMemcpyAsync(b->d_tile_items, b->h_tile_items, sizeof(ItemRef) * tiles,
                                hipMemcpyHostToDevice, b->stream));
     if (beads > 0)
-        HIP_TRY(hipMemcpyAsync(b->d_bead_sim, b->h_bead_sim, sizeof(int) * beads,
+        HIP_TRY(hipMemcpyAsync(b->d_bead_items, b->h_bead_items, sizeof(ItemRef) * beads,
                                hipMemcpyHostToDevice, b->stream));
     if (r > 0) {
         HIP_TRY(hipMemcpyAsync(b->d_args, b->h_args, sizeof(StepArgs) * 2 * r,
-                               hipMemcpyHostToDevice, b->stream));
-        HIP_TRY(hipMemcpyAsync(b->d_tile_off, b->h_tile_off, sizeof(int) * (r + 1),
-                               hipMemcpyHostToDevice, b->stream));
-        HIP_TRY(hipMemcpyAsync(b->d_bead_off, b->h_bead_off, sizeof(int) * (r + 1),
                                hipMemcpyHostToDevice, b->stream));
         HIP_TRY(hipMemcpyAsync(b->d_states, b->h_states, sizeof(BeadState*) * r,
                                hipMemcpyHostToDevice, b->stream));
@@ -1231,8 +1227,7 @@ int batch_rebuild(fpd_batch* b) {
 }
 
 int batch_enqueue(fpd_batch* b, int gpar) {
-    BatchArgs a{b->d_args, b->d_tile_off, b->d_bead_off, b->d_tile_sim, b->d_bead_sim,
-                b->d_counts, gpar};
+    BatchArgs a{b->d_args, b->d_tile_items, b->d_bead_items, b->d_counts, gpar};
     const dim3 block(b->launch.block_x, b->launch.block_y);
     HIP_TRY(launch_batch_step(b->storage, a, block, b->launch.rows_per_thread, b->h_counts,
                               b->any_periodic, b->stream));
@@ -1294,8 +1289,6 @@ int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage
     }
     const size_t n = (size_t)max_slots;
     bool ok = hipMalloc((void**)&b->d_args, sizeof(StepArgs) * 2 * n) == hipSuccess &&
-              hipMalloc((void**)&b->d_tile_off, sizeof(int) * (n + 1)) == hipSuccess &&
-              hipMalloc((void**)&b->d_bead_off, sizeof(int) * (n + 1)) == hipSuccess &&
               hipMalloc((void**)&b->d_counts, sizeof(int) * 3) == hipSuccess &&
               hipMalloc((void**)&b->d_states, sizeof(BeadState*) * n) == hipSuccess &&
               hipMalloc((void**)&b->d_health, sizeof(unsigned) * n) == hipSuccess &&
@@ -1322,15 +1315,13 @@ void fpd_batch_destroy(fpd_batch* b) {
     for (auto& e : b->entries) fpd_destroy(e.sim);
     b->entries.clear();
     (void)hipFree(b->d_args);
-    (void)hipFree(b->d_tile_off);
-    (void)hipFree(b->d_bead_off);
     (void)hipFree(b->d_counts);
     (void)hipFree(b->d_states);
     (void)hipFree(b->d_health);
-    (void)hipFree(b->d_tile_sim);
-    (void)hipFree(b->d_bead_sim);
-    (void)hipHostFree(b->h_tile_sim);
-    (void)hipHostFree(b->h_bead_sim);
+    (void)hipFree(b->d_tile_items);
+    (void)hipFree(b->d_bead_items);
+    (void)hipHostFree(b->h_tile_items);
+    (void)hipHostFree(b->h_bead_items);
     (void)hipHostFree(b->h_args);
     (void)hipHostFree(b->h_tile_off);
     (void)hipHostFree(b->h_bead_off);
