@@ -37,7 +37,8 @@ Other modes (each prints one JSON line):
                  Eq. (13) and the exact smooth solution;
   --mode shapes  the shape diagrams of Sec. IV.C (K x C at Re_ps = 1.5, Re_ps x C at
                  K = 3.3e-5, and the stuck cases of rigid and slightly flexible fibers) as
-                 one batch of recorded runs, each classified from its fiber-ends record.
+                 recorded runs in two batches on two streams advanced together, each run
+                 classified from its fiber-ends record.
 """
 from __future__ import annotations
 
@@ -263,7 +264,7 @@ def plain_fifo(_lib, ws, arrivals, steps, storage, stream):
 
 
 def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512, chunk=200,
-              budget_gb=64, seed=50):
+              budget_gb=64, seed=50, lanes=1):
     """C5 at one arrival rate: `n_req` Poisson arrivals of sweep simulations served with
     continuous batching, and the first `n_plain` of the same arrivals through the measured
     plain FIFO server.  Returns the result keys (p50 / p99 over the requests after
@@ -278,7 +279,7 @@ def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512,
             for i, (p, w, t) in enumerate(zip(params, ws, arrivals))]
     log(f"serve: {n_req} requests at {rate:.1f}/s, {steps} steps each, storage {storage}")
     srv = serve.Server(storage, hbm_budget=budget_gb << 30, max_slots=slots, chunk=chunk,
-                       stream=stream.cuda_stream, launch=dict(graph_chunk=32))
+                       stream=stream.cuda_stream, launch=dict(graph_chunk=32), lanes=lanes)
     done = srv.serve(reqs)
     srv.close()
     summ = serve.summarize(done, warmup=warmup)
@@ -296,6 +297,7 @@ def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512,
     pct = lambda a, q: round(float(np.percentile(a, q)), 3)  # noqa: E731
     return {
         "rate_per_s": round(rate, 3), "requests": n_req - warmup, "warmup": warmup,
+        "lanes": lanes,
         "completed": summ["completed"], "sims_per_s": round(summ["sims_per_s"], 3),
         "p50_s": round(summ["p50_s"], 3), "p99_s": round(summ["p99_s"], 3),
         "mean_s": round(summ["mean_s"], 3), "span_s": round(summ["span_s"], 2),
@@ -334,7 +336,7 @@ def main_serve(args):
     storage = args.storage if args.storage in ("f16dev", "bf16dev") else "f16dev"
     r = serve_run(stream, storage, args.requests + args.serve_warmup, args.sweep_steps,
                   args.rate, args.plain_requests, warmup=args.serve_warmup, slots=args.slots,
-                  chunk=args.chunk, budget_gb=args.hbm_budget_gb)
+                  chunk=args.chunk, budget_gb=args.hbm_budget_gb, lanes=args.serve_lanes)
     out = {
         "metric": "served sims/s at p50/p99 time-to-result", "value": r["sims_per_s"],
         "unit": "sims/s", "n_gpus": 1, "steps": args.sweep_steps, "warmup": args.serve_warmup,
@@ -554,26 +556,30 @@ def main_shapes(args):
     budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
     log(f"shape sweep: {len(ws)} channels, {nodes / 1e6:.2f}M nodes, {steps} steps "
         f"(gamma t = {gamma * steps:.0f}), storage {storage}")
-    b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
-    ids = [b.add(p, w.beads(), steps) for p, w in zip(params, ws)]
-    for sid in ids:
+    # the runs split over args.shape_batches batches on as many streams, advanced together
+    # (one batch's bead and force kernels overlap another's lattice kernel)
+    nb = max(1, min(args.shape_batches, len(ws)))
+    streams = [stream] + [torch.cuda.Stream() for _ in range(nb - 1)]
+    batches = [_lib.Batch(budget, len(ws), storage=storage, stream=s.cuda_stream)
+               for s in streams]
+    placed = []
+    for i, (p, w) in enumerate(zip(params, ws)):
+        b = batches[i % nb]
+        sid = b.add(p, w.beads(), steps)
         b.record_start(sid, every, steps // every + 8)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+        placed.append((b, sid))
     torch.cuda.synchronize()
-    e0.record(stream)
     left, t0 = steps, time.perf_counter()
     while left > 0:
-        adv = b.run(min(left, 25000))
+        adv = max(_lib.run_batches(batches, min(left, 25000)))
         if adv == 0:
             break
         left -= adv
         log(f"  {steps - left} steps, {time.perf_counter() - t0:.1f} s")
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
     rows = []
-    for (diag, k, c, r), w, sid in zip(pts, ws, ids):
+    for (diag, k, c, r), w, (b, sid) in zip(pts, ws, placed):
         done, status, hflags = b.info(sid)
         row = {"diagram": diag, "K": k, "C": round(w.confinement, 4), "Re_ps": r,
                "status": int(status), "health": int(hflags), "steps": int(done)}
@@ -592,7 +598,8 @@ def main_shapes(args):
         else:
             row["orbit"] = "failed"
         rows.append(row)
-    b.close()
+    for b in batches:
+        b.close()
     mlups = nodes * steps / (ms * 1e-3) / 1e6
     bytes_alg = 18 * BYTES_PER_VALUE[storage] * nodes
     achieved = bytes_alg * steps / (ms * 1e-3) / 1e9
@@ -609,10 +616,11 @@ def main_shapes(args):
         "config": {"workload": f"{len(ws)} confined-Couette fiber runs, N = 10, d = 8, "
                                f"H = N d / C, L_x = 25 d, r_eta = 100, xi = d / 8, "
                                f"gamma = {gamma:g}, recorded every {every} steps",
-                   "nodes_total": nodes, "parallelism": "single GPU"},
+                   "nodes_total": nodes, "batches": nb, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "kernel": "whole batch step (all kernels)",
+                     "traffic": None,
+                     "kernel": f"whole step of all runs ({nb} batches on {nb} streams)",
                      "bytes_per_launch_alg": bytes_alg},
         "runs": rows,
     }
@@ -716,6 +724,8 @@ def main():
     ap.add_argument("--mode", default="plain",
                     choices=["plain", "batch", "serve", "particle", "sandwich", "shapes"])
     ap.add_argument("--shape-steps", type=int, default=400000)
+    ap.add_argument("--shape-batches", type=int, default=2,
+                    help="batches (streams) the shape runs are split over")
     ap.add_argument("--sandwich-steps", type=int, default=4000)
     ap.add_argument("--particles", type=int, default=64)
     ap.add_argument("--particle-steps", type=int, default=90000)
@@ -731,6 +741,8 @@ def main():
     ap.add_argument("--plain-requests", type=int, default=40)
     ap.add_argument("--slots", type=int, default=512)
     ap.add_argument("--chunk", type=int, default=200)
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="batches (streams) the server spreads its requests over")
     ap.add_argument("--hbm-budget-gb", type=int, default=64)
     # sizes of the bounded runs added to the default line
     ap.add_argument("--x-sweep-sims", type=int, default=256)
@@ -818,11 +830,12 @@ def main():
         out["sweep_c4"] = sweep_run(stream, "f32", args.x_sweep_sims, args.x_sweep_steps,
                                     args.x_sweep_plain)
         at50 = serve_run(stream, "f16dev", args.x_serve_requests, args.x_serve_steps, 50.0,
-                         args.x_serve_plain)
+                         args.x_serve_plain, lanes=args.serve_lanes)
         cap = at50["sims_per_s"]
         at08 = serve_run(stream, "f16dev", args.x_serve_requests, args.x_serve_steps,
-                         0.8 * cap, args.x_serve_plain)
+                         0.8 * cap, args.x_serve_plain, lanes=args.serve_lanes)
         out["serve_c5"] = {"storage": "f16dev", "steps": args.x_serve_steps,
+                           "lanes": args.serve_lanes,
                            "capacity_sims_per_s": cap, "at_50_per_s": at50,
                            "at_0.8_capacity": at08}
     if not args.no_cpu_baseline:

@@ -371,6 +371,18 @@ int fpd_batch_add(fpd_batch *b, const fpd_params *p, const double *R, int64_t n_
  * Synchronises; FPD_EDEVICE on a HIP error. */
 int fpd_batch_run(fpd_batch *b, int64_t max_steps, int64_t *advanced);
 
+/* fpd_batch_run in two halves, so that batches on different streams advance at the same
+ * time from one host thread (while one batch's latency-bound bead and force kernels run,
+ * another's lattice kernel fills the device).  fpd_batch_launch enqueues on the batch's
+ * stream the steps fpd_batch_run would take and the health read-back, and returns without
+ * waiting (*advanced receives the step count, 0 when none is active); fpd_batch_wait waits
+ * for them and then updates step counts and statuses as fpd_batch_run does (FPD_OK at once
+ * when nothing is pending).  While a launch is pending every other call on the batch
+ * except fpd_batch_poll, fpd_batch_stats and fpd_batch_destroy fails with FPD_EINVAL, and
+ * fpd_batch_poll reports statuses as of the last wait.  FPD_EDEVICE on a HIP error. */
+int fpd_batch_launch(fpd_batch *b, int64_t max_steps, int64_t *advanced);
+int fpd_batch_wait(fpd_batch *b);
+
 /* Simulations that became DONE or FAILED since the last poll: ids[i], status[i]
  * (up to cap; *n receives the count). */
 int fpd_batch_poll(fpd_batch *b, int64_t *ids, int32_t *status, int32_t cap, int32_t *n);

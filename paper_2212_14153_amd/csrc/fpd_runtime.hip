@@ -1118,6 +1118,8 @@ struct fpd_batch {
     int cap_tiles = 0, cap_beads = 0;
     std::vector<int> table;  // entry index of table row r
     bool dirty = true;
+    bool pending = false;        // steps enqueued by fpd_batch_launch, not yet waited for
+    int64_t pending_steps = 0;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     int graph_counts[3] = {0, 0, 0};  // counts the graph's grids were sized for
@@ -1265,6 +1267,12 @@ size_t fpd_sim_footprint(const fpd_params* p) {
     return footprint_of(p);
 }
 
+// FPD_EINVAL while steps enqueued by fpd_batch_launch await fpd_batch_wait.
+static int batch_idle(const fpd_batch* b) {
+    if (b->pending) return fail(FPD_EINVAL, "a launch is pending: call fpd_batch_wait first");
+    return FPD_OK;
+}
+
 int fpd_batch_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t storage,
                      void* hip_stream, fpd_batch** out) {
     if (!out) return fail(FPD_EINVAL, "out is NULL");
@@ -1334,6 +1342,7 @@ void fpd_batch_destroy(fpd_batch* b) {
 
 int fpd_batch_set_launch(fpd_batch* b, const fpd_launch* c) {
     if (!b || !c) return fail(FPD_EINVAL, "NULL argument");
+    if (b->pending) return batch_idle(b);
     fpd_launch n;
     int rc = merge_launch(b->launch, c, n);  // checked before any member changes
     if (rc) return rc;
@@ -1351,6 +1360,7 @@ int fpd_batch_set_launch(fpd_batch* b, const fpd_launch* c) {
 int fpd_batch_add(fpd_batch* b, const fpd_params* p, const double* R, int64_t n_steps,
                   int64_t* sim_id) {
     if (!b || !p || !sim_id) return fail(FPD_EINVAL, "NULL argument");
+    if (b->pending) return batch_idle(b);
     if (n_steps < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
     int rc = validate(p);
     if (rc) return rc;
@@ -1383,9 +1393,11 @@ int fpd_batch_add(fpd_batch* b, const fpd_params* p, const double* R, int64_t n_
     return FPD_OK;
 }
 
-int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
+int fpd_batch_launch(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
     if (!b) return fail(FPD_EINVAL, "NULL batch");
     if (advanced) *advanced = 0;
+    int rc = batch_idle(b);
+    if (rc) return rc;
     if (max_steps <= 0) return FPD_OK;
     int64_t steps = max_steps;
     int active = 0;
@@ -1397,7 +1409,7 @@ int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
     if (active == 0) return FPD_OK;
     HIP_TRY(hipStreamSynchronize(b->stream));
     if (b->dirty) {
-        int rc = batch_rebuild(b);
+        rc = batch_rebuild(b);
         if (rc) return rc;
     }
     int64_t left = steps;
@@ -1405,7 +1417,7 @@ int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
     if (left >= chunk) {
         if (b->graph_chunk != chunk) {
             batch_drop_graph(b);
-            int rc = batch_build_graph(b, chunk);
+            rc = batch_build_graph(b, chunk);
             if (rc) return rc;
         }
         while (left >= chunk) {
@@ -1414,16 +1426,29 @@ int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
         }
     }
     for (int i = 0; left > 0; --left, ++i) {
-        int rc = batch_enqueue(b, i & 1);
+        rc = batch_enqueue(b, i & 1);
         if (rc) return rc;
     }
-    // bookkeeping and health
+    // health of every simulation, read back once the steps are done
     const int rows = (int)b->table.size();
     HIP_TRY(health_gather(b->d_states, b->d_health, rows, b->stream));
     if (rows > 0)
         HIP_TRY(hipMemcpyAsync(b->h_health, b->d_health, sizeof(unsigned) * rows,
                                hipMemcpyDeviceToHost, b->stream));
+    b->pending = true;
+    b->pending_steps = steps;
+    if (advanced) *advanced = steps;
+    return FPD_OK;
+}
+
+int fpd_batch_wait(fpd_batch* b) {
+    if (!b) return fail(FPD_EINVAL, "NULL batch");
+    if (!b->pending) return FPD_OK;
     HIP_TRY(hipStreamSynchronize(b->stream));
+    b->pending = false;
+    const int64_t steps = b->pending_steps;
+    b->pending_steps = 0;
+    const int rows = (int)b->table.size();
     for (int r = 0; r < rows; ++r) {
         BatchEntry& e = b->entries[b->table[r]];
         e.remaining -= steps;
@@ -1437,8 +1462,13 @@ int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
         if (e.status != FPD_SIM_ACTIVE) b->dirty = true;
     }
     if (steps & 1) b->dirty = true;
-    if (advanced) *advanced = steps;
     return FPD_OK;
+}
+
+int fpd_batch_run(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
+    const int rc = fpd_batch_launch(b, max_steps, advanced);
+    if (rc) return rc;
+    return fpd_batch_wait(b);
 }
 
 int fpd_batch_poll(fpd_batch* b, int64_t* ids, int32_t* status, int32_t cap, int32_t* n) {
@@ -1458,12 +1488,14 @@ int fpd_batch_poll(fpd_batch* b, int64_t* ids, int32_t* status, int32_t cap, int
 }
 
 int fpd_batch_read_beads(fpd_batch* b, int64_t id, double* R, double* V, double* F) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     return fpd_read_beads(e->sim, R, V, F);
 }
 
 int fpd_batch_read_populations(fpd_batch* b, int64_t id, double* f) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     return fpd_read_populations(e->sim, f);
@@ -1471,12 +1503,14 @@ int fpd_batch_read_populations(fpd_batch* b, int64_t id, double* f) {
 
 int fpd_batch_read_fields(fpd_batch* b, int64_t id, double* rho, double* ux, double* uy,
                           double* eta) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     return fpd_read_fields(e->sim, rho, ux, uy, eta);
 }
 
 int fpd_batch_set_static_phi(fpd_batch* b, int64_t id, const double* phi) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -1486,6 +1520,7 @@ int fpd_batch_set_static_phi(fpd_batch* b, int64_t id, const double* phi) {
 }
 
 int fpd_batch_record_start(fpd_batch* b, int64_t id, int32_t every, int64_t capacity) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -1495,6 +1530,7 @@ int fpd_batch_record_start(fpd_batch* b, int64_t id, int32_t every, int64_t capa
 }
 
 int fpd_batch_record_read(fpd_batch* b, int64_t id, double* out, int64_t cap, int64_t* n) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -1502,6 +1538,7 @@ int fpd_batch_record_read(fpd_batch* b, int64_t id, double* out, int64_t cap, in
 }
 
 int fpd_batch_particle_stats(fpd_batch* b, int64_t id, int32_t bead, double* out) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     return fpd_particle_stats(e->sim, bead, out);
@@ -1509,6 +1546,7 @@ int fpd_batch_particle_stats(fpd_batch* b, int64_t id, int32_t bead, double* out
 
 int fpd_batch_sim_info(fpd_batch* b, int64_t id, int64_t* steps, int32_t* status,
                        uint32_t* health) {
+    if (b && b->pending) return batch_idle(b);
     BatchEntry* e = b ? find_entry(b, id) : nullptr;
     if (!e) return fail(FPD_EINVAL, "unknown simulation %lld", (long long)id);
     if (steps) *steps = e->sim->steps;
@@ -1523,6 +1561,7 @@ int fpd_batch_sim_info(fpd_batch* b, int64_t id, int64_t* steps, int32_t* status
 
 int fpd_batch_release(fpd_batch* b, int64_t id) {
     if (!b) return fail(FPD_EINVAL, "NULL batch");
+    if (b->pending) return batch_idle(b);
     for (size_t i = 0; i < b->entries.size(); ++i)
         if (b->entries[i].id == id) {
             HIP_TRY(hipStreamSynchronize(b->stream));

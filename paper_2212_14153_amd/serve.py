@@ -31,6 +31,7 @@ class Request:
     beads: np.ndarray = field(default=None)   # final R
     populations: np.ndarray = field(default=None)   # final f[9, ny, nx] (if asked for)
     sim_id: int = 0
+    lane: int = 0                  # the server's batch that ran it
 
     @property
     def latency(self) -> float:
@@ -38,19 +39,32 @@ class Request:
 
 
 class Server:
-    """Admission by slots and HBM footprint; chunked execution; read-back on completion."""
+    """Admission by slots and HBM footprint; chunked execution; read-back on completion.
+
+    With lanes > 1 the budget and slots are split over that many device batches, each on
+    its own stream, advanced together (one batch's latency-bound bead kernels overlap
+    another's lattice kernel); a request goes to the lane with the fewest nodes admitted."""
 
     def __init__(self, storage: str, hbm_budget: int, max_slots: int, chunk: int = 200,
                  stream=None, launch=None, clock=time.perf_counter, batch=None,
-                 read_populations: bool = False):
-        # `batch` may be any object with the Batch methods used below (try_add, run, poll,
-        # beads, release, set_launch, close; populations if read_populations); by default
-        # the device batch of the C ABI.  read_populations: read every finished
-        # simulation's populations back too (Request.populations).
-        self.batch = batch if batch is not None else _lib.Batch(hbm_budget, max_slots,
-                                                                 storage=storage, stream=stream)
+                 read_populations: bool = False, lanes: int = 1):
+        # `batch` may be any object with the Batch methods used below (try_add, launch,
+        # wait, poll, beads, release, set_launch, close; populations if read_populations),
+        # or a list of them (one per lane); by default the device batches of the C ABI.
+        # read_populations: read every finished simulation's populations back too
+        # (Request.populations).
+        if batch is not None:
+            self.batches = list(batch) if isinstance(batch, (list, tuple)) else [batch]
+        else:
+            lanes = max(1, int(lanes))
+            self.batches = [_lib.Batch(hbm_budget // lanes, max(1, max_slots // lanes),
+                                       storage=storage, stream=stream if lanes == 1 else None)
+                            for _ in range(lanes)]
+        self.batch = self.batches[0]
+        self.load = [0] * len(self.batches)   # nodes admitted per lane
         if launch:
-            self.batch.set_launch(launch)
+            for b in self.batches:
+                b.set_launch(launch)
         self.chunk = int(chunk)
         self.read_populations = bool(read_populations)
         self.clock = clock
@@ -60,7 +74,8 @@ class Server:
         self.done = []
 
     def close(self):
-        self.batch.close()
+        for b in self.batches:
+            b.close()
 
     def now(self) -> float:
         return self.clock() - self.t0
@@ -68,27 +83,36 @@ class Server:
     def _admit(self):
         while self.waiting:
             req = self.waiting[0]
-            sid = self.batch.try_add(req.params, req.R, req.steps)
+            nodes = int(req.params.nx) * int(req.params.ny)
+            sid = None
+            for lane in sorted(range(len(self.batches)), key=lambda k: self.load[k]):
+                sid = self.batches[lane].try_add(req.params, req.R, req.steps)
+                if sid is not None:
+                    break
             if sid is None:
                 if not self.running:
                     raise RuntimeError(f"request {req.rid} does not fit an empty batch")
                 break
             self.waiting.popleft()
             req.sim_id = sid
+            req.lane = lane
             req.admitted = self.now()
-            self.running[sid] = req
+            self.load[lane] += nodes
+            self.running[(lane, sid)] = req
 
     def _collect(self):
-        for sid, status in self.batch.poll():
-            req = self.running.pop(sid)
-            req.status = status
-            if status == _lib.FPD_SIM_DONE:
-                req.beads = self.batch.beads(sid)[0]
-                if self.read_populations:
-                    req.populations = self.batch.populations(sid)
-            req.finished = self.now()
-            self.batch.release(sid)
-            self.done.append(req)
+        for lane, b in enumerate(self.batches):
+            for sid, status in b.poll():
+                req = self.running.pop((lane, sid))
+                req.status = status
+                if status == _lib.FPD_SIM_DONE:
+                    req.beads = b.beads(sid)[0]
+                    if self.read_populations:
+                        req.populations = b.populations(sid)
+                req.finished = self.now()
+                b.release(sid)
+                self.load[lane] -= int(req.params.nx) * int(req.params.ny)
+                self.done.append(req)
 
     def serve(self, requests, idle_sleep: float = 1e-3):
         """Serve `requests` (sorted by arrival time, seconds from start) to completion;
@@ -102,7 +126,7 @@ class Server:
                 self.waiting.append(pending.popleft())
             self._admit()
             if self.running:
-                self.batch.run(self.chunk)
+                _lib.run_batches(self.batches, self.chunk, slice_steps=self.chunk)
                 self._collect()
             elif pending:
                 time.sleep(min(idle_sleep, max(0.0, pending[0].arrival - self.now())))

@@ -139,3 +139,46 @@ def test_invalid_batch_launch_is_refused_before_any_change(bad):
         # the batch and its members keep the launch they had and still run
         assert b.run(20) == 20
         assert sorted(sid for sid, st in b.poll() if st == _lib.FPD_SIM_DONE) == sorted(ids)
+
+
+def test_batches_on_two_streams_advance_together():
+    """fpd_batch_launch / fpd_batch_wait: two batches on two streams advanced together give
+    each simulation's result as run alone, bitwise; while a launch is pending the batch
+    refuses other calls."""
+    import torch
+    ws = small_sweep("f32", seed=11)
+    print(f"[case] two streams {[(w.nx, w.ny, w.n_beads) for w in ws]}", flush=True)
+    targets = [120, 64, 120, 90, 32, 120]
+    alone = []
+    for w, t in zip(ws, targets):
+        with _lib.simulation_from_workload(w) as sim:
+            sim.step(t)
+            alone.append(sim.beads()[0])
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    batches = [_lib.Batch(hbm_budget=1 << 33, max_slots=8, storage="f32",
+                          stream=s.cuda_stream) for s in streams]
+    try:
+        where = {}
+        for i, (w, t) in enumerate(zip(ws, targets)):
+            b = batches[i % 2]
+            b.set_launch(dict(graph_chunk=8))
+            where[i] = (b, b.add(_lib.params_from_mapping(w.params()), w.beads(), t))
+        # the pending guard: a read during a launch is refused, the launch still completes
+        b0, sid0 = where[0]
+        assert b0.launch(16) == 16
+        with pytest.raises(_lib.FpdError):
+            b0.beads(sid0)
+        b0.wait()
+        b0.wait()  # nothing pending: a no-op
+        done = {}
+        while len(done) < len(ws):
+            adv = _lib.run_batches(batches, 20)
+            assert max(adv) > 0
+            for i, (b, sid) in where.items():
+                if i not in done and b.info(sid)[1] == _lib.FPD_SIM_DONE:
+                    done[i] = b.beads(sid)[0]
+        for i in range(len(ws)):
+            assert np.array_equal(done[i], alone[i]), i
+    finally:
+        for b in batches:
+            b.close()

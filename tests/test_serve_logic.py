@@ -1,6 +1,8 @@
 """Scheduling logic of the continuous-batching server, on the CPU with a fake batch that
 models slots, an HBM budget and per-step cost (no GPU; the device batch is tested in
 test_gpu_batch.py / test_gpu_serve.py)."""
+import types
+
 import numpy as np
 import pytest
 
@@ -33,12 +35,12 @@ class FakeBatch:
         return sum(m["bytes"] for m in self.members.values())
 
     def try_add(self, params, R, steps):
-        need = params["nodes"] * 36
+        need = params.nodes * 36
         if len(self.members) >= self.slots or self.used() + need > self.budget:
             return None
         sid = self.next
         self.next += 1
-        self.members[sid] = {"nodes": params["nodes"], "left": steps, "bytes": need,
+        self.members[sid] = {"nodes": params.nodes, "left": steps, "bytes": need,
                              "R": np.asarray(R) + steps, "reported": False}
         self.max_concurrent = max(self.max_concurrent, len(self.members))
         self.max_used = max(self.max_used, self.used())
@@ -53,6 +55,12 @@ class FakeBatch:
         for m in act:
             m["left"] -= s
         return s
+
+    def launch(self, k):   # the device batch's asynchronous half; wait() completes it
+        return self.run(k)
+
+    def wait(self):
+        pass
 
     def poll(self):
         out = []
@@ -80,13 +88,18 @@ class Clock:
 def make_requests(n, rate, seed=1, steps=1000):
     t = workloads.poisson_arrivals(n, rate=rate, seed=seed)
     rng = np.random.default_rng(seed)
-    return [serve.Request(i, {"nodes": int(rng.integers(1000, 5000))}, np.zeros((2, 2)), steps,
-                          float(t[i])) for i in range(n)]
+    reqs = []
+    for i in range(n):
+        nodes = int(rng.integers(1000, 5000))
+        p = types.SimpleNamespace(nodes=nodes, nx=nodes, ny=1)
+        reqs.append(serve.Request(i, p, np.zeros((2, 2)), steps, float(t[i])))
+    return reqs
 
 
-def run_server(reqs, slots, budget, chunk=100):
+def run_server(reqs, slots, budget, chunk=100, lanes=1):
     clock = Clock()
-    fb = FakeBatch(slots, budget, clock)
+    fbs = [FakeBatch(slots, budget, clock) for _ in range(lanes)]
+    fb = fbs[0] if lanes == 1 else fbs
     orig = serve._lib.FPD_SIM_DONE
     srv = serve.Server("f16dev", budget, slots, chunk=chunk, clock=clock, batch=fb)
     # the fake clock only moves when work runs: idle waits jump to the next arrival
@@ -149,3 +162,47 @@ def test_summary_percentiles_and_fifo_replay():
     # single FIFO server: waiting accumulates when service exceeds the gaps
     lat_f = serve.fifo_replay([0.0, 0.1, 0.2], [0.5, 0.5, 0.5])
     assert np.allclose(lat_f, [0.5, 0.9, 1.3])
+
+
+def test_run_batches_interleaves_launches_and_stops():
+    """run_batches: every round enqueues each live batch before any wait, slices are
+    bounded, a batch whose simulations are done (launch returns 0) drops out."""
+    from paper_2212_14153_amd import _lib
+    log = []
+
+    class FakeBatch:
+        def __init__(self, name, remaining):
+            self.name, self.remaining, self.pending = name, remaining, False
+
+        def launch(self, n):
+            assert not self.pending
+            adv = min(n, self.remaining)
+            self.remaining -= adv
+            self.pending = True
+            log.append(("launch", self.name, adv))
+            return adv
+
+        def wait(self):
+            self.pending = False
+            log.append(("wait", self.name))
+
+    a, b = FakeBatch("a", 1000), FakeBatch("b", 300)
+    assert _lib.run_batches([a, b], 700, slice_steps=256) == [700, 300]
+    assert (a.remaining, b.remaining) == (300, 0)
+    # first round: both launched, then both waited
+    assert log[:4] == [("launch", "a", 256), ("launch", "b", 256), ("wait", "a"),
+                       ("wait", "b")]
+    assert max(n for kind, *rest in log if kind == "launch" for n in rest[1:]) <= 256
+    assert not a.pending and not b.pending
+
+
+def test_requests_spread_over_lanes():
+    """Two batches (lanes): every request completes, each in one lane, both lanes take
+    work, and the result is the request's own."""
+    reqs = make_requests(40, rate=200.0, steps=500)
+    done, fbs = run_server(reqs, slots=8, budget=1 << 40, chunk=100, lanes=2)
+    assert sorted(r.rid for r in done) == list(range(40))
+    assert {r.lane for r in done} == {0, 1}
+    for r in done:
+        assert r.status == DONE and np.array_equal(r.beads, np.zeros((2, 2)) + 500)
+    assert all(not fb.members for fb in fbs)
