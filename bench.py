@@ -165,10 +165,12 @@ def run_plain_path(_lib, ws, storage, steps, stream):
     return times, finals
 
 
-def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153):
+def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153, batches=None):
     """C4: `sims` sweep simulations advanced together by the batch kernels (graph replay,
     launch shape from the autotuner), against the plain path measured on a seeded random
-    sample of `plain_sims` of them.  Returns the result keys."""
+    sample of `plain_sims` of them.  `batches` (default: two for the two-byte formats, one
+    otherwise) splits them over that many batches on as many streams, balanced by nodes.
+    Returns the result keys."""
     import numpy as np
     import workloads
     from paper_2212_14153_amd import _lib, autotune
@@ -189,31 +191,43 @@ def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153):
     if tune:
         cfg, _ = autotune.tune_batch(make_batch, storage, nodes)
         log(f"autotuned launch {cfg}")
-    b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
-    if cfg:
-        b.set_launch(dict(cfg, graph_chunk=32))
-    ids = [b.add(p, w.beads(), steps) for p, w in zip(params, ws)]
-    stream.synchronize()
+    import torch
+    nb = batches or (2 if storage in ("f16dev", "bf16dev") else 1)
+    streams = [stream] + [torch.cuda.Stream() for _ in range(nb - 1)]
+    bs = [_lib.Batch(budget, len(ws), storage=storage, stream=s.cuda_stream) for s in streams]
+    load = [0] * nb
+    ids = [None] * len(ws)
+    for i in sorted(range(len(ws)), key=lambda i: -ws[i].nx * ws[i].ny):
+        k = load.index(min(load))      # largest first onto the lighter batch
+        load[k] += ws[i].nx * ws[i].ny
+        ids[i] = (k, None)
+    for b in bs:
+        if cfg:
+            b.set_launch(dict(cfg, graph_chunk=32))
+    ids = [(k, bs[k].add(p, w.beads(), steps)) for (k, _), p, w in zip(ids, params, ws)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     finish = {}
     while len(finish) < len(ids):
-        if b.run(steps) == 0:
+        if max(_lib.run_batches(bs, steps)) == 0:
             break
         t = time.perf_counter() - t0
-        for sid, st in b.poll():
-            finish[sid] = (t, st)
+        for k, b in enumerate(bs):
+            for sid, st in b.poll():
+                finish[(k, sid)] = (t, st)
     wall = time.perf_counter() - t0
     ok = sum(1 for t, st in finish.values() if st == _lib.FPD_SIM_DONE)
     rng = np.random.default_rng(seed + 1)
     pick = sorted(rng.choice(len(ws), size=min(plain_sims, len(ws)), replace=False).tolist())
-    batch_R = [b.beads(ids[i])[0] for i in pick]
-    b.close()
+    batch_R = [bs[ids[i][0]].beads(ids[i][1])[0] for i in pick]
+    for b in bs:
+        b.close()
     log(f"batched: {wall:.2f} s for {len(ids)} simulations ({ok} done); plain path on "
         f"{len(pick)} of them")
     out = {
         "workload": f"sweep of {len(ws)} simulations (seed {seed}), 128x64..1024x512, "
                     f"{steps} steps each, {storage}",
-        "sims": len(ws), "steps": steps, "nodes_total": nodes, "launch": cfg,
+        "sims": len(ws), "steps": steps, "nodes_total": nodes, "launch": cfg, "batches": nb,
         "sims_per_s": round(ok / wall, 3), "seconds": round(wall, 3),
         "aggregate_mlups": round(nodes * steps / wall / 1e6, 1),
         "ms_per_batch_step": round(wall / steps * 1e3, 4),
@@ -316,7 +330,7 @@ def main_batch(args):
     torch.cuda.init()
     stream = torch.cuda.Stream()
     r = sweep_run(stream, args.storage, args.sims, args.sweep_steps, args.plain_sims,
-                  tune=not args.no_autotune)
+                  tune=not args.no_autotune, batches=args.sweep_batches or None)
     out = {
         "metric": "batched sims/s", "value": r["sims_per_s"], "unit": "sims/s",
         "n_gpus": 1, "steps": args.sweep_steps, "warmup": 0,
@@ -735,6 +749,9 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=20000)
     ap.add_argument("--plain-sims", type=int, default=32)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--sweep-batches", type=int, default=0,
+                    help="batches (streams) the sweep is split over; 0: two for the "
+                         "two-byte formats, one otherwise")
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--rate", type=float, default=50.0)
