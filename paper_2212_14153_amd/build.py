@@ -25,6 +25,10 @@ FLAGS = [
 ]
 
 
+# roctx ranges around the C ABI calls (rocprofv3 --marker-trace)
+LIBS = ["-lrocprofiler-sdk-roctx"]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -36,7 +40,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into one shared library; returns its path."""
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+           *[os.path.join(CSRC, s) for s in SOURCES], *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -17,11 +17,22 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fpd_internal.hpp"
 
 using namespace fpd;
 
 namespace {
+
+// A roctx range over one call of the C ABI (rocprofv3 --marker-trace shows it beside the
+// kernels it launched; without a tool attached the calls return at once).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 thread_local std::string g_err;
 
@@ -483,11 +494,13 @@ size_t fpd_population_bytes(const fpd_params* p) {
 }
 
 int fpd_create(const fpd_params* p, void* hip_stream, fpd_sim** out) {
+    TraceRange range("fpd_create");
     return create_impl(p, hip_stream, nullptr, nullptr, 0, out);
 }
 
 int fpd_create_with_buffers(const fpd_params* p, void* hip_stream, void* f_a, void* f_b,
                             size_t bytes_each, fpd_sim** out) {
+    TraceRange range("fpd_create_with_buffers");
     if (!f_a || !f_b) return fail(FPD_EINVAL, "buffers must not be NULL");
     if (((uintptr_t)f_a | (uintptr_t)f_b) & 15)
         return fail(FPD_EINVAL, "buffers must be 16-byte aligned");
@@ -608,6 +621,7 @@ int ensure_graph(fpd_sim* s, int64_t n, bool* replay) {
 extern "C" {
 
 int fpd_capture(fpd_sim* s, int64_t n) {
+    TraceRange range("fpd_capture");
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     if (n < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
     if (s->p.n_beads > 0 && !s->fiber)
@@ -617,6 +631,7 @@ int fpd_capture(fpd_sim* s, int64_t n) {
 }
 
 int fpd_step(fpd_sim* s, int64_t n) {
+    TraceRange range("fpd_step");
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     if (n < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
     if (n == 0) return FPD_OK;
@@ -694,6 +709,7 @@ int fpd_step_count(fpd_sim* s, int64_t* steps) {
 }
 
 int fpd_read_fields(fpd_sim* s, double* rho, double* ux, double* uy, double* eta) {
+    TraceRange range("fpd_read_fields");
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     const size_t S = (size_t)s->p.nx * s->p.ny;
     double* d = nullptr;
@@ -865,6 +881,7 @@ int fpd_particle_stats(fpd_sim* s, int32_t bead, double* out) {
 }
 
 int fpd_read_populations(fpd_sim* s, double* f) {
+    TraceRange range("fpd_read_populations");
     if (!s || !f) return fail(FPD_EINVAL, "NULL argument");
     const size_t n = (size_t)9 * s->p.nx * s->p.ny;
     double* d = nullptr;
@@ -892,6 +909,7 @@ static_assert(offsetof(BeadState, V) == offsetof(BeadState, R) + kBeadPairs &&
               "R, V, F must be adjacent in BeadState");
 
 int fpd_read_beads(fpd_sim* s, double* R, double* V, double* F) {
+    TraceRange range("fpd_read_beads");
     if (!s) return fail(FPD_EINVAL, "NULL simulation");
     const int N = s->p.n_beads;
     if (N == 0) return FPD_OK;
@@ -1020,6 +1038,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '6'};
 
 int fpd_save(fpd_sim* s, const char* path) {
+    TraceRange range("fpd_save");
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
     int rc = sync_check(s);
     if (rc) return rc;
@@ -1043,6 +1062,7 @@ int fpd_save(fpd_sim* s, const char* path) {
 }
 
 int fpd_load(fpd_sim* s, const char* path) {
+    TraceRange range("fpd_load");
     if (!s || !path) return fail(FPD_EINVAL, "NULL argument");
     int rc = sync_check(s);
     if (rc) return rc;
@@ -1359,6 +1379,7 @@ int fpd_batch_set_launch(fpd_batch* b, const fpd_launch* c) {
 
 int fpd_batch_add(fpd_batch* b, const fpd_params* p, const double* R, int64_t n_steps,
                   int64_t* sim_id) {
+    TraceRange range("fpd_batch_add");
     if (!b || !p || !sim_id) return fail(FPD_EINVAL, "NULL argument");
     if (b->pending) return batch_idle(b);
     if (n_steps < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
@@ -1394,6 +1415,7 @@ int fpd_batch_add(fpd_batch* b, const fpd_params* p, const double* R, int64_t n_
 }
 
 int fpd_batch_launch(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
+    TraceRange range("fpd_batch_launch");
     if (!b) return fail(FPD_EINVAL, "NULL batch");
     if (advanced) *advanced = 0;
     int rc = batch_idle(b);
@@ -1442,6 +1464,7 @@ int fpd_batch_launch(fpd_batch* b, int64_t max_steps, int64_t* advanced) {
 }
 
 int fpd_batch_wait(fpd_batch* b) {
+    TraceRange range("fpd_batch_wait");
     if (!b) return fail(FPD_EINVAL, "NULL batch");
     if (!b->pending) return FPD_OK;
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -1560,6 +1583,7 @@ int fpd_batch_sim_info(fpd_batch* b, int64_t id, int64_t* steps, int32_t* status
 }
 
 int fpd_batch_release(fpd_batch* b, int64_t id) {
+    TraceRange range("fpd_batch_release");
     if (!b) return fail(FPD_EINVAL, "NULL batch");
     if (b->pending) return batch_idle(b);
     for (size_t i = 0; i < b->entries.size(); ++i)
@@ -1643,6 +1667,7 @@ size_t fpd_static_scratch_need(const fpd_params* p) {
 int fpd_run_static(const fpd_params* p, void* hip_stream, void* f_a, void* f_b,
                    size_t bytes_each, int32_t init_populations, const double* R_in,
                    double* R_out, uint32_t* health, int64_t n_steps) {
+    TraceRange range("fpd_run_static");
     int rc = validate(p);
     if (rc) return rc;
     if (n_steps < 0) return fail(FPD_EINVAL, "n_steps must be >= 0");
