@@ -75,6 +75,13 @@ template <> struct Codec<FPD_F16DEV> {
     __device__ static inline uint32_t to_bits_scaled(T v) {
         return __builtin_bit_cast(uint16_t, (_Float16)v);
     }
+    // two values in one word (lo in the low half): one packed round-to-nearest-even
+    // conversion, the same bits as two to_bits_scaled
+    __device__ static inline uint32_t pack2_scaled(T lo, T hi) {
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        const h2 v = {(_Float16)lo, (_Float16)hi};
+        return __builtin_bit_cast(uint32_t, v);
+    }
 };
 
 // bfloat16 of g, round to nearest even (deviations are finite here).
@@ -102,6 +109,13 @@ template <> struct Codec<FPD_BF16DEV> {
     static constexpr bool kScaledCollide = false;   // no scale to take out
     __device__ static inline T from_bits_scaled(uint32_t b) { return from_bits(b); }
     __device__ static inline uint32_t to_bits_scaled(T v) { return to_bits(v); }
+    // two values in one word (lo in the low half): the hardware's packed conversion, round
+    // to nearest even like f32_to_bf16 (the same bits for every finite value)
+    __device__ static inline uint32_t pack2_scaled(T lo, T hi) {
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+        const b2 v = {(__bf16)lo, (__bf16)hi};
+        return __builtin_bit_cast(uint32_t, v);
+    }
 };
 
 // ------------------------------------------------------------------- helpers --------

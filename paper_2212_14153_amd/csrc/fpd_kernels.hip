@@ -661,13 +661,11 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
                 else
                     mrt_collide<T>(g[i], Fx[i], Fy[i], s_nu[i], s_q[i], s_e, s_eps);
             }
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const uint32_t b = Cd::to_bits_scaled(g[i][k]);
-                if (i & 1) bits[k][i >> 1] |= b << 16;
-                else bits[k][i >> 1] = b;
-            }
         }
+#pragma unroll
+        for (int i = 0; i < G; i += 2)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) bits[k][i >> 1] = Cd::pack2_scaled(g[i][k], g[i + 1][k]);
         uint16_t* o = dst + (long long)y * stride + x0;
         if (x0 + G - 1 < nx) {
 #pragma unroll
