@@ -763,8 +763,11 @@ template <int ST, int SPT, int BC>
 __global__ void __launch_bounds__(256) batch_step_kernel(BatchArgs b) {
     __shared__ TileLds lds;
     const int item = blockIdx.x;
-    if (item >= b.counts[1]) return;
+    // the entry is read together with the count (one wait for both; the test of e.sim,
+    // never negative, keeps its load ahead of the branch): the grid is sized from the
+    // count and never exceeds the table's capacity, so the read stays inside it
     const ItemRef e = item_ref(b.tile_items, item);
+    if (item >= b.counts[1] || e.sim < 0) return;
     const StepArgs a = load_args(b.args, 2 * e.sim + b.gpar);
     tile_any<ST, SPT, BC, true>(a, tile_window(a), e.local, lds);
 }
@@ -984,8 +987,8 @@ __global__ void __launch_bounds__(kBatchBeadBlock) batch_bead_kernel(BatchArgs b
     __shared__ double scratch[2 * (kBeadLanes / 64)];
     __shared__ double s_R[2];
     const int item = blockIdx.x;
-    if (item >= b.counts[2]) return;
-    const ItemRef e = item_ref(b.bead_items, item);
+    const ItemRef e = item_ref(b.bead_items, item);  // with the count, as in the lattice kernel
+    if (item >= b.counts[2] || e.sim < 0) return;
     const StepArgs a = load_args(b.args, 2 * e.sim + b.gpar);
     bead_block<ST, kBatchBeadVelBatch, kBatchBeadBlock>(a, e.local, 1, 1 - a.parity,
                                                         scratch, s_R);
