@@ -173,7 +173,7 @@ def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153, b
     Returns the result keys."""
     import numpy as np
     import workloads
-    from paper_2212_14153_amd import _lib, autotune
+    from paper_2212_14153_amd import _lib, autotune, serve
     ws = workloads.sweep_sims(sims, seed=seed, steps=steps, storage=storage)
     params = sweep_params(_lib, ws, storage)
     nodes = sum(w.nx * w.ny for w in ws)
@@ -209,7 +209,7 @@ def sweep_run(stream, storage, sims, steps, plain_sims, tune=True, seed=14153, b
     t0 = time.perf_counter()
     finish = {}
     while len(finish) < len(ids):
-        if max(_lib.run_batches(bs, steps)) == 0:
+        if max(serve.run_batches(bs, steps)) == 0:
             break
         t = time.perf_counter() - t0
         for k, b in enumerate(bs):
@@ -374,7 +374,7 @@ def main_particle(args):
     import numpy as np
     import torch
     import workloads
-    from paper_2212_14153_amd import _lib
+    from paper_2212_14153_amd import _lib, serve
     torch.cuda.init()
     stream = torch.cuda.Stream()
     storage = args.storage
@@ -403,7 +403,7 @@ def main_particle(args):
         t0 = time.perf_counter()
         done = 0
         while done < n:
-            adv = max(_lib.run_batches(batches, n - done))
+            adv = max(serve.run_batches(batches, n - done))
             if adv == 0:
                 break
             done += adv
@@ -558,7 +558,7 @@ def main_shapes(args):
     (stuck / Jeffery / S-turn / S-coiled) with its periods and stuck angle."""
     import torch
     import workloads
-    from paper_2212_14153_amd import _lib, tumbling
+    from paper_2212_14153_amd import _lib, serve, tumbling
     torch.cuda.init()
     stream = torch.cuda.Stream()
     storage = args.storage
@@ -586,7 +586,7 @@ def main_shapes(args):
     torch.cuda.synchronize()
     left, t0 = steps, time.perf_counter()
     while left > 0:
-        adv = max(_lib.run_batches(batches, min(left, 25000)))
+        adv = max(serve.run_batches(batches, min(left, 25000)))
         if adv == 0:
             break
         left -= adv

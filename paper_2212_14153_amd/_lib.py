@@ -579,26 +579,3 @@ class Batch:
         a, h, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
         check(lib().fpd_batch_stats(self.h, ctypes.byref(a), ctypes.byref(h), ctypes.byref(b)))
         return a.value, h.value, b.value
-
-
-def run_batches(batches, max_steps: int, slice_steps: int = 512):
-    """Advance several batches (each on its own stream) at the same time, up to max_steps
-    steps each: in rounds of at most slice_steps steps, every batch's launch is enqueued
-    before the first wait, so the streams' work interleaves on the device (a launch of many
-    steps would fill the queue before the next batch's).  Returns the steps each batch
-    advanced."""
-    total = [0] * len(batches)
-    live = list(range(len(batches)))
-    while live:
-        launched = []
-        try:
-            for i in live:
-                launched.append((i, batches[i].launch(min(slice_steps,
-                                                          max_steps - total[i]))))
-        finally:
-            for i, _ in launched:
-                batches[i].wait()
-        for i, adv in launched:
-            total[i] += adv
-        live = [i for i, adv in launched if adv > 0 and total[i] < max_steps]
-    return total

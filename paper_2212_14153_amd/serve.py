@@ -38,6 +38,30 @@ class Request:
         return self.finished - self.arrival
 
 
+def run_batches(batches, max_steps: int, slice_steps: int = 512):
+    """Advance several batches (each on its own stream) at the same time, up to max_steps
+    steps each: in rounds of at most slice_steps steps, every batch's launch is enqueued
+    before the first wait, so the streams' work interleaves on the device (a launch of many
+    steps would fill the queue before the next batch's).  Returns the steps each batch
+    advanced."""
+    total = [0] * len(batches)
+    live = list(range(len(batches)))
+    while live:
+        launched = []
+        try:
+            for i in live:
+                launched.append((i, batches[i].launch(min(slice_steps,
+                                                          max_steps - total[i]))))
+        finally:
+            for i, _ in launched:
+                batches[i].wait()
+        for i, adv in launched:
+            total[i] += adv
+        live = [i for i, adv in launched if adv > 0 and total[i] < max_steps]
+    return total
+
+
+
 class Server:
     """Admission by slots and HBM footprint; chunked execution; read-back on completion.
 
@@ -57,9 +81,10 @@ class Server:
             self.batches = list(batch) if isinstance(batch, (list, tuple)) else [batch]
         else:
             lanes = max(1, int(lanes))
+            # lane 0 on the caller's stream (if given), the others on streams of their own
             self.batches = [_lib.Batch(hbm_budget // lanes, max(1, max_slots // lanes),
-                                       storage=storage, stream=stream if lanes == 1 else None)
-                            for _ in range(lanes)]
+                                       storage=storage, stream=stream if k == 0 else None)
+                            for k in range(lanes)]
         self.batch = self.batches[0]
         self.load = [0] * len(self.batches)   # nodes admitted per lane
         if launch:
@@ -126,7 +151,7 @@ class Server:
                 self.waiting.append(pending.popleft())
             self._admit()
             if self.running:
-                _lib.run_batches(self.batches, self.chunk, slice_steps=self.chunk)
+                run_batches(self.batches, self.chunk, slice_steps=self.chunk)
                 self._collect()
             elif pending:
                 time.sleep(min(idle_sleep, max(0.0, pending[0].arrival - self.now())))

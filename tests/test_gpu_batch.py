@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import workloads
-from paper_2212_14153_amd import _lib
+from paper_2212_14153_amd import _lib, serve
 
 pytestmark = pytest.mark.gpu
 
@@ -172,7 +172,7 @@ def test_batches_on_two_streams_advance_together():
         b0.wait()  # nothing pending: a no-op
         done = {}
         while len(done) < len(ws):
-            adv = _lib.run_batches(batches, 20)
+            adv = serve.run_batches(batches, 20)
             assert max(adv) > 0
             for i, (b, sid) in where.items():
                 if i not in done and b.info(sid)[1] == _lib.FPD_SIM_DONE:

@@ -167,7 +167,6 @@ def test_summary_percentiles_and_fifo_replay():
 def test_run_batches_interleaves_launches_and_stops():
     """run_batches: every round enqueues each live batch before any wait, slices are
     bounded, a batch whose simulations are done (launch returns 0) drops out."""
-    from paper_2212_14153_amd import _lib
     log = []
 
     class FakeBatch:
@@ -187,7 +186,7 @@ def test_run_batches_interleaves_launches_and_stops():
             log.append(("wait", self.name))
 
     a, b = FakeBatch("a", 1000), FakeBatch("b", 300)
-    assert _lib.run_batches([a, b], 700, slice_steps=256) == [700, 300]
+    assert serve.run_batches([a, b], 700, slice_steps=256) == [700, 300]
     assert (a.remaining, b.remaining) == (300, 0)
     # first round: both launched, then both waited
     assert log[:4] == [("launch", "a", 256), ("launch", "b", 256), ("wait", "a"),
