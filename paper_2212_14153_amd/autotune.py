@@ -16,7 +16,7 @@ import sys
 import tempfile
 import time
 
-SHAPES = [(256, 1), (128, 2), (128, 1), (64, 4), (64, 2)]
+SHAPES = [(256, 1), (128, 2), (128, 1), (64, 4), (64, 2), (64, 1)]
 CANDIDATES = [dict(block_x=bx, block_y=by, rows_per_thread=spt, xcd_remap=xr)
               for (bx, by), spt, xr in itertools.product(SHAPES, (1, 2), (2, 1))]
 
