@@ -278,7 +278,7 @@ def plain_fifo(_lib, ws, arrivals, steps, storage, stream):
 
 
 def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512, chunk=200,
-              budget_gb=64, seed=50, lanes=1):
+              budget_gb=64, seed=50, lanes=1, tune=True):
     """C5 at one arrival rate: `n_req` Poisson arrivals of sweep simulations served with
     continuous batching, and the first `n_plain` of the same arrivals through the measured
     plain FIFO server.  Returns the result keys (p50 / p99 over the requests after
@@ -292,8 +292,22 @@ def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512,
     reqs = [serve.Request(i, p, w.beads(), steps, float(t))
             for i, (p, w, t) in enumerate(zip(params, ws, arrivals))]
     log(f"serve: {n_req} requests at {rate:.1f}/s, {steps} steps each, storage {storage}")
+    cfg = {}
+    if tune:   # the batch launch shape, tuned on the requests' simulations (cached)
+        from paper_2212_14153_amd import autotune
+        budget = int(1.05 * sum(_lib.fpd_sim_footprint(p) for p in params)) + (1 << 26)
+
+        def make_batch():
+            b = _lib.Batch(budget, len(ws), storage=storage, stream=stream.cuda_stream)
+            for p, w in zip(params, ws):
+                b.add(p, w.beads(), 1 << 40)
+            return b
+
+        cfg, _ = autotune.tune_batch(make_batch, storage, sum(w.nx * w.ny for w in ws))
+        log(f"serve: autotuned launch {cfg}")
     srv = serve.Server(storage, hbm_budget=budget_gb << 30, max_slots=slots, chunk=chunk,
-                       stream=stream.cuda_stream, launch=dict(graph_chunk=32), lanes=lanes)
+                       stream=stream.cuda_stream, launch=dict(cfg, graph_chunk=32),
+                       lanes=lanes)
     done = srv.serve(reqs)
     srv.close()
     summ = serve.summarize(done, warmup=warmup)
@@ -311,7 +325,7 @@ def serve_run(stream, storage, n_req, steps, rate, n_plain, warmup=0, slots=512,
     pct = lambda a, q: round(float(np.percentile(a, q)), 3)  # noqa: E731
     return {
         "rate_per_s": round(rate, 3), "requests": n_req - warmup, "warmup": warmup,
-        "lanes": lanes,
+        "lanes": lanes, "launch": cfg or None,
         "completed": summ["completed"], "sims_per_s": round(summ["sims_per_s"], 3),
         "p50_s": round(summ["p50_s"], 3), "p99_s": round(summ["p99_s"], 3),
         "mean_s": round(summ["mean_s"], 3), "span_s": round(summ["span_s"], 2),

@@ -95,9 +95,17 @@ void window_size(const fpd_params* p, double rc, int& w, int& h) {
 
 // Launch shapes measured best on MI355X at 8192 x 2048 (default block order, no XCD remap):
 // 128 x 1 for float64, 256 x 1 for float32, 256 x 1 with two rows per thread for the
-// two-byte formats (whose lanes update two nodes each: 512-node tiles).
-fpd_launch default_launch(int storage, int graph_chunk) {
+// two-byte formats (whose lanes update two nodes each: 512-node tiles).  Below about a
+// million nodes the kernel is latency-bound and more, smaller tiles pay: at 1024 x 256,
+// 64 x 1 with one row per thread took 15.8 against 17.0 us per step (float32) and 19.9
+// against 25.4 (float16 deviations); float64 keeps 128 x 1 (29.8 against 30.3 with 64 x 1).
+// nodes = 0: the large-lattice shapes (batches, whose members differ in size).
+constexpr long long kSmallLattice = 1LL << 20;
+
+fpd_launch default_launch(int storage, int graph_chunk, long long nodes = 0) {
+    const bool small = nodes > 0 && nodes <= kSmallLattice;
     if (storage == FPD_F64) return fpd_launch{128, 1, 1, 2, graph_chunk};
+    if (small) return fpd_launch{64, 1, 1, 2, graph_chunk};
     if (nodes_per_lane(storage) > 1) return fpd_launch{256, 1, 2, 2, graph_chunk};
     return fpd_launch{256, 1, 1, 2, graph_chunk};
 }
@@ -382,7 +390,7 @@ int create_impl(const fpd_params* p, void* stream, void* fa, void* fb, size_t by
     s->elem = storage_elem(p->storage);
     s->buf_bytes = (size_t)p->ny * (size_t)s->L.stride * s->elem;
     s->rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
-    s->launch = default_launch(p->storage, 64);
+    s->launch = default_launch(p->storage, 64, (long long)p->nx * p->ny);
     auto bail = [&](int code) {
         fpd_destroy(s);
         return code;
@@ -1705,7 +1713,7 @@ int fpd_run_static(const fpd_params* p, void* hip_stream, void* f_a, void* f_b,
     s.cur = 0;
     s.stream = (hipStream_t)hip_stream;
     s.rc = p->radius + (p->cutoff > 0.0 ? p->cutoff : default_cutoff(p->storage)) * p->xi;
-    s.launch = default_launch(p->storage, 64);
+    s.launch = default_launch(p->storage, 64, (long long)p->nx * p->ny);
     if (init_populations)
         HIP_TRY(launch_init_state(p->storage, s.L, p->u_wall, p->init_flow, f_a, s.stream));
     if (N > 0) {
