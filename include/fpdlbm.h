@@ -261,6 +261,11 @@ int fpd_particle_stats(fpd_sim *s, int32_t bead, double *out);
 
 /* ---------------------------------------------------------------- tuning ----- */
 
+/* Launch shape of the fused lattice kernel (results are bitwise the same for every shape;
+ * the shape only changes speed).  Defaults: 128 x 1 for FPD_F64, 256 x 1 for FPD_F32,
+ * 256 x 1 with two rows per thread for the two-byte formats, and 64 x 1 for FPD_F32 and
+ * the two-byte formats at 2^20 nodes or fewer; graph_chunk 64.  FPD_EINVAL for a value
+ * outside those fpd_launch allows (nothing changes then); synchronises. */
 int fpd_set_launch(fpd_sim *s, const fpd_launch *cfg);
 
 /* Replace the FPD_FLAG_NO_GRAPH / FPD_FLAG_TIME_KERNELS bits (FPD_FLAG_CLAMP_PHI is fixed
