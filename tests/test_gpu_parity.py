@@ -181,12 +181,16 @@ def test_ragged_lattices_with_fiber(nx, ny, n, seed, storage, tol):
     assert np.max(np.abs(R - st.R)) <= (1e-11 if storage == "f64" else 1e-6)
 
 
-def test_fiber_straddling_the_periodic_boundary():
-    w = small_fiber(96, 40, 5, 7, "f64", theta=0.2).with_(cx=1.0)
-    print_case("wrap", w, "f64")
-    st, _, f, R, V, F = run_both(w, "f64", 80)
-    assert rel_err(f, st.f) <= 1e-11
-    assert np.max(np.abs(R - st.R)) <= 1e-11
+@pytest.mark.parametrize("storage,tol,tol_r", [("f64", 1e-11, 1e-11), ("f32", 1e-5, 1e-6)])
+def test_fiber_straddling_the_periodic_boundary(storage, tol, tol_r):
+    """The fiber's support crosses x = 0: minimum images in FP64 and, for FP32 storage, the
+    integer offsets plus FP32 fraction of the fiber tiles and the bead kernel."""
+    w = small_fiber(96, 40, 5, 7, storage, theta=0.2).with_(cx=1.0)
+    print_case("wrap", w, storage)
+    st, _, f, R, V, F = run_both(w, storage, 80)
+    assert rel_err(f, st.f) <= tol
+    assert np.max(np.abs(R - st.R)) <= tol_r
+    assert st.R[:, 0].min() < 1.0 and (st.R[:, 0].min() < 0 or st.R[:, 0].max() > 95)
 
 
 def test_fields_match_oracle():
