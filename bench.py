@@ -695,10 +695,11 @@ def time_steps(sim, stream, steps, warmup):
     return e0.elapsed_time(e1) / steps, timed_path(steps, chunk)
 
 
-def kernel_pass(sim, steps, warmup=4):
+def kernel_pass(sim, steps, warmup=4, flags=0):
     """The same number of steps again with every lattice and bead launch stamped by its own
-    dispatch (FPD_FLAG_TIME_KERNELS), after `warmup` untimed steps in the same mode: average
-    lattice and bead kernel durations in ms."""
+    dispatch (FPD_FLAG_TIME_KERNELS: whole steps, one lattice kernel each), after `warmup`
+    untimed steps in the same mode: average lattice and bead kernel durations in ms.  The
+    simulation's flags are `flags` afterwards."""
     from paper_2212_14153_amd import _lib
     sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
     sim.step(warmup)
@@ -707,7 +708,7 @@ def kernel_pass(sim, steps, warmup=4):
     sim.step(steps)
     sim.sync()
     ms_lat, n_lat, ms_bead, n_bead = sim.kernel_times()
-    sim.set_flags(0)
+    sim.set_flags(flags)
     return ms_lat / max(n_lat, 1), (ms_bead / n_bead if n_bead else 0.0)
 
 
@@ -756,6 +757,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload (no c2, sweep_c4, serve_c5 keys)")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows_per_thread,xcd_remap")
+    ap.add_argument("--no-split", action="store_true",
+                    help="whole steps (FPD_FLAG_NO_SPLIT) in the timed region")
     ap.add_argument("--mode", default="plain",
                     choices=["plain", "batch", "serve", "particle", "sandwich", "shapes"])
     ap.add_argument("--shape-steps", type=int, default=400000)
@@ -819,7 +822,9 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.Stream()
     log(f"workload {w.name}: {w.nx}x{w.ny}, {w.n_beads} beads, storage {args.storage}")
-    sim = _lib.simulation_from_workload(w, storage=args.storage, stream=stream.cuda_stream)
+    base_flags = _lib.FPD_FLAG_NO_SPLIT if args.no_split else 0
+    sim = _lib.simulation_from_workload(w, storage=args.storage, stream=stream.cuda_stream,
+                                        flags=base_flags)
     if args.launch:
         bx, by, spt, xr = (int(v) for v in args.launch.split(","))
         sim.set_launch(dict(block_x=bx, block_y=by, rows_per_thread=spt, xcd_remap=xr))
@@ -829,16 +834,19 @@ def main():
 
     # timed region: the production path (captured graphs replayed), whole step
     ms_step, path = time_steps(sim, stream, args.steps, args.warmup)
+    path["split_steps"] = sim.split_active()
     cfg = sim.get_launch()
     mlups = nodes / (ms_step * 1e-3) / 1e6
     how = (f"{path['graph_replays']} graph replays of {path['graph_chunk']} steps"
            if path["graph_replays"] else "direct launches")
     if path["graph_replays"] and path["direct_steps"]:
         how += f" + {path['direct_steps']} direct steps"
+    if path["split_steps"]:
+        how += " (split steps)"
     log(f"{how}: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS")
 
     # the same simulation, every lattice and bead launch stamped by its own dispatch
-    lat_ms, bead_ms = kernel_pass(sim, args.steps)
+    lat_ms, bead_ms = kernel_pass(sim, args.steps, flags=base_flags)
     bytes_alg = 18 * BYTES_PER_VALUE[args.storage] * nodes
     achieved = bytes_alg / (lat_ms * 1e-3) / 1e9
     log(f"lattice kernel {lat_ms * 1e3:.1f} us ({achieved:.0f} GB/s), bead kernel "

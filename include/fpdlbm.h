@@ -72,6 +72,7 @@ extern "C" {
 #define FPD_FLAG_CLAMP_PHI     0x1u  /* clamp sum_i phi_i to 1 in Eq. (1)                 */
 #define FPD_FLAG_NO_GRAPH      0x2u  /* launch every kernel directly (no graph replay)    */
 #define FPD_FLAG_TIME_KERNELS  0x4u  /* time the lattice and bead kernels (implies NO_GRAPH) */
+#define FPD_FLAG_NO_SPLIT      0x8u  /* one lattice kernel per step (no split steps)      */
 
 /* health bits, sticky until fpd_clear_health */
 #define FPD_HEALTH_NAN      0x1u   /* NaN or Inf in a bead position or velocity           */
@@ -181,7 +182,17 @@ int fpd_init_fiber_line(fpd_sim *s, double cx, double cy, double theta);
  * 10-12), (2) the MRT collide-and-stream update with moving-wall bounce-back, (3) V^{n+1}
  * by Eq. (5) and R^{n+1} = R^n + V^{n+1}.  FPD_EINVAL for n_steps < 0, FPD_ESTATE before
  * fpd_init_fiber when the simulation has beads; an unstable run is reported by health
- * bits (fpd_sync), not here. */
+ * bits (fpd_sync), not here.
+ * Split steps: with a fiber whose reserved window spans at most about a quarter of the
+ * lattice's tiles, in float32 or the two-byte formats (no fixed profile, neither
+ * FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS),
+ * step (2) runs as two kernels, the tiles away from the fiber on a second stream of the
+ * library's own (non-blocking, default priority) while the bead kernel of the step before
+ * finishes, and the tiles near it after that bead kernel; the results are the same bits.
+ * The simulation's stream waits for the second stream before fpd_step returns, so work
+ * enqueued on it afterwards follows every step.  The first step after fpd_init_fiber or
+ * fpd_load runs whole.  FPD_HEALTH_SUPPORT is raised if a bead outran the split's margin
+ * of three nodes (far beyond FPD_HEALTH_MACH). */
 int fpd_step(fpd_sim *s, int64_t n_steps);
 
 /* Capture now, without running any step, the graph that fpd_step(s, n_steps) replays
@@ -268,10 +279,14 @@ int fpd_particle_stats(fpd_sim *s, int32_t bead, double *out);
  * outside those fpd_launch allows (nothing changes then); synchronises. */
 int fpd_set_launch(fpd_sim *s, const fpd_launch *cfg);
 
-/* Replace the FPD_FLAG_NO_GRAPH / FPD_FLAG_TIME_KERNELS bits (FPD_FLAG_CLAMP_PHI is fixed
- * at creation and ignored here); synchronises. */
+/* Replace the FPD_FLAG_NO_GRAPH / FPD_FLAG_TIME_KERNELS / FPD_FLAG_NO_SPLIT bits
+ * (FPD_FLAG_CLAMP_PHI is fixed at creation and ignored here); synchronises. */
 int fpd_set_flags(fpd_sim *s, uint32_t flags);
 int fpd_get_launch(fpd_sim *s, fpd_launch *cfg);
+
+/* Whether fpd_step splits its steps as things stand (see fpd_step): *on = 1 or 0.  The
+ * first step after fpd_init_fiber or fpd_load runs whole either way. */
+int fpd_split_active(fpd_sim *s, int32_t *on);
 
 /* Kernel timing with FPD_FLAG_TIME_KERNELS: summed duration (ms) and launch count of the
  * fused lattice kernel and of the bead kernel since the last reset.  Each duration is that

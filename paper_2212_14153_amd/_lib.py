@@ -21,7 +21,7 @@ FPD_OK, FPD_EINVAL, FPD_ENOMEM, FPD_EUNSTABLE, FPD_EDEVICE, FPD_ESTATE = 0, -1, 
 FPD_F64, FPD_F32, FPD_F16DEV, FPD_BF16DEV = 0, 1, 2, 3
 FPD_INIT_REST, FPD_INIT_LINEAR_COUETTE = 0, 1
 FPD_WALLS, FPD_PERIODIC = 0, 1
-FPD_FLAG_CLAMP_PHI, FPD_FLAG_NO_GRAPH, FPD_FLAG_TIME_KERNELS = 0x1, 0x2, 0x4
+FPD_FLAG_CLAMP_PHI, FPD_FLAG_NO_GRAPH, FPD_FLAG_TIME_KERNELS, FPD_FLAG_NO_SPLIT = 0x1, 0x2, 0x4, 0x8
 FPD_HEALTH_NAN, FPD_HEALTH_STRAIN, FPD_HEALTH_MACH, FPD_HEALTH_WALL, FPD_HEALTH_SUPPORT = (
     0x1, 0x2, 0x4, 0x8, 0x10)
 FPD_MAX_BEADS = 256
@@ -94,6 +94,7 @@ SIGNATURES = [
     ("fpd_set_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_get_launch", ctypes.c_int, [_SIM, ctypes.POINTER(fpd_launch)]),
     ("fpd_set_flags", ctypes.c_int, [_SIM, ctypes.c_uint32]),
+    ("fpd_split_active", ctypes.c_int, [_SIM, ctypes.POINTER(ctypes.c_int32)]),
     ("fpd_kernel_times", ctypes.c_int,
      [_SIM, _D, ctypes.POINTER(ctypes.c_int64), _D, ctypes.POINTER(ctypes.c_int64)]),
     ("fpd_reset_kernel_times", ctypes.c_int, [_SIM]),
@@ -401,6 +402,11 @@ class Simulation:
 
     def set_flags(self, flags: int):
         check(lib().fpd_set_flags(self.h, int(flags)))
+
+    def split_active(self) -> bool:
+        on = ctypes.c_int32(0)
+        check(lib().fpd_split_active(self.h, ctypes.byref(on)))
+        return bool(on.value)
 
     def get_launch(self) -> LaunchConfig:
         c = fpd_launch()

@@ -57,7 +57,22 @@ struct BeadState {
     // and each bead's share of it at the step's start (ev_kernel, read by the tiles)
     double ev_k, ev_d;
     double Fev[kMaxBeads][2];
+    // Partition of a split step, one slot per parity like the window: columns x0 + [0, w)
+    // and rows y0 + [0, h) (modulo the lattice along periodic directions; w = 0: empty),
+    // the step's support window grown by kPartMargin nodes, written by the step before.
+    int part[2][4];
 };
+
+// A bead moves less than one node per step (0.3 c_s raises FPD_HEALTH_MACH long before),
+// so the support window of step n grown by one node holds that of step n + 1, and one more
+// node holds the ring around it that the bead kernel of step n + 1 pulls from; the third
+// is slack.
+constexpr int kPartMargin = 3;
+
+// The tiles of a step: all of them (one kernel), or those outside the step's partition
+// (kPartFluid: no fiber work, so the bead kernel of the step before may still be running)
+// and those inside it (kPartFiber: the fiber tiles and the step's bookkeeping).
+enum { kPartAll = 0, kPartFluid = 1, kPartFiber = 2 };
 
 // Value (k, y, x) of a population buffer sits at y * stride + k * plane + x.  The nine
 // direction rows of one lattice row are adjacent (plane = nx padded to 64 elements, stride
@@ -108,6 +123,7 @@ struct StepArgs {
     int tiles_x, n_tiles;     // tiling of the fused lattice kernel
     int rows_per_block;       // block_y * rows_per_thread
     int xcd_remap;
+    int part_gw, part_gh;     // grid of the kPartFiber kernel in tiles (its blocks: gw * gh)
 };
 
 // Fiber-ends recorder (device memory): at the start of every step tile 0 counts the step
@@ -153,6 +169,10 @@ struct NodeBox {
 // then not for stream capture.
 hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
                        hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// One half of a split step (kPartFluid or kPartFiber; the fiber half's grid is
+// a.part_gw * a.part_gh blocks)
+hipError_t launch_step_part(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
+                            int part, hipStream_t st);
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
                        hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);

@@ -413,6 +413,103 @@ __device__ inline Window tile_window(const StepArgs& a) {
                          a.fib.rect_hmax);
 }
 
+// One axis of a partition from a window axis (start x0, length w on n nodes) grown by m
+// nodes: wrapping along a periodic axis, clipped at the walls otherwise.
+__device__ inline void grow_axis(int x0, int w, int m, int n, bool wrap, int& p0, int& pw) {
+    if (w <= 0) {
+        p0 = 0;
+        pw = 0;
+    } else if (wrap) {
+        pw = w + 2 * m >= n ? n : w + 2 * m;
+        p0 = pw == n ? 0 : imod(x0 - m, n);
+    } else {
+        p0 = max(x0 - m, 0);
+        pw = min(x0 + w - 1 + m, n - 1) - p0 + 1;
+    }
+}
+
+// Whether a window axis grown by m nodes lies inside a partition axis (p0, pw).
+__device__ inline bool axis_inside(int x0, int w, int m, int p0, int pw, int n, bool wrap) {
+    if (w <= 0) return true;
+    if (wrap) {
+        if (pw >= n) return true;
+        return w + 2 * m <= pw && imod(x0 - m - p0, n) + w + 2 * m <= pw;
+    }
+    const int lo = max(x0 - m, 0), hi = min(x0 + w - 1 + m, n - 1);
+    return lo >= p0 && hi <= p0 + pw - 1;
+}
+
+// The bookkeeping of a step, by every thread of one block: the step's bead kernel fills
+// the other window and occupancy slots from scratch, and the next step's partition is this
+// step's window grown by kPartMargin.  check (a split step): the partition this step was
+// split by held the window and the ring of one node around it, else FPD_HEALTH_SUPPORT
+// (fiber tiles outside it then ran without their fiber terms).
+__device__ inline void step_duties(const StepArgs& a, const Window& win, bool check) {
+    BeadState* bs = a.fib.bs;
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    if (tid == 0) {
+        int* nxt = bs->win[1 - a.parity];
+        nxt[0] = 0x7fffffff;
+        nxt[1] = -0x7fffffff;
+        nxt[2] = 0x7fffffff;
+        nxt[3] = -0x7fffffff;
+        unsigned h = win.clamped ? FPD_HEALTH_SUPPORT : 0u;
+        const int nx = a.L.nx, ny = a.L.ny;
+        const bool per = a.L.periodic != 0;
+        const int ww = win.h > 0 ? win.w : 0;
+        if (check) {
+            const int* P = bs->part[a.parity];
+            if (!axis_inside(win.x0, ww, 1, P[0], P[1], nx, true) ||
+                !axis_inside(win.y0, win.h, 1, P[2], P[3], ny, per))
+                h |= FPD_HEALTH_SUPPORT;
+        }
+        int* Q = bs->part[1 - a.parity];
+        grow_axis(win.x0, ww, kPartMargin, nx, true, Q[0], Q[1]);
+        grow_axis(win.y0, ww > 0 ? win.h : 0, kPartMargin, ny, per, Q[2], Q[3]);
+        if (Q[1] == 0 || Q[3] == 0) Q[1] = Q[3] = 0;
+        if (h) atomicOr(&bs->health, h);
+    }
+    for (int i = tid; i < occ_words(a.fib); i += blockDim.x * blockDim.y)
+        bs->occ[1 - a.parity][i] = 0u;
+}
+
+// The tiles a partition axis (p0, pw) meets, for tiles of width t (the last of `tiles` is
+// n - (tiles - 1) t wide): the first and how many, at most cap (the fiber kernel's grid).
+__device__ inline void part_axis(int p0, int pw, int n, int t, int tiles, int cap, int& first,
+                                 int& count) {
+    first = 0;
+    count = 0;
+    if (pw <= 0) return;
+    if (pw >= n) {
+        count = min(tiles, cap);
+        return;
+    }
+    const int last = p0 + pw - 1;  // past n: the wrapped part, from tile 0 on
+    const int tl = last < n ? last / t : tiles + (last - n) / t;
+    first = p0 / t;
+    count = min(min(tl - first + 1, tiles), cap);
+}
+
+struct TileSpan {
+    int tx0, ntx, ty0, nty, tiles_y;
+};
+
+// The tiles of this step's partition (a run modulo the tiling along each axis); the fluid
+// and the fiber kernels of a step take exactly this set apart, so every tile runs once.
+__device__ inline TileSpan part_span(const StepArgs& a, int tw) {
+    const int* P = a.fib.bs->part[a.parity];
+    TileSpan sp;
+    sp.tiles_y = a.n_tiles / a.tiles_x;
+    part_axis(P[0], P[1], a.L.nx, tw, a.tiles_x, a.part_gw, sp.tx0, sp.ntx);
+    part_axis(P[2], P[3], a.L.ny, a.rows_per_block, sp.tiles_y, a.part_gh, sp.ty0, sp.nty);
+    if (sp.ntx == 0 || sp.nty == 0) sp.ntx = sp.nty = 0;
+    return sp;
+}
+
+__device__ inline bool in_span(const TileSpan& sp, int tx, int ty, int tiles_x) {
+    return imod(tx - sp.tx0, tiles_x) < sp.ntx && imod(ty - sp.ty0, sp.tiles_y) < sp.nty;
+}
+
 // Step (1) at one node (x, y) of a fiber tile: phi_i^n (Eq. 2), eta^n (Eq. 1, with a
 // fixed profile phi_s(y) if one is set) and the relaxation rates, f^n (Eq. 4, plus the
 // uniform body force), recorded in the force window.  Fx, Fy are overwritten; s_nu and
@@ -462,10 +559,11 @@ __device__ inline bool periodic_of(int bc, const StepArgs& a) {
 
 // One tile (block_x nodes on rows_per_block rows) of one simulation.
 // Must be reached by every thread of the block (it synchronises when the tile meets the
-// fiber).  The tile numbered 0 also resets the window slot the bead kernel fills next.
+// fiber).  In a one-kernel step (PART = kPartAll) the tile numbered 0 also does the step's
+// bookkeeping (step_duties); a fluid-part tile (kPartFluid) reads no fiber state at all.
 // FR: the forces F^n and F/A of this step come from a forces kernel (a batch); else the
 // tiles near the fiber compute them from the positions.
-template <int ST, int SPT, int BC, bool FR>
+template <int ST, int SPT, int BC, bool FR, int PART = kPartAll>
 __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int tile,
                                     TileLds& lds) {
     using Cd = Codec<ST>;
@@ -492,30 +590,19 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     // latency overlaps the reads of the window, the occupancy bitmap and the bead list
     T g0[9];
     if (x < nx && ybase < ny) pull<Cd>(src, nx, ny, stride, plane, x, ybase, per, u6, g0);
+    // a fluid-part tile checks the partition while those loads are in flight
+    if constexpr (PART == kPartFluid)
+        if (in_span(part_span(a, tw), tx, ty, a.tiles_x)) return;  // block-uniform
 
     // Block-uniform: does this tile meet the fiber's support window?
     int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
     bool fiber_tile = false;
-    if (a.fib.n > 0) {
-        BeadState* bs = a.fib.bs;
+    if (PART != kPartFluid && a.fib.n > 0) {
         wx0 = win.x0;
         wy0 = win.y0;
         ww = win.w;
         wh = win.h;
-        if (tile == 0) {
-            // the bead kernel of this step fills the other slots from scratch
-            const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-            if (tid == 0) {
-                int* nxt = bs->win[1 - a.parity];
-                nxt[0] = 0x7fffffff;
-                nxt[1] = -0x7fffffff;
-                nxt[2] = 0x7fffffff;
-                nxt[3] = -0x7fffffff;
-                if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
-            }
-            for (int i = tid; i < occ_words(a.fib); i += blockDim.x * blockDim.y)
-                bs->occ[1 - a.parity][i] = 0u;
-        }
+        if (PART == kPartAll && tile == 0) step_duties(a, win, false);
         const bool rows_hit =
             per ? cols_overlap(ytile, a.rows_per_block, wy0, wh, ny)
                          : (ytile <= wy0 + wh - 1 && ytile + a.rows_per_block - 1 >= wy0);
@@ -531,7 +618,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
     if (fiber_tile && nb == 0) fiber_tile = false;
     // a fixed profile phi_s(y) makes every tile take the fiber path (with no beads to
     // gather outside the window); plain: no force and no viscosity change on this tile
-    if (a.row_phi) fiber_tile = true;
+    if (PART != kPartFluid && a.row_phi) fiber_tile = true;
     const bool plain = !fiber_tile && a.gx == 0.0 && a.gy == 0.0;  // block-uniform
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
@@ -561,7 +648,7 @@ __device__ inline void lattice_tile(const StepArgs& a, const Window& win, int ti
 
 // lattice_tile for 2-byte storage: a tile is G * block_x nodes wide and each lane updates
 // G neighbouring nodes with the same per-node arithmetic as the one-node path.
-template <int ST, int SPT, int BC, bool FR>
+template <int ST, int SPT, int BC, bool FR, int PART = kPartAll>
 __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, int tile,
                                           TileLds& lds) {
     using Cd = Codec<ST>;
@@ -589,26 +676,12 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
 
     int nb = 0, wx0 = 0, wy0 = 0, ww = 0, wh = 0;
     bool fiber_tile = false;
-    if (a.fib.n > 0) {
-        BeadState* bs = a.fib.bs;
+    if (PART != kPartFluid && a.fib.n > 0) {
         wx0 = win.x0;
         wy0 = win.y0;
         ww = win.w;
         wh = win.h;
-        if (tile == 0) {
-            // the bead kernel of this step fills the other slots from scratch
-            const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-            if (tid == 0) {
-                int* nxt = bs->win[1 - a.parity];
-                nxt[0] = 0x7fffffff;
-                nxt[1] = -0x7fffffff;
-                nxt[2] = 0x7fffffff;
-                nxt[3] = -0x7fffffff;
-                if (win.clamped) atomicOr(&bs->health, FPD_HEALTH_SUPPORT);
-            }
-            for (int i = tid; i < occ_words(a.fib); i += blockDim.x * blockDim.y)
-                bs->occ[1 - a.parity][i] = 0u;
-        }
+        if (PART == kPartAll && tile == 0) step_duties(a, win, false);
         const bool rows_hit =
             per ? cols_overlap(ytile, a.rows_per_block, wy0, wh, ny)
                          : (ytile <= wy0 + wh - 1 && ytile + a.rows_per_block - 1 >= wy0);
@@ -624,7 +697,7 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
     if (fiber_tile && nb == 0) fiber_tile = false;
     // a fixed profile phi_s(y) makes every tile take the fiber path (with no beads to
     // gather outside the window); plain: no force and no viscosity change on this tile
-    if (a.row_phi) fiber_tile = true;
+    if (PART != kPartFluid && a.row_phi) fiber_tile = true;
     const bool plain = !fiber_tile && a.gx == 0.0 && a.gy == 0.0;  // block-uniform
 #pragma unroll
     for (int r = 0; r < SPT; ++r) {
@@ -690,12 +763,12 @@ __device__ inline void lattice_tile_group(const StepArgs& a, const Window& win, 
     }
 }
 
-template <int ST, int SPT, int BC, bool FR>
+template <int ST, int SPT, int BC, bool FR, int PART = kPartAll>
 __device__ inline void tile_any(const StepArgs& a, const Window& win, int tile, TileLds& lds) {
     if constexpr (nodes_per_lane(ST) > 1)
-        lattice_tile_group<ST, SPT, BC, FR>(a, win, tile, lds);
+        lattice_tile_group<ST, SPT, BC, FR, PART>(a, win, tile, lds);
     else
-        lattice_tile<ST, SPT, BC, FR>(a, win, tile, lds);
+        lattice_tile<ST, SPT, BC, FR, PART>(a, win, tile, lds);
 }
 
 // Called by every thread of one block ahead of the step's lattice kernel, and only while a
@@ -735,6 +808,35 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a) {
     __shared__ TileLds lds;
     const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     tile_any<ST, SPT, BC, false>(a, tile_window(a), tile, lds);
+}
+
+// A split step: the lattice step as two kernels over complementary tile sets.  fluid_kernel
+// (the full grid, in step_kernel's block order) updates the tiles outside the step's
+// partition and reads no fiber state, so it runs while the bead kernel of the step before
+// still finishes; fiber_kernel (a.part_gw * a.part_gh blocks over the partition, block 0
+// also doing the step's bookkeeping) updates the tiles inside it after that bead kernel.
+// A tile runs the same code in either as in step_kernel, so the results are the same bits.
+template <int ST, int SPT, int BC>
+__global__ void __launch_bounds__(256) fluid_kernel(StepArgs a) {
+    __shared__ TileLds lds;
+    const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    if constexpr (nodes_per_lane(ST) > 1) {  // (the one-node tiles check after their loads)
+        const TileSpan sp = part_span(a, nodes_per_lane(ST) * (int)blockDim.x);
+        if (in_span(sp, tile % a.tiles_x, tile / a.tiles_x, a.tiles_x)) return;
+    }
+    tile_any<ST, SPT, BC, false, kPartFluid>(a, Window{0, 0, 0, 0, false}, tile, lds);
+}
+
+template <int ST, int SPT, int BC>
+__global__ void __launch_bounds__(256) fiber_kernel(StepArgs a) {
+    __shared__ TileLds lds;
+    const Window win = tile_window(a);
+    if (blockIdx.x == 0) step_duties(a, win, true);
+    const TileSpan sp = part_span(a, nodes_per_lane(ST) * (int)blockDim.x);
+    const int ox = (int)blockIdx.x % a.part_gw, oy = (int)blockIdx.x / a.part_gw;
+    if (ox >= sp.ntx || oy >= sp.nty) return;  // block-uniform
+    const int tx = (sp.tx0 + ox) % a.tiles_x, ty = (sp.ty0 + oy) % sp.tiles_y;
+    tile_any<ST, SPT, BC, false, kPartFiber>(a, win, ty * a.tiles_x + tx, lds);
 }
 
 // The argument table is read-only while a batch kernel runs: viewing it in the constant
@@ -1422,6 +1524,41 @@ hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int spt, hipS
         case FPD_F32: return launch_step_t<FPD_F32>(a, block, spt, st, t0, t1);
         case FPD_F16DEV: return launch_step_t<FPD_F16DEV>(a, block, spt, st, t0, t1);
         case FPD_BF16DEV: return launch_step_t<FPD_BF16DEV>(a, block, spt, st, t0, t1);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int ST, int BC>
+static void (*part_kernel_for(int spt, int part))(StepArgs) {
+    const bool fl = part == kPartFluid;
+    switch (spt) {
+        case 1: return fl ? fluid_kernel<ST, 1, BC> : fiber_kernel<ST, 1, BC>;
+        case 2: return fl ? fluid_kernel<ST, 2, BC> : fiber_kernel<ST, 2, BC>;
+        case 4: return fl ? fluid_kernel<ST, 4, BC> : fiber_kernel<ST, 4, BC>;
+    }
+    return nullptr;
+}
+
+template <int ST>
+static hipError_t launch_part_t(const StepArgs& a, dim3 block, int spt, int part,
+                                hipStream_t st) {
+    void (*k)(StepArgs) = a.L.periodic ? part_kernel_for<ST, kPeriodic>(spt, part)
+                                       : part_kernel_for<ST, kWalls>(spt, part);
+    if (!k) return hipErrorInvalidValue;
+    const int blocks = part == kPartFluid ? a.n_tiles : a.part_gw * a.part_gh;
+    return launch_k(k, dim3(blocks), block, st, nullptr, nullptr, a);
+}
+
+hipError_t launch_step_part(int storage, const StepArgs& a, dim3 block, int spt, int part,
+                            hipStream_t st) {
+    if (part != kPartFluid && part != kPartFiber) return hipErrorInvalidValue;
+    if (a.part_gw < 1 || a.part_gh < 1 || a.part_gw > a.tiles_x ||
+        a.part_gh > a.n_tiles / a.tiles_x)
+        return hipErrorInvalidValue;
+    switch (storage) {  // (float64 steps are never split)
+        case FPD_F32: return launch_part_t<FPD_F32>(a, block, spt, part, st);
+        case FPD_F16DEV: return launch_part_t<FPD_F16DEV>(a, block, spt, part, st);
+        case FPD_BF16DEV: return launch_part_t<FPD_BF16DEV>(a, block, spt, part, st);
     }
     return hipErrorInvalidValue;
 }

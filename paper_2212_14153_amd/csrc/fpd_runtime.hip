@@ -13,6 +13,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -135,6 +136,11 @@ struct fpd_sim {
     fpd_launch launch{};
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_chunk = 0;
+    // split steps: the fluid kernels on a side stream, the fiber and bead kernels on
+    // `stream`, ordered by the two events (created with the first split step)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fluid = nullptr, ev_fiber = nullptr;
+    bool part_valid = false;     // BeadState::part[cur] was written by the step before
     // kernel timing
     std::vector<hipEvent_t> events;
     double ms_lat = 0.0, ms_bead = 0.0;
@@ -189,6 +195,12 @@ StepArgs make_args(const fpd_sim* s, int src_idx) {
     const int tiles_y = (s->L.ny + a.rows_per_block - 1) / a.rows_per_block;
     a.n_tiles = a.tiles_x * tiles_y;
     a.xcd_remap = c.xcd_remap == 1 ? 1 : 0;
+    // the fiber kernel's grid holds any partition: a window is at most rect_wmax x
+    // rect_hmax nodes, the partition kPartMargin more on each side, and a run of columns
+    // meets at most two tiles more than its width in tiles (one may be the narrow last)
+    const int m2 = 2 * kPartMargin;
+    a.part_gw = std::min(a.tiles_x, (s->rect_wmax + m2 + tw - 1) / tw + 2);
+    a.part_gh = std::min(tiles_y, (s->rect_hmax + m2 + a.rows_per_block - 1) / a.rows_per_block + 2);
     return a;
 }
 
@@ -254,6 +266,69 @@ bool has_ev(const fpd_sim* s) {
     return s->fiber && chains_of(&s->p) > 1 && s->p.ev_k > 0.0;
 }
 
+// Whether fpd_step splits the lattice step (fluid_kernel / fiber_kernel): with a fiber,
+// no fixed profile, neither FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS, a fiber kernel
+// grid of at most a quarter of the tiles (larger ones leave little to overlap), and not
+// in float64.  On MI355X at 8192 x 2048 with a 40-bead fiber (graph replay) split steps
+// took 107.4 against 112.4 us (float16 deviations) and 195.4 against 196.6 us (float32):
+// the bead kernel runs beside the fluid kernel, less the wait between the two streams
+// (about 5 us against 1 us between kernels of one stream).  In float64 they took 406.5
+// against 401.2 us: the float64 fiber tiles, heavy in double-precision arithmetic, slow
+// the fluid kernel beside them by more than the bead kernel's 15 us.
+bool use_split(const fpd_sim* s) {
+    if (!s->fiber || s->p.n_beads <= 0 || s->row_phi || s->p.storage == FPD_F64) return false;
+    if (s->p.flags & (FPD_FLAG_NO_SPLIT | FPD_FLAG_TIME_KERNELS)) return false;
+    const StepArgs a = make_args(s, s->cur);
+    return 4LL * a.part_gw * a.part_gh <= (long long)a.n_tiles;
+}
+
+int ensure_split(fpd_sim* s) {
+    if (!s->side) HIP_TRY(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+    if (!s->ev_fluid) HIP_TRY(hipEventCreateWithFlags(&s->ev_fluid, hipEventDisableTiming));
+    if (!s->ev_fiber) HIP_TRY(hipEventCreateWithFlags(&s->ev_fiber, hipEventDisableTiming));
+    return FPD_OK;
+}
+
+// One split step from buffer `from`.  The fluid kernel of step n reads the buffer the
+// fluid and fiber kernels of step n - 1 wrote and overwrites the one every kernel of step
+// n - 2 read, so it waits for the fiber kernel of step n - 1 (ev_fiber; the fluid kernel
+// of n - 1 is before it on the side stream; the bead kernel of n - 2 is before that fiber
+// kernel).  The fiber kernel of step n waits for the fluid kernel of step n - 1
+// (ev_fluid, taken before it is recorded again) and, on `stream`, for the bead kernel of
+// step n - 1, whose positions it needs; the bead kernel of step n reads only tiles of the
+// partition, which the fiber kernel wrote.  first: the start of a run (split_steps), whose
+// stream is already after every earlier kernel.
+int enqueue_split_step(fpd_sim* s, int from, bool first) {
+    const StepArgs a = make_args(s, from);
+    const dim3 block(s->launch.block_x, s->launch.block_y);
+    const int rpt = s->launch.rows_per_thread;
+    HIP_TRY(hipStreamWaitEvent(s->side, s->ev_fiber, 0));
+    HIP_TRY(launch_step_part(s->p.storage, a, block, rpt, kPartFluid, s->side));
+    if (!first) HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_fluid, 0));
+    HIP_TRY(hipEventRecord(s->ev_fluid, s->side));
+    HIP_TRY(launch_record(a, s->stream));
+    if (has_ev(s)) HIP_TRY(launch_ev(a, s->stream));
+    HIP_TRY(launch_step_part(s->p.storage, a, block, rpt, kPartFiber, s->stream));
+    HIP_TRY(hipEventRecord(s->ev_fiber, s->stream));
+    HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - from, s->stream));
+    return FPD_OK;
+}
+
+// n split steps from buffer `from`, then `stream` waits for the side stream's last kernel,
+// so work enqueued on `stream` afterwards follows all of them (also inside a capture, where
+// this joins the side stream back).
+int split_steps(fpd_sim* s, int from, int64_t n) {
+    HIP_TRY(hipEventRecord(s->ev_fiber, s->stream));
+    int b = from;
+    for (int64_t i = 0; i < n; ++i) {
+        int rc = enqueue_split_step(s, b, i == 0);
+        if (rc) return rc;
+        b = 1 - b;
+    }
+    HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_fluid, 0));
+    return FPD_OK;
+}
+
 // One step from buffer `from` (launches only).
 int enqueue_step(fpd_sim* s, int from) {
     const StepArgs a = make_args(s, from);
@@ -267,12 +342,21 @@ int enqueue_step(fpd_sim* s, int from) {
 
 int build_graph(fpd_sim* s, int from, int chunk, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
+    const bool split = use_split(s);
+    if (split) {
+        int rs = ensure_split(s);
+        if (rs) return rs;
+    }
     HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     int rc = FPD_OK;
-    int b = from;
-    for (int i = 0; i < chunk && rc == FPD_OK; ++i) {
-        rc = enqueue_step(s, b);
-        b = 1 - b;
+    if (split) {
+        rc = split_steps(s, from, chunk);
+    } else {
+        int b = from;
+        for (int i = 0; i < chunk && rc == FPD_OK; ++i) {
+            rc = enqueue_step(s, b);
+            b = 1 - b;
+        }
     }
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (rc != FPD_OK) {
@@ -518,8 +602,12 @@ int fpd_create_with_buffers(const fpd_params* p, void* hip_stream, void* f_a, vo
 void fpd_destroy(fpd_sim* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->side) (void)hipStreamSynchronize(s->side);
     drop_graphs(s);
     for (auto e : s->events) (void)hipEventDestroy(e);
+    if (s->ev_fluid) (void)hipEventDestroy(s->ev_fluid);
+    if (s->ev_fiber) (void)hipEventDestroy(s->ev_fiber);
+    if (s->side) (void)hipStreamDestroy(s->side);
     if (s->own_bufs)
         for (auto& b : s->buf)
             if (b) (void)hipFree(b);
@@ -582,6 +670,7 @@ int fpd_init_fiber(fpd_sim* s, const double* R) {
     }
     HIP_TRY(hipMemcpyAsync(s->bs, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
     drop_graphs(s);
+    s->part_valid = false;
     s->fiber = true;  // make_args hands the beads to the kernels only with a fiber
     // the stream is synchronised on every path below: the copy reads h from this frame
     const int rc = fiber_init_device(s);
@@ -650,12 +739,25 @@ int fpd_step(fpd_sim* s, int64_t n) {
         int rc = step_timed(s, n);
         if (rc) return rc;
         s->steps += n;
+        s->part_valid = true;
         return FPD_OK;
     }
     int64_t left = n;
+    const bool split = use_split(s);
+    if (split) {
+        int rc = ensure_split(s);
+        if (rc) return rc;
+        if (!s->part_valid) {  // the first split step's partition comes from a whole step
+            rc = enqueue_step(s, s->cur);
+            if (rc) return rc;
+            s->cur = 1 - s->cur;
+            s->part_valid = true;
+            --left;
+        }
+    }
     const int chunk = s->launch.graph_chunk;
     bool replay = false;
-    int rg = ensure_graph(s, n, &replay);
+    int rg = ensure_graph(s, left, &replay);
     if (rg) return rg;
     if (replay) {
         while (left >= chunk) {
@@ -663,12 +765,19 @@ int fpd_step(fpd_sim* s, int64_t n) {
             left -= chunk;  // chunk is even: the state returns to the same buffer
         }
     }
+    if (left > 0 && split) {
+        int rc = split_steps(s, s->cur, left);
+        if (rc) return rc;
+        if (left & 1) s->cur = 1 - s->cur;
+        left = 0;
+    }
     for (; left > 0; --left) {
         int rc = enqueue_step(s, s->cur);
         if (rc) return rc;
         s->cur = 1 - s->cur;
     }
     s->steps += n;
+    s->part_valid = true;
     return FPD_OK;
 }
 
@@ -983,8 +1092,15 @@ int fpd_set_flags(fpd_sim* s, uint32_t flags) {
     int rc = sync_check(s);
     if (rc) return rc;
     const uint32_t keep = s->p.flags & FPD_FLAG_CLAMP_PHI;
-    s->p.flags = keep | (flags & (FPD_FLAG_NO_GRAPH | FPD_FLAG_TIME_KERNELS));
+    s->p.flags =
+        keep | (flags & (FPD_FLAG_NO_GRAPH | FPD_FLAG_TIME_KERNELS | FPD_FLAG_NO_SPLIT));
     drop_graphs(s);
+    return FPD_OK;
+}
+
+int fpd_split_active(fpd_sim* s, int32_t* on) {
+    if (!s || !on) return fail(FPD_EINVAL, "NULL argument");
+    *on = use_split(s) ? 1 : 0;
     return FPD_OK;
 }
 
@@ -1043,7 +1159,7 @@ int fpd_copy_probe(void* hip_stream, size_t bytes, int32_t iters, double* gbps) 
 
 // ---------------------------------------------------------------- checkpoint -------
 
-static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '6'};
+static const char kMagic[8] = {'F', 'P', 'D', 'L', 'B', 'M', '0', '7'};
 
 int fpd_save(fpd_sim* s, const char* path) {
     TraceRange range("fpd_save");
@@ -1095,6 +1211,7 @@ int fpd_load(fpd_sim* s, const char* path) {
     fclose(fp);
     if (!ok) return fail(FPD_EINVAL, "%s is truncated", path);
     drop_graphs(s);
+    s->part_valid = false;
     s->cur = par;
     HIP_TRY(hipMemcpy(s->buf[s->cur], pops.data(), bytes, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->bs, &h, sizeof h, hipMemcpyHostToDevice));

@@ -47,9 +47,10 @@ def test_default_bench_line():
     assert 0.3 < r["frac"] < 1.0
     assert r["traffic"] is None or r["traffic"] >= r["bytes_per_launch_alg"]
     assert d["health_flags"] == 0
-    # every timed step replayed a captured graph (the chunk divides the 20 steps)
+    # every timed step replayed a captured graph (the chunk divides the 20 steps), of split
+    # steps (float32 with a 40-bead fiber on 8192 x 2048)
     assert d["config"]["timed_path"] == {"graph_chunk": 20, "graph_replays": 1,
-                                         "direct_steps": 0}
+                                         "direct_steps": 0, "split_steps": True}
 
 
 def test_bench_line_extras_small():
