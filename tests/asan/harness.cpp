@@ -2,10 +2,10 @@
 //
 // Built with AddressSanitizer on the host code only (the device code is the same as in
 // the library), it drives the C ABI through the paths that touch host memory: creation and
-// validation, stepping and read-back in three storage formats, checkpoint save / load
-// (including a truncated file and a missing one), recording, launch settings, a batch with
-// admission, launch / wait and the pending guard, release and the allocation-free entry
-// point, plus the error returns for NULL and invalid arguments.  Exit status 0 when every
+// validation, stepping and read-back in three storage formats, split steps, checkpoint
+// save / load (including a truncated file and a missing one), recording, launch settings,
+// a batch with admission, launch / wait and the pending guard, release and the
+// allocation-free entry point, plus the error returns for NULL and invalid arguments.  Exit status 0 when every
 // call returned what it should; AddressSanitizer aborts on any invalid host access.
 #include <hip/hip_runtime.h>
 
@@ -274,12 +274,64 @@ static int run_static() {
     return 0;
 }
 
+// split steps (a lattice large enough that the fiber's partition is a small part of it):
+// the side stream and events are created on first use and released by fpd_destroy, also
+// with split steps still in flight
+static int split(int storage) {
+    fpd_params p = channel(storage, 1024, 384, 10);
+    fpd_sim* s = nullptr;
+    EXPECT(fpd_create(&p, nullptr, &s), FPD_OK);
+    const std::vector<double> R = fiber(p);
+    EXPECT(fpd_init_fiber(s, R.data()), FPD_OK);
+    int32_t on = -1;
+    EXPECT(fpd_split_active(s, &on), FPD_OK);
+    if (on != 1) {
+        fprintf(stderr, "FAIL: split steps expected for storage %d\n", storage);
+        return 1;
+    }
+    EXPECT(fpd_split_active(s, nullptr), FPD_EINVAL);
+    EXPECT(fpd_split_active(nullptr, &on), FPD_EINVAL);
+    fpd_launch c;
+    EXPECT(fpd_get_launch(s, &c), FPD_OK);
+    c.graph_chunk = 8;
+    EXPECT(fpd_set_launch(s, &c), FPD_OK);
+    EXPECT(fpd_step(s, 3), FPD_OK);   // a whole first step, then direct split steps
+    EXPECT(fpd_capture(s, 16), FPD_OK);
+    EXPECT(fpd_step(s, 16), FPD_OK);  // graph replays of split steps
+    EXPECT(fpd_step(s, 5), FPD_OK);
+    EXPECT(fpd_sync(s), FPD_OK);
+    const std::string path = temp_path("split");
+    EXPECT(fpd_save(s, path.c_str()), FPD_OK);
+    EXPECT(fpd_load(s, path.c_str()), FPD_OK);
+    remove(path.c_str());
+    EXPECT(fpd_step(s, 4), FPD_OK);
+    EXPECT(fpd_set_flags(s, FPD_FLAG_NO_SPLIT), FPD_OK);
+    EXPECT(fpd_split_active(s, &on), FPD_OK);
+    if (on != 0) {
+        fprintf(stderr, "FAIL: FPD_FLAG_NO_SPLIT left split steps on\n");
+        return 1;
+    }
+    EXPECT(fpd_step(s, 4), FPD_OK);
+    EXPECT(fpd_set_flags(s, 0), FPD_OK);
+    std::vector<double> Rb(2 * (size_t)p.n_beads);
+    EXPECT(fpd_read_beads(s, Rb.data(), nullptr, nullptr), FPD_OK);
+    EXPECT(fpd_step(s, 6), FPD_OK);  // left running: fpd_destroy waits for both streams
+    fpd_destroy(s);
+    return 0;
+}
+
 int main() {
     const int storages[3] = {FPD_F64, FPD_F32, FPD_F16DEV};
     for (int st : storages) {
         printf("[asan] lifecycle storage %d\n", st);
         fflush(stdout);
         if (lifecycle(st)) return 1;
+    }
+    const int split_storages[2] = {FPD_F32, FPD_F16DEV};
+    for (int st : split_storages) {
+        printf("[asan] split steps storage %d\n", st);
+        fflush(stdout);
+        if (split(st)) return 1;
     }
     printf("[asan] invalid arguments\n");
     fflush(stdout);
