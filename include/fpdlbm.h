@@ -184,8 +184,7 @@ int fpd_init_fiber_line(fpd_sim *s, double cx, double cy, double theta);
  * fpd_init_fiber when the simulation has beads; an unstable run is reported by health
  * bits (fpd_sync), not here.
  * Split steps: with a fiber whose reserved window spans at most about a quarter of the
- * lattice's tiles, in float32 or the two-byte formats (no fixed profile, neither
- * FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS),
+ * lattice's tiles (no fixed profile, neither FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS),
  * step (2) runs as two kernels, the tiles away from the fiber on a second stream of the
  * library's own (non-blocking, default priority) while the bead kernel of the step before
  * finishes, and the tiles near it after that bead kernel; the results are the same bits.

@@ -12,6 +12,8 @@
 //                position, and the bead's share of the next support window and health bits
 //                (integer atomic min / max / or: order-independent).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 
 #include "fpd_device.hpp"
@@ -1498,6 +1500,44 @@ static hipError_t launch_k(void (*k)(P...), dim3 grid, dim3 block, hipStream_t s
     return hipLaunchKernel((const void*)k, grid, block, argv, 0, st);
 }
 
+// Dynamic LDS (unused by the kernel) that leaves room for `blocks` resident blocks of it
+// per compute unit on the current device, not more: midway between the shares of `blocks`
+// and `blocks + 1` of the device's LDS per compute unit, so that the allocation granule
+// does not change the count; within the per-block limit; 0 if the device does not report
+// them.
+static size_t lds_for_blocks(int blocks) {
+    static int per_cu[64], per_block[64];  // per device; 0: not asked yet, -1: unknown
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (per_cu[dev] == 0) {
+        int c = 0, b = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                  dev) != hipSuccess || c <= 0)
+            c = -1;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || b <= 0)
+            b = -1;
+        per_block[dev] = b;
+        per_cu[dev] = c;
+    }
+    if (per_cu[dev] <= 0 || per_block[dev] <= 0) return 0;
+    const int mid = (per_cu[dev] / blocks + per_cu[dev] / (blocks + 1)) / 2;
+    return (size_t)std::min(mid, per_block[dev]);
+}
+
+// Resident fluid-kernel waves per compute unit (the fluid kernel has no LDS of its own, so
+// only registers would limit it).  At 8192 x 2048 with the 40-bead fiber, split steps with
+// the fluid kernel held to 8 / 7 / 5 / 4 blocks of two waves per compute unit took 390.3 /
+// 388.2 / 386.3 / 387.7 us in float64, against 406.4 us unheld; with 6 / 5 / 4 blocks of
+// four waves 104.8-106.3 / 108.3-113.3 / 115.5 us in float16 deviations against
+// 106.9-107.1, and with 6 / 5 blocks 194.4 / 194.2 us in float32 against 195.7: fewer
+// concurrent row streams beside the fiber tiles.  (The whole-step kernel's own 15.5 KB of
+// LDS holds it to 10 blocks; fewer gained it at most 0.6 %.)
+template <int ST>
+constexpr int fluid_waves_per_cu() {
+    return ST == FPD_F64 ? 10 : 24;
+}
+
 template <int ST, int BC>
 static void (*step_kernel_for(int spt))(StepArgs) {
     switch (spt) {
@@ -1546,7 +1586,13 @@ static hipError_t launch_part_t(const StepArgs& a, dim3 block, int spt, int part
                                        : part_kernel_for<ST, kWalls>(spt, part);
     if (!k) return hipErrorInvalidValue;
     const int blocks = part == kPartFluid ? a.n_tiles : a.part_gw * a.part_gh;
-    return launch_k(k, dim3(blocks), block, st, nullptr, nullptr, a);
+    size_t lds = 0;
+    if (part == kPartFluid) {
+        const int waves = ((int)(block.x * block.y) + 63) / 64;
+        lds = lds_for_blocks(std::max(1, fluid_waves_per_cu<ST>() / waves));
+    }
+    void* argv[] = {(void*)&a};
+    return hipLaunchKernel((const void*)k, dim3(blocks), block, argv, lds, st);
 }
 
 hipError_t launch_step_part(int storage, const StepArgs& a, dim3 block, int spt, int part,
@@ -1555,7 +1601,8 @@ hipError_t launch_step_part(int storage, const StepArgs& a, dim3 block, int spt,
     if (a.part_gw < 1 || a.part_gh < 1 || a.part_gw > a.tiles_x ||
         a.part_gh > a.n_tiles / a.tiles_x)
         return hipErrorInvalidValue;
-    switch (storage) {  // (float64 steps are never split)
+    switch (storage) {
+        case FPD_F64: return launch_part_t<FPD_F64>(a, block, spt, part, st);
         case FPD_F32: return launch_part_t<FPD_F32>(a, block, spt, part, st);
         case FPD_F16DEV: return launch_part_t<FPD_F16DEV>(a, block, spt, part, st);
         case FPD_BF16DEV: return launch_part_t<FPD_BF16DEV>(a, block, spt, part, st);

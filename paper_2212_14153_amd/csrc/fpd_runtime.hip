@@ -267,16 +267,15 @@ bool has_ev(const fpd_sim* s) {
 }
 
 // Whether fpd_step splits the lattice step (fluid_kernel / fiber_kernel): with a fiber,
-// no fixed profile, neither FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS, a fiber kernel
-// grid of at most a quarter of the tiles (larger ones leave little to overlap), and not
-// in float64.  On MI355X at 8192 x 2048 with a 40-bead fiber (graph replay) split steps
-// took 107.4 against 112.4 us (float16 deviations) and 195.4 against 196.6 us (float32):
-// the bead kernel runs beside the fluid kernel, less the wait between the two streams
-// (about 5 us against 1 us between kernels of one stream).  In float64 they took 406.5
-// against 401.2 us: the float64 fiber tiles, heavy in double-precision arithmetic, slow
-// the fluid kernel beside them by more than the bead kernel's 15 us.
+// no fixed profile, neither FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS, and a fiber
+// kernel grid of at most a quarter of the tiles (larger ones leave little to overlap).
+// On MI355X at 8192 x 2048 with a 40-bead fiber (graph replay, the fluid kernel's
+// occupancy held down as fluid_waves_per_cu states) split steps took about 4 % less than
+// whole steps in float64 and float16 deviations and 1 % less in float32: the bead kernel
+// runs beside the fluid kernel, less the wait between the two streams (about 5 us against
+// 1 us between kernels of one stream).
 bool use_split(const fpd_sim* s) {
-    if (!s->fiber || s->p.n_beads <= 0 || s->row_phi || s->p.storage == FPD_F64) return false;
+    if (!s->fiber || s->p.n_beads <= 0 || s->row_phi) return false;
     if (s->p.flags & (FPD_FLAG_NO_SPLIT | FPD_FLAG_TIME_KERNELS)) return false;
     const StepArgs a = make_args(s, s->cur);
     return 4LL * a.part_gw * a.part_gh <= (long long)a.n_tiles;

@@ -52,12 +52,12 @@ def compare(w, launch=None):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
 def test_split_steps_are_bitwise_whole_steps(storage):
     compare(fiber(1024, 384, storage, cx=400.0, cy=190.0, theta=0.7))
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
 def test_split_across_the_periodic_x_edge(storage):
     """The partition wraps around x = 0 (its tiles run from the last, narrow one on)."""
     compare(fiber(1000, 384, storage, cx=2.0, cy=150.0, theta=0.3))
@@ -85,13 +85,10 @@ def test_split_with_other_launch_shapes(storage, launch):
 
 
 def test_split_not_taken_where_it_cannot_pay():
-    """A partition of more than a quarter of the tiles (a small lattice), float64 storage
-    or a fixed profile: whole steps."""
+    """A partition of more than a quarter of the tiles (a small lattice) or a fixed
+    profile: whole steps."""
     w = fiber(96, 40, "f32", cx=48.0, cy=20.0, theta=0.2, n_beads=5)
     with _lib.simulation_from_workload(w, storage="f32") as sim:
-        assert not sim.split_active()
-    w = fiber(1024, 384, "f64", cx=400.0, cy=190.0, theta=0.7)
-    with _lib.simulation_from_workload(w, storage="f64") as sim:
         assert not sim.split_active()
     w = fiber(1024, 384, "f32", cx=400.0, cy=190.0, theta=0.7)
     with _lib.simulation_from_workload(w, storage="f32") as sim:
