@@ -281,10 +281,24 @@ bool use_split(const fpd_sim* s) {
     return 4LL * a.part_gw * a.part_gh <= (long long)a.n_tiles;
 }
 
+// The side stream and the two events, on the device of the simulation's stream (made
+// current for the creation if another one is).
 int ensure_split(fpd_sim* s) {
-    if (!s->side) HIP_TRY(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
-    if (!s->ev_fluid) HIP_TRY(hipEventCreateWithFlags(&s->ev_fluid, hipEventDisableTiming));
-    if (!s->ev_fiber) HIP_TRY(hipEventCreateWithFlags(&s->ev_fiber, hipEventDisableTiming));
+    if (s->side && s->ev_fluid && s->ev_fiber) return FPD_OK;
+    hipDevice_t dev = 0;
+    int cur = 0;
+    HIP_TRY(hipStreamGetDevice(s->stream, &dev));
+    HIP_TRY(hipGetDevice(&cur));
+    if (dev != cur) HIP_TRY(hipSetDevice(dev));
+    hipError_t e = hipSuccess;
+    if (!s->side) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    if (e == hipSuccess && !s->ev_fluid)
+        e = hipEventCreateWithFlags(&s->ev_fluid, hipEventDisableTiming);
+    if (e == hipSuccess && !s->ev_fiber)
+        e = hipEventCreateWithFlags(&s->ev_fiber, hipEventDisableTiming);
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess)
+        return fail(FPD_EDEVICE, "split-step stream or events: %s", hipGetErrorString(e));
     return FPD_OK;
 }
 
