@@ -80,9 +80,10 @@ def kernel_hash() -> str:
     return kernel_source_hash()
 
 
-def measured_traffic(storage, nodes, workload):
+def measured_traffic(storage, nodes, workload, kernel="step_kernel"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source, this storage and this workload; else None."""
+    on the current kernel source, this storage, this workload and these kernels; else
+    None."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -90,7 +91,7 @@ def measured_traffic(storage, nodes, workload):
         return None
     ent = rec.get("entries", {}).get(storage)
     if (not ent or rec.get("kernel_sha") != kernel_hash() or ent.get("nodes") != nodes
-            or ent.get("workload") != workload):
+            or ent.get("workload") != workload or ent.get("kernel") != kernel):
         return None
     return ent.get("bytes_per_launch")
 
@@ -697,11 +698,11 @@ def time_steps(sim, stream, steps, warmup):
 
 def kernel_pass(sim, steps, warmup=4, flags=0):
     """The same number of steps again with every lattice and bead launch stamped by its own
-    dispatch (FPD_FLAG_TIME_KERNELS: whole steps, one lattice kernel each), after `warmup`
-    untimed steps in the same mode: average lattice and bead kernel durations in ms.  The
-    simulation's flags are `flags` afterwards."""
+    dispatch (FPD_FLAG_TIME_KERNELS added to `flags`: the steps split or whole as in the
+    timed region), after `warmup` untimed steps in the same mode: average lattice-pass and
+    bead kernel durations in ms.  The simulation's flags are `flags` afterwards."""
     from paper_2212_14153_amd import _lib
-    sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
+    sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS | flags)
     sim.step(warmup)
     sim.sync()
     sim.reset_kernel_times()
@@ -845,8 +846,11 @@ def main():
         how += " (split steps)"
     log(f"{how}: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS")
 
-    # the same simulation, every lattice and bead launch stamped by its own dispatch
+    # the same simulation, every lattice and bead launch stamped by its own dispatch (split
+    # steps: the lattice pass from the earlier start to the later end of the fluid and
+    # fiber kernels, beside each other)
     lat_ms, bead_ms = kernel_pass(sim, args.steps, flags=base_flags)
+    lattice = "fluid_kernel+fiber_kernel" if path["split_steps"] else "step_kernel"
     bytes_alg = 18 * BYTES_PER_VALUE[args.storage] * nodes
     achieved = bytes_alg / (lat_ms * 1e-3) / 1e9
     log(f"lattice kernel {lat_ms * 1e3:.1f} us ({achieved:.0f} GB/s), bead kernel "
@@ -854,7 +858,7 @@ def main():
     flags, strain = sim.health()
     sim.close()
 
-    traffic = measured_traffic(args.storage, nodes, args.workload)
+    traffic = measured_traffic(args.storage, nodes, args.workload, lattice)
     out = {
         "metric": "MLUPS & % HBM roofline", "value": round(mlups, 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -866,7 +870,7 @@ def main():
                    "launch": cfg.__dict__, "timed_path": path},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "kernel": "step_kernel",
+                     "traffic": traffic, "kernel": lattice,
                      "bytes_per_launch_alg": bytes_alg, "avg_launch_ms": round(lat_ms, 5)},
         "bead_kernel_ms": round(bead_ms, 5),
         "copy_probe_gbps": round(copy_gbps, 1),

@@ -71,7 +71,7 @@ extern "C" {
 /* flags */
 #define FPD_FLAG_CLAMP_PHI     0x1u  /* clamp sum_i phi_i to 1 in Eq. (1)                 */
 #define FPD_FLAG_NO_GRAPH      0x2u  /* launch every kernel directly (no graph replay)    */
-#define FPD_FLAG_TIME_KERNELS  0x4u  /* time the lattice and bead kernels (implies NO_GRAPH) */
+#define FPD_FLAG_TIME_KERNELS  0x4u  /* time the lattice pass and bead kernel (no graph)    */
 #define FPD_FLAG_NO_SPLIT      0x8u  /* one lattice kernel per step (no split steps)      */
 
 /* health bits, sticky until fpd_clear_health */
@@ -184,7 +184,7 @@ int fpd_init_fiber_line(fpd_sim *s, double cx, double cy, double theta);
  * fpd_init_fiber when the simulation has beads; an unstable run is reported by health
  * bits (fpd_sync), not here.
  * Split steps: with a fiber whose reserved window spans at most about a quarter of the
- * lattice's tiles (no fixed profile, neither FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS),
+ * lattice's tiles (no fixed profile, not FPD_FLAG_NO_SPLIT),
  * step (2) runs as two kernels, the tiles away from the fiber on a second stream of the
  * library's own (non-blocking, default priority) while the bead kernel of the step before
  * finishes, and the tiles near it after that bead kernel; the results are the same bits.
@@ -287,10 +287,13 @@ int fpd_get_launch(fpd_sim *s, fpd_launch *cfg);
  * first step after fpd_init_fiber or fpd_load runs whole either way. */
 int fpd_split_active(fpd_sim *s, int32_t *on);
 
-/* Kernel timing with FPD_FLAG_TIME_KERNELS: summed duration (ms) and launch count of the
- * fused lattice kernel and of the bead kernel since the last reset.  Each duration is that
- * of the dispatch itself: its events are stamped by the launch (hipExtLaunchKernel), not
- * recorded as separate queue entries around it. */
+/* Kernel timing with FPD_FLAG_TIME_KERNELS: summed duration (ms) and count of the lattice
+ * passes and of the bead kernels since the last reset.  Each duration is that of the
+ * dispatches themselves: their events are stamped by the launch (hipExtLaunchKernel), not
+ * recorded as separate queue entries around it.  A whole step's lattice pass is its fused
+ * lattice kernel; a split step's (fpd_step) runs from the earlier start to the later end of
+ * its fluid and fiber kernels, which run beside each other.  The first split step after
+ * fpd_init_fiber or fpd_load runs whole and untimed. */
 int fpd_kernel_times(fpd_sim *s, double *ms_lattice, int64_t *n_lattice, double *ms_bead,
                      int64_t *n_bead);
 int fpd_reset_kernel_times(fpd_sim *s);

@@ -172,7 +172,8 @@ hipError_t launch_step(int storage, const StepArgs& a, dim3 block, int rows_per_
 // One half of a split step (kPartFluid or kPartFiber; the fiber half's grid is
 // a.part_gw * a.part_gh blocks)
 hipError_t launch_step_part(int storage, const StepArgs& a, dim3 block, int rows_per_thread,
-                            int part, hipStream_t st);
+                            int part, hipStream_t st, hipEvent_t t0 = nullptr,
+                            hipEvent_t t1 = nullptr);
 hipError_t launch_bead(int storage, const StepArgs& a, int do_velocity, int win_out,
                        hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_forces(const StepArgs& a, hipStream_t st);

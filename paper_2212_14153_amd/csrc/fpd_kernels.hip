@@ -1581,7 +1581,7 @@ static void (*part_kernel_for(int spt, int part))(StepArgs) {
 
 template <int ST>
 static hipError_t launch_part_t(const StepArgs& a, dim3 block, int spt, int part,
-                                hipStream_t st) {
+                                hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     void (*k)(StepArgs) = a.L.periodic ? part_kernel_for<ST, kPeriodic>(spt, part)
                                        : part_kernel_for<ST, kWalls>(spt, part);
     if (!k) return hipErrorInvalidValue;
@@ -1592,20 +1592,22 @@ static hipError_t launch_part_t(const StepArgs& a, dim3 block, int spt, int part
         lds = lds_for_blocks(std::max(1, fluid_waves_per_cu<ST>() / waves));
     }
     void* argv[] = {(void*)&a};
+    if (t0 || t1)
+        return hipExtLaunchKernel((const void*)k, dim3(blocks), block, argv, lds, st, t0, t1, 0);
     return hipLaunchKernel((const void*)k, dim3(blocks), block, argv, lds, st);
 }
 
 hipError_t launch_step_part(int storage, const StepArgs& a, dim3 block, int spt, int part,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     if (part != kPartFluid && part != kPartFiber) return hipErrorInvalidValue;
     if (a.part_gw < 1 || a.part_gh < 1 || a.part_gw > a.tiles_x ||
         a.part_gh > a.n_tiles / a.tiles_x)
         return hipErrorInvalidValue;
     switch (storage) {
-        case FPD_F64: return launch_part_t<FPD_F64>(a, block, spt, part, st);
-        case FPD_F32: return launch_part_t<FPD_F32>(a, block, spt, part, st);
-        case FPD_F16DEV: return launch_part_t<FPD_F16DEV>(a, block, spt, part, st);
-        case FPD_BF16DEV: return launch_part_t<FPD_BF16DEV>(a, block, spt, part, st);
+        case FPD_F64: return launch_part_t<FPD_F64>(a, block, spt, part, st, t0, t1);
+        case FPD_F32: return launch_part_t<FPD_F32>(a, block, spt, part, st, t0, t1);
+        case FPD_F16DEV: return launch_part_t<FPD_F16DEV>(a, block, spt, part, st, t0, t1);
+        case FPD_BF16DEV: return launch_part_t<FPD_BF16DEV>(a, block, spt, part, st, t0, t1);
     }
     return hipErrorInvalidValue;
 }

@@ -267,8 +267,8 @@ bool has_ev(const fpd_sim* s) {
 }
 
 // Whether fpd_step splits the lattice step (fluid_kernel / fiber_kernel): with a fiber,
-// no fixed profile, neither FPD_FLAG_NO_SPLIT nor FPD_FLAG_TIME_KERNELS, and a fiber
-// kernel grid of at most a quarter of the tiles (larger ones leave little to overlap).
+// no fixed profile, not FPD_FLAG_NO_SPLIT, and a fiber kernel grid of at most a quarter
+// of the tiles (larger ones leave little to overlap).
 // On MI355X at 8192 x 2048 with a 40-bead fiber (graph replay, the fluid kernel's
 // occupancy held down as fluid_waves_per_cu states) split steps took about 4 % less than
 // whole steps in float64 and float16 deviations and 1 % less in float32: the bead kernel
@@ -276,7 +276,7 @@ bool has_ev(const fpd_sim* s) {
 // 1 us between kernels of one stream).
 bool use_split(const fpd_sim* s) {
     if (!s->fiber || s->p.n_beads <= 0 || s->row_phi) return false;
-    if (s->p.flags & (FPD_FLAG_NO_SPLIT | FPD_FLAG_TIME_KERNELS)) return false;
+    if (s->p.flags & FPD_FLAG_NO_SPLIT) return false;
     const StepArgs a = make_args(s, s->cur);
     return 4LL * a.part_gw * a.part_gh <= (long long)a.n_tiles;
 }
@@ -387,10 +387,26 @@ int build_graph(fpd_sim* s, int from, int chunk, hipGraphExec_t* out) {
 }
 
 // Steps launched one by one, the lattice and bead kernels each stamped with the start and
-// end of their own dispatch (durations summed into ms_lat and ms_bead).
+// end of their own dispatch (durations summed into ms_lat and ms_bead).  Split steps (the
+// order of enqueue_split_step) stamp the fluid and the fiber kernel; their lattice pass
+// runs from the earlier start to the later end of the two.
 int step_timed(fpd_sim* s, int64_t n) {
     const bool fib = s->fiber && s->p.n_beads > 0;
-    const size_t per = fib ? 4 : 2;
+    const bool split = use_split(s);
+    if (split) {
+        int rc = ensure_split(s);
+        if (rc) return rc;
+        if (!s->part_valid && n > 0) {  // the first split step's partition (untimed)
+            rc = enqueue_step(s, s->cur);
+            if (rc) return rc;
+            s->cur = 1 - s->cur;
+            s->part_valid = true;
+            --n;
+        }
+    }
+    const size_t per = split ? 6 : fib ? 4 : 2;
+    const dim3 block(s->launch.block_x, s->launch.block_y);
+    const int rpt = s->launch.rows_per_thread;
     for (int64_t done = 0; done < n;) {
         const int64_t batch = n - done < 512 ? n - done : 512;
         const size_t need = (size_t)batch * per;
@@ -399,33 +415,56 @@ int step_timed(fpd_sim* s, int64_t n) {
             HIP_TRY(hipEventCreate(&e));
             s->events.push_back(e);
         }
+        if (split) HIP_TRY(hipEventRecord(s->ev_fiber, s->stream));
         for (int64_t i = 0; i < batch; ++i) {
             const StepArgs a = make_args(s, s->cur);
-            const dim3 block(s->launch.block_x, s->launch.block_y);
             hipEvent_t* ev = &s->events[(size_t)i * per];
+            if (split) {
+                HIP_TRY(hipStreamWaitEvent(s->side, s->ev_fiber, 0));
+                HIP_TRY(launch_step_part(s->p.storage, a, block, rpt, kPartFluid, s->side,
+                                         ev[0], ev[1]));
+                if (i > 0) HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_fluid, 0));
+                HIP_TRY(hipEventRecord(s->ev_fluid, s->side));
+            }
             HIP_TRY(launch_record(a, s->stream));
             if (has_ev(s)) HIP_TRY(launch_ev(a, s->stream));
-            HIP_TRY(launch_step(s->p.storage, a, block, s->launch.rows_per_thread, s->stream,
-                                ev[0], ev[1]));
-            if (fib)
-                HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - s->cur, s->stream, ev[2], ev[3]));
+            if (split) {
+                HIP_TRY(launch_step_part(s->p.storage, a, block, rpt, kPartFiber, s->stream,
+                                         ev[2], ev[3]));
+                HIP_TRY(hipEventRecord(s->ev_fiber, s->stream));
+                HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - s->cur, s->stream, ev[4], ev[5]));
+            } else {
+                HIP_TRY(launch_step(s->p.storage, a, block, rpt, s->stream, ev[0], ev[1]));
+                if (fib)
+                    HIP_TRY(launch_bead(s->p.storage, a, 1, 1 - s->cur, s->stream, ev[2],
+                                        ev[3]));
+            }
             s->cur = 1 - s->cur;
         }
+        if (split) HIP_TRY(hipStreamWaitEvent(s->stream, s->ev_fluid, 0));
         HIP_TRY(hipStreamSynchronize(s->stream));
         for (int64_t i = 0; i < batch; ++i) {
             hipEvent_t* ev = &s->events[(size_t)i * per];
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            if (split) {  // times relative to the fluid kernel's start, either sign
+                float fib0 = 0.f, fib1 = 0.f;
+                HIP_TRY(hipEventElapsedTime(&fib0, ev[0], ev[2]));
+                HIP_TRY(hipEventElapsedTime(&fib1, ev[0], ev[3]));
+                ms = std::max(ms, fib1) - std::min(0.f, fib0);
+            }
             s->ms_lat += ms;
             s->n_lat += 1;
             if (fib) {
-                HIP_TRY(hipEventElapsedTime(&ms, ev[2], ev[3]));
+                const hipEvent_t* b = split ? ev + 4 : ev + 2;
+                HIP_TRY(hipEventElapsedTime(&ms, b[0], b[1]));
                 s->ms_bead += ms;
                 s->n_bead += 1;
             }
         }
         done += batch;
     }
+    s->part_valid = true;
     return FPD_OK;
 }
 
@@ -752,7 +791,6 @@ int fpd_step(fpd_sim* s, int64_t n) {
         int rc = step_timed(s, n);
         if (rc) return rc;
         s->steps += n;
-        s->part_valid = true;
         return FPD_OK;
     }
     int64_t left = n;

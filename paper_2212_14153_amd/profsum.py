@@ -101,19 +101,23 @@ def _pick(per_kernel: dict, key: str):
 
 
 def traffic_entry(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int):
+    """Scaled HBM bytes per launch of `kernel`; 'a+b' names the kernels of one pass (a
+    split step's fluid and fiber kernels), whose per-dispatch medians add up."""
     fetch = read_counter(fetch_csv, "FETCH_SIZE")
     write = read_counter(write_csv, "WRITE_SIZE")
     copy_f = statistics.median(_pick(fetch, COPY_KERNEL)) * 1024.0
     copy_w = statistics.median(_pick(write, COPY_KERNEL)) * 1024.0
     f_fetch = copy_bytes / copy_f
     f_write = copy_bytes / copy_w
-    k_f = statistics.median(_pick(fetch, kernel)) * 1024.0
-    k_w = statistics.median(_pick(write, kernel)) * 1024.0
+    parts = kernel.split("+")
+    k_f = sum(statistics.median(_pick(fetch, k)) for k in parts) * 1024.0
+    k_w = sum(statistics.median(_pick(write, k)) for k in parts) * 1024.0
     read, wrote = round(k_f * f_fetch), round(k_w * f_write)
     return {"fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4),
             "read_bytes_per_launch": read, "write_bytes_per_launch": wrote,
             "bytes_per_launch": read + wrote,
-            "dispatches": [len(_pick(fetch, kernel)), len(_pick(write, kernel))]}
+            "dispatches": [min(len(_pick(fetch, k)) for k in parts),
+                           min(len(_pick(write, k)) for k in parts)]}
 
 
 def main(argv=None):
@@ -159,11 +163,12 @@ def main(argv=None):
         new = not os.path.exists(a.md)
         with open(a.md, "a") as f:
             if new:
-                f.write("# HBM traffic of the fused lattice kernel (rocprofv3 counters)\n\n"
-                        "FETCH_SIZE and WRITE_SIZE per dispatch (median), each scaled by the "
-                        "factor that makes the same counter read the known size of a 1 GiB "
-                        "plain copy dispatched in the same run.\n\n")
-            f.write(f"## {a.storage}, {a.nodes} nodes, kernel source {sha}\n\n"
+                f.write("# HBM traffic of the lattice pass (rocprofv3 counters)\n\n"
+                        "FETCH_SIZE and WRITE_SIZE per dispatch (median; for a split step "
+                        "the fluid and the fiber kernel added), each scaled by the factor "
+                        "that makes the same counter read the known size of a 1 GiB plain "
+                        "copy dispatched in the same run.\n\n")
+            f.write(f"## {a.storage}, {a.nodes} nodes, {a.kernel}, kernel source {sha}\n\n"
                     f"Commands (FETCH_SIZE, then WRITE_SIZE):\n\n```\n{a.command}\n```\n\n"
                     f"- fetch factor {ent['fetch_factor']}, write factor {ent['write_factor']}\n"
                     f"- read {ent['read_bytes_per_launch']} B, write "

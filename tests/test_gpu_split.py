@@ -84,6 +84,28 @@ def test_split_with_other_launch_shapes(storage, launch):
     compare(fiber(1000, 390, storage, cx=990.0, cy=200.0, theta=2.4), launch)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16dev"])
+def test_timed_split_steps_match_untimed(storage):
+    """FPD_FLAG_TIME_KERNELS keeps split steps (direct launches, each kernel stamped): the
+    same bits as graph-replayed split steps; the first step after the fiber runs whole and
+    untimed; a lattice pass spans its fluid and fiber kernels."""
+    w = fiber(1024, 384, storage, cx=400.0, cy=190.0, theta=0.7)
+    print(f"[case] timed split {storage}", flush=True)
+    with _lib.simulation_from_workload(w, storage=storage,
+                                       flags=_lib.FPD_FLAG_TIME_KERNELS) as a, \
+            _lib.simulation_from_workload(w, storage=storage) as b:
+        assert a.split_active()
+        a.step(31)
+        b.set_launch(dict(graph_chunk=10))
+        b.step(31)
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.populations(), b.populations())
+        assert np.array_equal(a.beads()[0], b.beads()[0])
+        ms_l, n_l, ms_b, n_b = a.kernel_times()
+        assert n_l == 30 and n_b == 30 and ms_l > 0 and ms_b > 0
+
+
 def test_split_not_taken_where_it_cannot_pay():
     """A partition of more than a quarter of the tiles (a small lattice) or a fixed
     profile: whole steps."""
@@ -93,8 +115,10 @@ def test_split_not_taken_where_it_cannot_pay():
     w = fiber(1024, 384, "f32", cx=400.0, cy=190.0, theta=0.7)
     with _lib.simulation_from_workload(w, storage="f32") as sim:
         assert sim.split_active()
-        sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)
+        sim.set_flags(_lib.FPD_FLAG_NO_SPLIT)
         assert not sim.split_active()
+        sim.set_flags(_lib.FPD_FLAG_TIME_KERNELS)  # timed steps stay split
+        assert sim.split_active()
         sim.set_flags(0)
         assert sim.split_active()
         sim.set_static_phi(np.zeros(w.ny))

@@ -64,17 +64,39 @@ def test_bench_uses_an_entry_only_where_it_was_measured(tmp_path, monkeypatch):
     bench = load_bench()
     sha = profsum.kernel_source_hash()
     path = tmp_path / "traffic.json"
+    split = "fluid_kernel+fiber_kernel"
     rec = {"kernel_sha": sha,
-           "entries": {"f32": {"bytes_per_launch": 1234, "nodes": 4096, "workload": "c3"}}}
+           "entries": {"f32": {"bytes_per_launch": 1234, "nodes": 4096, "workload": "c3",
+                               "kernel": split}}}
     path.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    assert bench.measured_traffic("f32", 4096, "c3") == 1234
-    assert bench.measured_traffic("f32", 4096, "suspension") is None   # same lattice size
-    assert bench.measured_traffic("f32", 8192, "c3") is None
-    assert bench.measured_traffic("f64", 4096, "c3") is None
+    assert bench.measured_traffic("f32", 4096, "c3", split) == 1234
+    assert bench.measured_traffic("f32", 4096, "c3", "step_kernel") is None  # other kernels
+    assert bench.measured_traffic("f32", 4096, "suspension", split) is None  # same lattice size
+    assert bench.measured_traffic("f32", 8192, "c3", split) is None
+    assert bench.measured_traffic("f64", 4096, "c3", split) is None
     rec["kernel_sha"] = "0" * 16                                         # kernels changed since
     path.write_text(json.dumps(rec))
-    assert bench.measured_traffic("f32", 4096, "c3") is None
+    assert bench.measured_traffic("f32", 4096, "c3", split) is None
+
+
+def test_traffic_of_a_pass_adds_its_kernels(tmp_path):
+    """'a+b': the per-dispatch medians of both kernels add up, each scaled by the factor
+    the copy kernel of the same run gives."""
+    def write(path, counter, copy_kib, a_kib, b_kib):
+        lines = ["Kernel_Name,Counter_Name,Counter_Value"]
+        lines += [f"copy_kernel,{counter},{copy_kib}"] * 3
+        lines += [f'"void fpd::fluid_kernel<1, 1, 0>(fpd::StepArgs)",{counter},{v}' for v in a_kib]
+        lines += [f'"void fpd::fiber_kernel<1, 1, 0>(fpd::StepArgs)",{counter},{v}' for v in b_kib]
+        path.write_text("\n".join(lines) + "\n")
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    write(f, "FETCH_SIZE", 512.0, [100.0, 101.0, 99.0], [10.0, 12.0, 11.0])
+    write(w, "WRITE_SIZE", 1024.0, [90.0, 90.0, 91.0], [8.0, 8.0, 9.0])
+    ent = profsum.traffic_entry(str(f), str(w), "fluid_kernel+fiber_kernel", 1024 * 1024)
+    assert ent["fetch_factor"] == 2.0 and ent["write_factor"] == 1.0
+    assert ent["read_bytes_per_launch"] == round((100.0 + 11.0) * 1024 * 2.0)
+    assert ent["write_bytes_per_launch"] == round((90.0 + 8.0) * 1024)
+    assert ent["dispatches"] == [3, 3]
 
 
 def test_committed_traffic_entries_name_their_workload():
