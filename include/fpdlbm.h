@@ -198,7 +198,9 @@ int fpd_step(fpd_sim *s, int64_t n_steps);
  * (steps are replayed in captured chunks of graph_chunk steps when n_steps >= graph_chunk
  * and neither FPD_FLAG_NO_GRAPH nor FPD_FLAG_TIME_KERNELS is set; otherwise there is
  * nothing to capture and the call does nothing), so that the capture cost stays out of a
- * timed fpd_step.  Synchronous with respect to the host; enqueues no work. */
+ * timed fpd_step; with split steps right after fpd_init_fiber or fpd_load, the graph of
+ * the steps after the whole first one.  Synchronous with respect to the host; enqueues no
+ * work. */
 int fpd_capture(fpd_sim *s, int64_t n_steps);
 
 /* Wait for the stream; FPD_EUNSTABLE if a health bit is set. */

@@ -751,8 +751,9 @@ int fpd_init_fiber_line(fpd_sim* s, double cx, double cy, double theta) {
 
 namespace {
 
-// Whether fpd_step(n) replays graphs, and the graph it replays captured (nothing runs).
-int ensure_graph(fpd_sim* s, int64_t n, bool* replay) {
+// Whether n steps from buffer `from` replay graphs, and the graph they replay captured
+// (nothing runs).
+int ensure_graph(fpd_sim* s, int from, int64_t n, bool* replay) {
     const int chunk = s->launch.graph_chunk;
     *replay = !(s->p.flags & (FPD_FLAG_NO_GRAPH | FPD_FLAG_TIME_KERNELS)) && chunk >= 2 &&
               n >= chunk;
@@ -761,7 +762,7 @@ int ensure_graph(fpd_sim* s, int64_t n, bool* replay) {
         drop_graphs(s);
         s->graph_chunk = chunk;
     }
-    if (!s->graph[s->cur]) return build_graph(s, s->cur, chunk, &s->graph[s->cur]);
+    if (!s->graph[from]) return build_graph(s, from, chunk, &s->graph[from]);
     return FPD_OK;
 }
 
@@ -776,7 +777,9 @@ int fpd_capture(fpd_sim* s, int64_t n) {
     if (s->p.n_beads > 0 && !s->fiber)
         return fail(FPD_ESTATE, "fpd_init_fiber must come before fpd_capture");
     bool replay = false;
-    return ensure_graph(s, n, &replay);
+    if (use_split(s) && !s->part_valid && n > 0)  // fpd_step runs one whole step first
+        return ensure_graph(s, 1 - s->cur, n - 1, &replay);
+    return ensure_graph(s, s->cur, n, &replay);
 }
 
 int fpd_step(fpd_sim* s, int64_t n) {
@@ -808,7 +811,7 @@ int fpd_step(fpd_sim* s, int64_t n) {
     }
     const int chunk = s->launch.graph_chunk;
     bool replay = false;
-    int rg = ensure_graph(s, left, &replay);
+    int rg = ensure_graph(s, s->cur, left, &replay);
     if (rg) return rg;
     if (replay) {
         while (left >= chunk) {

@@ -125,6 +125,23 @@ def test_split_not_taken_where_it_cannot_pay():
         assert not sim.split_active()
 
 
+def test_capture_right_after_the_fiber():
+    """fpd_capture right after fpd_init_fiber captures the graph of the steps after the
+    whole first one; the run matches one without the capture."""
+    w = fiber(1024, 384, "f32", cx=400.0, cy=190.0, theta=0.7)
+    print("[case] capture after init", flush=True)
+    with _lib.simulation_from_workload(w, storage="f32") as a, \
+            _lib.simulation_from_workload(w, storage="f32", flags=_lib.FPD_FLAG_NO_SPLIT) as b:
+        a.set_launch(dict(graph_chunk=8))
+        a.capture(17)
+        a.step(17)
+        b.step(17)
+        a.sync()
+        b.sync()
+        assert np.array_equal(a.populations(), b.populations())
+        assert np.array_equal(a.beads()[0], b.beads()[0])
+
+
 def test_split_after_save_and_load(tmp_path):
     """After fpd_load the first step runs whole (the stored partition is not trusted) and
     the run continues as if uninterrupted."""
