@@ -106,6 +106,25 @@ def test_timed_split_steps_match_untimed(storage):
         assert n_l == 30 and n_b == 30 and ms_l > 0 and ms_b > 0
 
 
+def test_split_with_the_fiber_ends_recorder():
+    """The recorder's kernel runs on the fiber stream ahead of each fiber kernel, beside
+    the fluid kernel: the same records and state as with whole steps."""
+    w = fiber(1024, 384, "f32", cx=400.0, cy=190.0, theta=0.7)
+    print("[case] split with recorder", flush=True)
+    out = []
+    for flags in (_lib.FPD_FLAG_NO_SPLIT, 0):
+        with _lib.simulation_from_workload(w, storage="f32", flags=flags) as sim:
+            sim.set_launch(dict(graph_chunk=8))
+            sim.record_start(every=3, capacity=64)
+            sim.step(40)
+            sim.sync()
+            out.append((sim.split_active(), sim.record(), sim.populations()))
+    assert not out[0][0] and out[1][0]
+    assert out[0][1].shape[0] >= 13
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 def test_split_not_taken_where_it_cannot_pay():
     """A partition of more than a quarter of the tiles (a small lattice) or a fixed
     profile: whole steps."""
